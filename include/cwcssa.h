@@ -1,0 +1,255 @@
+/*
+ * cwcssa -- bulk stochastic simulation of Calculus of Wrapped Compartments
+ * (CWC) models on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only; no C++ exceptions cross it.  Every
+ * call returns a cwc_status (CWC_OK = 0, errors < 0); the message of the
+ * last error on the calling thread is available from cwc_last_error().
+ *
+ * What the library computes (Aldinucci et al., "On Designing Multicore-aware
+ * Simulators for Biological Systems", PDP 2011):
+ *   - the CWC term/rule model of Sec. 2.1 restricted to a fixed compartment
+ *     tree: every compartment holds a content multiset and, if its label has
+ *     one, a wrap multiset; rules rewrite the content of a compartment, or
+ *     the content of a compartment together with the wrap and content of one
+ *     of its children;
+ *   - the stochastic semantics of Sec. 2.2: a rule's rate in a context is the
+ *     kinetic constant times the number of distinct reactant combinations
+ *     (product of binomial coefficients, the a a b b -> rate 4k example);
+ *   - Gillespie's direct method (Sec. 2.2 two-step procedure; Sec. 2.3
+ *     Match / Resolve / Update loop), run independently for every replica of
+ *     every instance of a parameter sweep (Sec. 3.1.2, Sec. 5.2);
+ *   - trajectories sampled at fixed simulation times and reduced across
+ *     replicas into mean and variance per sample time, on line (Sec. 3,
+ *     Fig. "simout"; Sec. 5.2 schema iii).
+ *
+ * Random stream and arithmetic (fixed so that results are reproducible
+ * bit for bit, independent of batch size, execution form or tuning):
+ *   - draw e of trajectory g: Philox4x32-10, key = (seed lo, seed hi),
+ *     counter = (e lo, e hi, g lo, g hi); g = instance * R + replica;
+ *   - u_tau = (m(x0,x1) + 1) 2^-53, u_sel = m(x2,x3) 2^-53 with
+ *     m(a,b) = (a << 21) | (b >> 11);
+ *   - tau = -ssa_log(u_tau) / a0 (ssa_log: exponent split plus an atanh
+ *     series, correctly rounded + - * / only, no FMA contraction);
+ *   - propensities in a perfect binary tree over the leaf array (slot blocks
+ *     per compartment, each padded to a power of two, compartments padded to
+ *     a power of two); node = left + right in binary64;
+ *   - selection: x = u_sel * a0; at each node go left if x < L or R == 0,
+ *     otherwise x -= L and go right;
+ *   - sample k (time k*dt) holds the state after every event at time
+ *     <= k*dt; the draw that crosses the last sample time is discarded.
+ */
+#ifndef CWCSSA_H
+#define CWCSSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CWC_ABI_VERSION 1u
+
+typedef int32_t cwc_status;
+#define CWC_OK             0
+#define CWC_E_INVALID     -1   /* malformed argument or model            */
+#define CWC_E_UNSUPPORTED -2   /* outside the supported CWC fragment      */
+#define CWC_E_NOMEM       -3   /* arena / device memory / budget too small */
+#define CWC_E_DEVICE      -4   /* HIP runtime error                       */
+#define CWC_E_NOTREADY    -5   /* results requested before completion     */
+#define CWC_E_COMPILE     -6   /* kernel generation / compilation failed  */
+
+/* Per-trajectory terminal status (data, not an error). */
+#define CWC_REPLICA_OK        0   /* reached the last sample time            */
+#define CWC_REPLICA_ABSORBED  1   /* total rate 0: remaining samples filled  */
+#define CWC_REPLICA_OVERFLOW  2   /* an event would push a count above cap;
+                                     the pre-event state is final, samples
+                                     from then on are not contributed        */
+#define CWC_REPLICA_EVENT_CAP 3   /* max_events applied; samples from then on
+                                     are not contributed                     */
+
+/* Pattern regions of a rule (Sec. 2.1: a rule is applied to the content of
+ * a compartment of its label; a pattern may also name one child
+ * compartment's wrap and content). */
+#define CWC_REGION_PARENT 0   /* content of the compartment the rule runs in */
+#define CWC_REGION_WRAP   1   /* wrap of the child compartment               */
+#define CWC_REGION_CHILD  2   /* content of the child compartment            */
+
+/* Execution forms. */
+#define CWC_MODE_PLAIN      0  /* one lane per replica, grid covers all     */
+#define CWC_MODE_PERSISTENT 1  /* resident grid, lanes refill from a queue  */
+
+typedef struct cwc_ctx cwc_ctx;
+typedef struct cwc_model cwc_model;
+typedef struct cwc_run cwc_run;
+typedef struct cwc_server cwc_server;
+
+/* --------------------------------------------------------------- basics */
+
+/* Returns CWC_ABI_VERSION of the loaded library. */
+uint32_t cwc_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until
+ * the next library call on the same thread. */
+const char *cwc_last_error(void);
+
+/* ------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`.
+ *   arena, arena_bytes: optional caller-owned device buffer (e.g. a torch
+ *     tensor's storage) from which all run buffers are sub-allocated; the
+ *     library never frees it.  NULL/0: the library allocates device memory
+ *     itself with hipMalloc.
+ * Errors: CWC_E_INVALID (bad device), CWC_E_DEVICE. */
+cwc_status cwc_ctx_create(int device, void *arena, size_t arena_bytes,
+                          cwc_ctx **out);
+void cwc_ctx_destroy(cwc_ctx *ctx);
+
+/* --------------------------------------------------------------- model */
+
+typedef struct {
+    int32_t region;    /* CWC_REGION_*                         */
+    int32_t species;   /* atom index, 0 <= species < n_species */
+    int32_t mult;      /* multiplicity >= 1                    */
+} cwc_term;
+
+typedef struct {
+    int32_t parent_type;   /* label l of "l: P -> O" (Sec. 2.1)            */
+    int32_t child_type;    /* -1: content-only rule; else the child label  */
+    int32_t n_lhs;         /* terms of the pattern P                       */
+    const cwc_term *lhs;
+    int32_t n_rhs;         /* terms of O                                   */
+    const cwc_term *rhs;
+    double k;              /* kinetic constant (Sec. 2.2), finite, > 0     */
+} cwc_rule;
+
+/* A CWC model with a fixed compartment tree.  Compartments are listed in
+ * preorder; compartment 0 is the top level (parent -1) and every other
+ * compartment's parent has a smaller index.  Count cells are ordered by
+ * compartment; each compartment contributes n_species content cells, then
+ * n_species wrap cells if its label has a wrap.
+ * Supported fragment (else CWC_E_UNSUPPORTED): total reactant order <= 2
+ * per rule (mass action up to bimolecular), no compartment creation or
+ * dissolution, patterns of depth <= 1 (a rule reaches at most one child). */
+typedef struct {
+    int32_t n_species;
+    int32_t n_types;
+    int32_t n_comp;
+    const int32_t *type_has_wrap;  /* [n_types] 0/1                        */
+    const int32_t *comp_type;      /* [n_comp]                             */
+    const int32_t *comp_parent;    /* [n_comp]                             */
+    const int32_t *init_counts;    /* [n_cells] initial multiplicities     */
+    int32_t n_rules;
+    const cwc_rule *rules;         /* [n_rules]                            */
+} cwc_model_desc;
+
+typedef struct {
+    int32_t n_cells;     /* C                                              */
+    int32_t n_slots;     /* (rule, context) pairs                          */
+    int32_t n_leaves;    /* P, power of two                                */
+    int32_t p_local;     /* leaves per compartment block                   */
+    int32_t n_rules;
+    int32_t layout;      /* 0 = lane per replica, 1 = wave per replica     */
+} cwc_model_info;
+
+/* Validates and flattens `d` into rule/context slots, generates the model's
+ * device code and compiles it for the context's device (compiled code is
+ * cached on disk by content hash).  `d` is copied; the caller keeps it.
+ * Errors: CWC_E_INVALID (bad indices, k <= 0 or not finite, negative
+ * counts, non-preorder tree), CWC_E_UNSUPPORTED, CWC_E_COMPILE. */
+cwc_status cwc_model_create(cwc_ctx *ctx, const cwc_model_desc *d,
+                            cwc_model **out);
+cwc_status cwc_model_get_info(const cwc_model *m, cwc_model_info *info);
+/* Copies the generated device source (NUL-terminated) into buf if it fits;
+ * *len receives the required size including the NUL. */
+cwc_status cwc_model_source(const cwc_model *m, char *buf, size_t cap,
+                            size_t *len);
+void cwc_model_destroy(cwc_model *m);
+/* Host-only: flattens and validates `d` and returns the generated device
+ * source (as cwc_model_source) without a device or a compilation. */
+cwc_status cwc_codegen(const cwc_model_desc *d, char *buf, size_t cap,
+                       size_t *len);
+
+/* ----------------------------------------------------------------- run */
+
+typedef struct {
+    int32_t block_size;        /* threads per block, multiple of 64; 0 = auto */
+    int32_t waves_per_simd;    /* persistent grid: resident waves per SIMD    */
+    int32_t refill_chunk;      /* persistent: items taken per queue refill    */
+    int32_t lanes_per_replica; /* 1 (lane layout) or 64 (wave layout); 0 = auto */
+} cwc_tuning;
+
+typedef struct {
+    uint64_t seed;
+    int64_t n_instances;            /* I >= 1                                   */
+    int64_t replicas_per_instance;  /* R >= 1; G = I * R trajectories           */
+    const double *rate_table;       /* host [I][n_rules] or NULL (model k)      */
+    const int32_t *init_table;      /* host [I][n_cells] or NULL (model init)   */
+    double dt;                      /* sample spacing > 0                       */
+    int32_t n_samples;              /* K + 1 >= 1 sample times k*dt             */
+    int32_t mode;                   /* CWC_MODE_*                               */
+    int32_t want_traj;              /* keep samples [G][K+1][C]                 */
+    int32_t want_digest;            /* keep an FNV-1a digest of fired leaves    */
+    int32_t count_cap;              /* > 0; typically INT32_MAX                 */
+    int64_t max_events;             /* per trajectory; 0 = unlimited            */
+    const cwc_tuning *tuning;       /* NULL = library choice                    */
+} cwc_run_desc;
+
+/* Enqueues a run on `hip_stream` (a hipStream_t; NULL = the null stream).
+ * Host tables are copied before return.  Buffers come from the context's
+ * arena (CWC_E_NOMEM if it is too small) or from hipMalloc.
+ * Errors: CWC_E_INVALID, CWC_E_NOMEM, CWC_E_DEVICE. */
+cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m,
+                          const cwc_run_desc *d, void *hip_stream,
+                          cwc_run **out);
+/* Re-enqueues the same run (same inputs, same buffers; results are
+ * overwritten with identical values).  In persistent mode the launch
+ * sequence is replayed from a captured HIP graph. */
+cwc_status cwc_run_relaunch(cwc_run *r, void *hip_stream);
+cwc_status cwc_run_query(cwc_run *r, int *done);
+cwc_status cwc_run_wait(cwc_run *r);
+/* Device time of the last launch of the simulation kernel (HIP events on
+ * the run's stream), and of the whole launch sequence. */
+cwc_status cwc_run_elapsed(cwc_run *r, float *sim_ms, float *total_ms);
+
+/* Statistics per (instance, sample, cell): mean and unbiased variance
+ * (NaN where fewer than 1 / 2 trajectories contributed) and the number of
+ * contributing trajectories per (instance, sample).  Layout [I][K+1][C] and
+ * [I][K+1].  Any pointer may be NULL.  dst_is_device: destinations are
+ * device pointers.  CWC_E_NOTREADY before completion. */
+cwc_status cwc_run_fetch_stats(cwc_run *r, double *mean, double *var,
+                               int64_t *n, int dst_is_device);
+/* Exact integer moments: S1 = sum x, S2 = sum x^2 split as
+ * s2_hi32 * 2^32 + s2_lo32 (each an exact uint64 sum), layout [I][K+1][C]. */
+cwc_status cwc_run_fetch_moments(cwc_run *r, uint64_t *s1, uint64_t *s2_hi32,
+                                 uint64_t *s2_lo32, int64_t *n,
+                                 int dst_is_device);
+/* Samples [G][K+1][C] int32 (requires want_traj); entries at or after a
+ * trajectory's n_recorded are unspecified. */
+cwc_status cwc_run_fetch_trajectories(cwc_run *r, int32_t *dst,
+                                      int dst_is_device);
+/* Per trajectory [G]: applied events, terminal status, digest (0 unless
+ * want_digest), final simulation time, number of recorded samples, final
+ * counts [G][C].  Any pointer may be NULL. */
+cwc_status cwc_run_fetch_counters(cwc_run *r, int64_t *events,
+                                  uint8_t *status, uint64_t *digest,
+                                  double *t_final, int32_t *n_recorded,
+                                  int32_t *final_counts, int dst_is_device);
+void cwc_run_destroy(cwc_run *r);
+
+/* --------------------------------------------------------------- stats */
+
+/* Finalises exact moments into mean/var on the device (the same routine the
+ * runs use).  All pointers are device pointers; rows = I*(K+1).
+ * n[row] trajectories; s1/s2_hi32/s2_lo32 [row][C]. */
+cwc_status cwc_stats_finalize(cwc_ctx *ctx, const int64_t *n,
+                              const uint64_t *s1, const uint64_t *s2_hi32,
+                              const uint64_t *s2_lo32, int64_t rows,
+                              int32_t n_cells, double *mean, double *var,
+                              void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CWCSSA_H */

@@ -1,0 +1,350 @@
+"""ctypes binding of the cwcssa C ABI (include/cwcssa.h).
+
+Argument marshalling only: every step of the simulation runs in the
+library's HIP kernels.  PyTorch supplies device memory (an optional arena
+tensor, device result tensors) and streams; model dictionaries are those of
+the ``workloads`` module.  Loading fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libcwcssa.so")
+
+CWC_OK = 0
+ERRORS = {-1: "CWC_E_INVALID", -2: "CWC_E_UNSUPPORTED", -3: "CWC_E_NOMEM",
+          -4: "CWC_E_DEVICE", -5: "CWC_E_NOTREADY", -6: "CWC_E_COMPILE"}
+MODE_PLAIN, MODE_PERSISTENT = 0, 1
+REGION = {"p": 0, "w": 1, "c": 2}
+
+# exported symbols, in the order include/cwcssa.h declares them
+SYMBOLS = [
+    "cwc_abi_version", "cwc_last_error", "cwc_ctx_create", "cwc_ctx_destroy",
+    "cwc_model_create", "cwc_model_get_info", "cwc_model_source",
+    "cwc_model_destroy", "cwc_codegen", "cwc_run_submit", "cwc_run_relaunch",
+    "cwc_run_query", "cwc_run_wait", "cwc_run_elapsed", "cwc_run_fetch_stats",
+    "cwc_run_fetch_moments", "cwc_run_fetch_trajectories",
+    "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_stats_finalize",
+]
+
+
+class CwcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERRORS.get(code, str(code)), msg))
+        self.code = code
+
+
+class cwc_term(ctypes.Structure):
+    _fields_ = [("region", ctypes.c_int32), ("species", ctypes.c_int32),
+                ("mult", ctypes.c_int32)]
+
+
+class cwc_rule(ctypes.Structure):
+    _fields_ = [("parent_type", ctypes.c_int32), ("child_type", ctypes.c_int32),
+                ("n_lhs", ctypes.c_int32), ("lhs", ctypes.POINTER(cwc_term)),
+                ("n_rhs", ctypes.c_int32), ("rhs", ctypes.POINTER(cwc_term)),
+                ("k", ctypes.c_double)]
+
+
+class cwc_model_desc(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_types", ctypes.c_int32),
+                ("n_comp", ctypes.c_int32),
+                ("type_has_wrap", ctypes.POINTER(ctypes.c_int32)),
+                ("comp_type", ctypes.POINTER(ctypes.c_int32)),
+                ("comp_parent", ctypes.POINTER(ctypes.c_int32)),
+                ("init_counts", ctypes.POINTER(ctypes.c_int32)),
+                ("n_rules", ctypes.c_int32), ("rules", ctypes.POINTER(cwc_rule))]
+
+
+class cwc_model_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("n_cells", "n_slots", "n_leaves", "p_local", "n_rules", "layout")]
+
+
+class cwc_tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("block_size", "waves_per_simd", "refill_chunk", "lanes_per_replica")]
+
+
+class cwc_run_desc(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_instances", ctypes.c_int64),
+                ("replicas_per_instance", ctypes.c_int64),
+                ("rate_table", ctypes.c_void_p), ("init_table", ctypes.c_void_p),
+                ("dt", ctypes.c_double), ("n_samples", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("want_traj", ctypes.c_int32),
+                ("want_digest", ctypes.c_int32), ("count_cap", ctypes.c_int32),
+                ("max_events", ctypes.c_int64),
+                ("tuning", ctypes.POINTER(cwc_tuning))]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libcwcssa.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("cwcssa library not built: %s missing (run "
+                          "__graft_entry__.build() or paper_1010_2438_amd/build.py)" % path)
+    L = ctypes.CDLL(path)
+    P, I32, I64, S = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.cwc_abi_version.restype = ctypes.c_uint32
+    L.cwc_last_error.restype = ctypes.c_char_p
+    sig = {
+        "cwc_ctx_create": [ctypes.c_int, P, S, ctypes.POINTER(P)],
+        "cwc_model_create": [P, ctypes.POINTER(cwc_model_desc), ctypes.POINTER(P)],
+        "cwc_model_get_info": [P, ctypes.POINTER(cwc_model_info)],
+        "cwc_model_source": [P, ctypes.c_char_p, S, ctypes.POINTER(S)],
+        "cwc_codegen": [ctypes.POINTER(cwc_model_desc), ctypes.c_char_p, S, ctypes.POINTER(S)],
+        "cwc_run_submit": [P, P, ctypes.POINTER(cwc_run_desc), P, ctypes.POINTER(P)],
+        "cwc_run_relaunch": [P, P],
+        "cwc_run_query": [P, ctypes.POINTER(ctypes.c_int)],
+        "cwc_run_wait": [P],
+        "cwc_run_elapsed": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+        "cwc_run_fetch_stats": [P, P, P, P, ctypes.c_int],
+        "cwc_run_fetch_moments": [P, P, P, P, P, ctypes.c_int],
+        "cwc_run_fetch_trajectories": [P, P, ctypes.c_int],
+        "cwc_run_fetch_counters": [P, P, P, P, P, P, P, ctypes.c_int],
+        "cwc_stats_finalize": [P, P, P, P, P, I64, I32, P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int32
+    for name in ("cwc_ctx_destroy", "cwc_model_destroy", "cwc_run_destroy"):
+        getattr(L, name).argtypes = [P]
+        getattr(L, name).restype = None
+    _lib = L
+    return L
+
+
+def check(code: int):
+    if code != CWC_OK:
+        raise CwcError(code, load().cwc_last_error().decode())
+
+
+# ------------------------------------------------------------- marshalling
+
+class _ModelDesc:
+    """Keeps the ctypes arrays of a cwc_model_desc alive."""
+
+    def __init__(self, model: Dict):
+        ns = len(model["species"])
+        types, comps = model["types"], model["compartments"]
+        self.has_wrap = (ctypes.c_int32 * len(types))(*[int(bool(t["wrap"])) for t in types])
+        self.comp_type = (ctypes.c_int32 * len(comps))(*[c["type"] for c in comps])
+        self.comp_parent = (ctypes.c_int32 * len(comps))(*[c["parent"] for c in comps])
+        init = []
+        iw = model.get("init_wrap") or [None] * len(comps)
+        for i, c in enumerate(comps):
+            init.extend(int(x) for x in model["init"][i])
+            if types[c["type"]]["wrap"]:
+                init.extend(int(x) for x in (iw[i] if iw[i] is not None else [0] * ns))
+        self.init = (ctypes.c_int32 * max(1, len(init)))(*init)
+        self.terms = []
+        rules = []
+        for r in model["rules"]:
+            sides = []
+            for side in ("lhs", "rhs"):
+                ts = [cwc_term(REGION[reg], int(sp), int(m))
+                      for reg, atoms in r[side].items() for sp, m in atoms.items()
+                      if int(m) > 0]
+                arr = (cwc_term * max(1, len(ts)))(*ts)
+                self.terms.append(arr)
+                sides.append((len(ts), arr))
+            rules.append(cwc_rule(r["parent"], r["child"], sides[0][0], sides[0][1],
+                                  sides[1][0], sides[1][1], float(r["k"])))
+        self.rules = (cwc_rule * max(1, len(rules)))(*rules)
+        self.desc = cwc_model_desc(ns, len(types), len(comps), self.has_wrap,
+                                   self.comp_type, self.comp_parent, self.init,
+                                   len(rules), self.rules)
+
+
+def cwc_codegen(model: Dict) -> str:
+    """Generated device source for a model (host only, no device)."""
+    L = load()
+    md = _ModelDesc(model)
+    n = ctypes.c_size_t()
+    check(L.cwc_codegen(ctypes.byref(md.desc), None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    check(L.cwc_codegen(ctypes.byref(md.desc), buf, n.value, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Context:
+    """cwc_ctx_create / cwc_ctx_destroy.  ``arena_bytes`` > 0 allocates a
+    torch uint8 tensor on the device and hands its storage to the library
+    as the arena."""
+
+    def __init__(self, device: int = 0, arena_bytes: int = 0):
+        L = load()
+        self.arena = None
+        ptr, nbytes = None, 0
+        if arena_bytes:
+            import torch
+            self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda:%d" % device)
+            ptr, nbytes = self.arena.data_ptr(), arena_bytes
+        h = ctypes.c_void_p()
+        check(L.cwc_ctx_create(device, ptr, nbytes, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().cwc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Model:
+    """cwc_model_create from a model dictionary."""
+
+    def __init__(self, ctx: Context, model: Dict):
+        L = load()
+        self.ctx = ctx
+        self.dict = model
+        md = _ModelDesc(model)
+        h = ctypes.c_void_p()
+        check(L.cwc_model_create(ctx.h, ctypes.byref(md.desc), ctypes.byref(h)))
+        self.h = h
+        info = cwc_model_info()
+        check(L.cwc_model_get_info(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in cwc_model_info._fields_}
+
+    def source(self) -> str:
+        L = load()
+        n = ctypes.c_size_t()
+        check(L.cwc_model_source(self.h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        check(L.cwc_model_source(self.h, buf, n.value, ctypes.byref(n)))
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().cwc_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Run:
+    """cwc_run_submit and the fetches.  ``run`` is a workloads.make_run
+    dictionary; ``mode`` 'plain' or 'persistent'."""
+
+    def __init__(self, ctx: Context, model: Model, run: Dict, mode="plain",
+                 want_traj=False, want_digest=False, tuning: Optional[Dict] = None,
+                 stream=None):
+        L = load()
+        self.ctx, self.model = ctx, model
+        self.I, self.R = run["n_instances"], run["replicas"]
+        self.G = self.I * self.R
+        self.K1 = run["n_samples"]
+        self.C = model.info["n_cells"]
+        self._rate = run.get("rate_table")
+        self._init = run.get("init_table")
+        if self._rate is not None:
+            self._rate = np.ascontiguousarray(self._rate, dtype=np.float64)
+            assert self._rate.shape == (self.I, model.info["n_rules"])
+        if self._init is not None:
+            self._init = np.ascontiguousarray(self._init, dtype=np.int32)
+            assert self._init.shape == (self.I, self.C)
+        self._tun = None
+        if tuning:
+            self._tun = cwc_tuning(*[int(tuning.get(f, 0)) for f, _ in cwc_tuning._fields_])
+        d = cwc_run_desc(
+            run["seed"], self.I, self.R,
+            None if self._rate is None else self._rate.ctypes.data,
+            None if self._init is None else self._init.ctypes.data,
+            run["dt"], self.K1, MODE_PERSISTENT if mode == "persistent" else MODE_PLAIN,
+            int(want_traj), int(want_digest), run["count_cap"], run["max_events"],
+            ctypes.pointer(self._tun) if self._tun is not None else None)
+        self.want_traj = want_traj
+        h = ctypes.c_void_p()
+        check(L.cwc_run_submit(ctx.h, model.h, ctypes.byref(d),
+                               _stream_handle(stream), ctypes.byref(h)))
+        self.h = h
+
+    def relaunch(self, stream=None):
+        check(load().cwc_run_relaunch(self.h, _stream_handle(stream)))
+
+    def done(self) -> bool:
+        v = ctypes.c_int()
+        check(load().cwc_run_query(self.h, ctypes.byref(v)))
+        return bool(v.value)
+
+    def wait(self):
+        check(load().cwc_run_wait(self.h))
+        return self
+
+    def elapsed_ms(self):
+        a, b = ctypes.c_float(), ctypes.c_float()
+        check(load().cwc_run_elapsed(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def stats(self):
+        mean = np.empty((self.I, self.K1, self.C), np.float64)
+        var = np.empty_like(mean)
+        n = np.empty((self.I, self.K1), np.int64)
+        check(load().cwc_run_fetch_stats(self.h, mean.ctypes.data, var.ctypes.data,
+                                         n.ctypes.data, 0))
+        return mean, var, n
+
+    def moments(self):
+        s1 = np.empty((self.I, self.K1, self.C), np.uint64)
+        hi, lo = np.empty_like(s1), np.empty_like(s1)
+        n = np.empty((self.I, self.K1), np.int64)
+        check(load().cwc_run_fetch_moments(self.h, s1.ctypes.data, hi.ctypes.data,
+                                           lo.ctypes.data, n.ctypes.data, 0))
+        return s1, hi, lo, n
+
+    def counters(self):
+        G, C = self.G, self.C
+        out = {"events": np.empty(G, np.int64), "status": np.empty(G, np.uint8),
+               "digest": np.empty(G, np.uint64), "t_final": np.empty(G, np.float64),
+               "n_recorded": np.empty(G, np.int32),
+               "final_counts": np.empty((G, C), np.int32)}
+        check(load().cwc_run_fetch_counters(
+            self.h, *[out[k].ctypes.data for k in ("events", "status", "digest", "t_final",
+                                                   "n_recorded", "final_counts")], 0))
+        return out
+
+    def trajectories(self):
+        t = np.empty((self.G, self.K1, self.C), np.int32)
+        check(load().cwc_run_fetch_trajectories(self.h, t.ctypes.data, 0))
+        return t
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().cwc_run_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

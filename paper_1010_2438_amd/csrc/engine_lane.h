@@ -1,0 +1,272 @@
+// Device engine, lane-per-replica layout: every lane of a wavefront runs
+// its own trajectory of Gillespie's direct method over a CWC model whose
+// slot structure has been compiled into the model section that precedes
+// this file.  The model section defines CWC_C (cells), CWC_P (leaves),
+// CWC_NR (rules) and statement macros over named scalar variables, so the
+// whole per-lane state (counts, rates, propensity tree) lives in registers
+// with no indexed arrays:
+//   CWC_DECL_K / CWC_LOAD_K(ptr)       rate variables k<r>
+//   CWC_DECL_STATE                     counts n<c>, tree nodes a<i>
+//   CWC_LOAD_COUNTS(ptr) / CWC_STORE_COUNTS(ptr)
+//   CWC_TREE                           leaves k * prod C(n, m), node sums
+//   CWC_ROOT                           the root value (total propensity a0)
+//   CWC_DESCEND(x, j)                  selection descent -> leaf index j
+//   CWC_APPLY(j, cap, ovf)             net change of leaf j unless overflow
+//   CWC_STAGE(ptr, stride)             counts -> ptr[c * stride]
+//
+// One event (paper Sec. 2.3, Match / Resolve / Update):
+//   Resolve  - one Philox4x32-10 block keyed by the run seed at counter
+//              (event, trajectory) gives u_tau and u_sel; tau = -ln(u_tau)/a0
+//              (Sec. 2.2 step 1); samples whose time precedes the event are
+//              emitted; x = u_sel * a0 selects a leaf of the propensity tree
+//              (Sec. 2.2 step 2: slot i with probability a_i / a0);
+//   Update   - the chosen rule's net change is applied at its context;
+//   Match    - (first, each iteration) every slot's propensity
+//              k * prod C(n, m) and the tree are computed from the counts,
+//              all in registers.
+// Sampled states are reduced on line into exact integer moments per
+// (instance, sample, cell) with 64-bit atomics (Sec. 5.2 schema iii).
+//
+// Compiled with contraction of a*b+c into FMA disabled: every binary64
+// operation rounds once, matching the contract in include/cwcssa.h.
+
+typedef unsigned int u32;
+typedef unsigned long long u64;
+typedef int i32;
+typedef long long i64;
+
+#define CWC_ST_OK 0
+#define CWC_ST_ABSORBED 1
+#define CWC_ST_OVERFLOW 2
+#define CWC_ST_EVENT_CAP 3
+#define CWC_ST_RUNNING (-1)
+
+// ------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// multiplies; the key advances by the Weyl constants between rounds.
+__device__ __forceinline__ void cwc_philox(u32 c0, u32 c1, u32 c2, u32 c3,
+                                           u32 k0, u32 k1, u32 &x0, u32 &x1,
+                                           u32 &x2, u32 &x3)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        u64 p0 = (u64)0xD2511F53u * (u64)c0;
+        u64 p1 = (u64)0xCD9E8D57u * (u64)c2;
+        u32 n0 = (u32)(p1 >> 32) ^ c1 ^ k0;
+        u32 n2 = (u32)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (u32)p1;
+        c3 = (u32)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    x0 = c0; x1 = c1; x2 = c2; x3 = c3;
+}
+
+// 53 random bits -> binary64, exact.
+__device__ __forceinline__ double cwc_u_open0(u32 a, u32 b)   // (0, 1]
+{
+    u64 m = ((u64)a << 21) | (u64)(b >> 11);
+    return (double)(m + 1ull) * 0x1p-53;
+}
+__device__ __forceinline__ double cwc_u_open1(u32 a, u32 b)   // [0, 1)
+{
+    u64 m = ((u64)a << 21) | (u64)(b >> 11);
+    return (double)m * 0x1p-53;
+}
+
+// ------------------------------------------------------------- ssa_log
+// Natural logarithm on [2^-53, 1]: u = 2^E f exactly from the bits, f
+// folded into [sqrt2/2, sqrt2]; ln f = 2 atanh(s), s = (f-1)/(f+1), as
+// 2s + 2 s z p(z), z = s^2, p(z) = sum_{j=0..10} z^j / (2j+3) by Horner;
+// ln u = E*LN2_HI + (E*LN2_LO + ln f) with LN2_HI holding 32 significant
+// bits of ln 2 (E*LN2_HI exact).  Only correctly rounded + - * /.
+__device__ __forceinline__ double cwc_ssa_log(double u)
+{
+    const double SQRT2 = __longlong_as_double(0x3FF6A09E667F3BCDll);
+    const double LN2_HI = __longlong_as_double(0x3FE62E42FF000000ll);
+    const double LN2_LO = __longlong_as_double((long long)0xBDC718432A1B0E26ull);
+    u64 b = (u64)__double_as_longlong(u);
+    int E = (int)((b >> 52) & 0x7FFull) - 1023;
+    double f = __longlong_as_double((long long)((b & 0x000FFFFFFFFFFFFFull) |
+                                                0x3FF0000000000000ull));
+    bool big = f > SQRT2;
+    f = big ? f * 0.5 : f;
+    E = big ? E + 1 : E;
+    double s = (f - 1.0) / (f + 1.0);
+    double z = s * s;
+    double p = 1.0 / 23.0;
+    p = p * z; p = p + 1.0 / 21.0;
+    p = p * z; p = p + 1.0 / 19.0;
+    p = p * z; p = p + 1.0 / 17.0;
+    p = p * z; p = p + 1.0 / 15.0;
+    p = p * z; p = p + 1.0 / 13.0;
+    p = p * z; p = p + 1.0 / 11.0;
+    p = p * z; p = p + 1.0 / 9.0;
+    p = p * z; p = p + 1.0 / 7.0;
+    p = p * z; p = p + 1.0 / 5.0;
+    p = p * z; p = p + 1.0 / 3.0;
+    double t = z * p;
+    t = s * t;
+    double lnf = (2.0 * s) + (2.0 * t);
+    double Ed = (double)E;
+    double lo = Ed * LN2_LO;
+    lo = lo + lnf;
+    double hi = Ed * LN2_HI;
+    return hi + lo;
+}
+
+// On-line reduction of one sampled state (paper Sec. 5.2 schema iii): exact
+// 64-bit sums of x and of x^2 (split in 32-bit halves, so no sum wraps for
+// fewer than 2^32 trajectories) per (instance, sample, cell), plus the
+// sample itself if trajectories are kept.  The counts arrive through this
+// lane's column of the wavefront's LDS staging area ([cell][lane]), so the
+// per-cell loop stays rolled and short-lived in registers.
+__device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const i32 *col,
+                                              i64 row, i32 *tr)
+{
+#pragma unroll 1
+    for (int c = 0; c < CWC_C; ++c) {
+        const i32 v = col[c * 64];
+        const u64 x = (u64)(u32)v;
+        const u64 q = x * x;
+        atomicAdd(p.s1 + row + c, x);
+        atomicAdd(p.s2_lo32 + row + c, q & 0xFFFFFFFFull);
+        if (q >> 32) atomicAdd(p.s2_hi32 + row + c, q >> 32);
+        if (tr) tr[c] = v;
+    }
+}
+
+// ------------------------------------------------------------- main loop
+
+template <bool PERSIST, bool SHARED_K>
+__device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
+{
+    const double INF = __longlong_as_double(0x7FF0000000000000ll);
+    __shared__ i32 stage[4 * CWC_C * 64];          // [wave][cell][lane]
+    i32 *const col = stage + (threadIdx.x >> 6) * (CWC_C * 64) + (threadIdx.x & 63);
+    CWC_DECL_K;
+    CWC_DECL_STATE;
+    if (SHARED_K) { CWC_LOAD_K(p.rates); }
+
+    double t = 0.0, t_next = 0.0;   // current time, time of the next sample
+    u64 e = 0, dig = 0;             // applied events (= next draw), digest
+    i64 g = 0, lg = 0, inst = 0;    // global / local trajectory id, instance
+    i32 kn = 0;                     // next sample index
+
+    // begin trajectory `item` (local id): counts, rates, tree, clocks
+#define CWC_BEGIN(item)                                                       \
+    do {                                                                      \
+        lg = (item);                                                          \
+        g = p.g_base + lg;                                                    \
+        inst = g / p.R;                                                       \
+        { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
+          CWC_LOAD_COUNTS(ini_); }                                            \
+        if (!SHARED_K) {                                                      \
+            const double *kr_ = p.rates + (i64)p.rate_stride * inst;          \
+            CWC_LOAD_K(kr_);                                                  \
+        }                                                                     \
+        t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
+        dig = 0xcbf29ce484222325ull;                                          \
+    } while (0)
+
+    // emit sample kn of the current state and move to the next sample time
+#define CWC_EMIT()                                                            \
+    do {                                                                      \
+        const i64 row_ = (inst * (i64)p.K1 + kn) * (i64)CWC_C;                \
+        i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+        CWC_STAGE(col, 64);                                                   \
+        cwc_emit_moments(p, col, row_, tr_);                                  \
+        kn += 1;                                                              \
+        t_next = (kn < p.K1) ? (double)kn * p.dt : INF;                       \
+    } while (0)
+
+    const i64 tid = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    bool active = tid < p.G;
+    bool live = active;             // persistent form: may still receive work
+    if (active) CWC_BEGIN(tid);
+    for (;;) {
+        if (PERSIST) {
+            // lanes whose trajectory ended claim the next unclaimed items,
+            // one atomic per wavefront per refill
+            const u64 want = __ballot(live && !active);
+            if (want) {
+                const int cnt = __popcll(want);
+                const int lane = __lane_id();
+                const int leader = __ffsll((long long)want) - 1;
+                u64 base = 0;
+                if (lane == leader) base = atomicAdd(p.cursor, (u64)cnt);
+                base = __shfl(base, leader);
+                if (live && !active) {
+                    const u64 below = want & ((1ull << lane) - 1ull);
+                    const i64 item = (i64)(base + (u64)__popcll(below));
+                    if (item < p.G) {
+                        CWC_BEGIN(item);
+                        active = true;
+                    } else {
+                        live = false;
+                    }
+                }
+            }
+            if (!__any(live)) break;
+        } else {
+            if (!__any(active)) break;
+        }
+        if (!active) continue;
+
+        int st = CWC_ST_RUNNING;
+        CWC_TREE;                       // Match: propensities of the state
+        u32 x0, x1, x2, x3;
+        cwc_philox((u32)e, (u32)(e >> 32), (u32)g, (u32)((u64)g >> 32),
+                   (u32)p.seed, (u32)(p.seed >> 32), x0, x1, x2, x3);
+        const double a0 = CWC_ROOT;
+        if (a0 == 0.0) {
+            // absorbing state: the remaining samples hold the current counts
+            while (kn < p.K1) CWC_EMIT();
+            st = CWC_ST_ABSORBED;
+        } else {
+            const double tau = (-cwc_ssa_log(cwc_u_open0(x0, x1))) / a0;
+            const double tn = t + tau;
+            while (t_next < tn) CWC_EMIT();
+            if (kn >= p.K1) {
+                st = CWC_ST_OK;
+            } else {
+                double x = cwc_u_open1(x2, x3) * a0;
+                i32 j;
+                CWC_DESCEND(x, j);
+                bool ovf;
+                CWC_APPLY(j, p.cap, ovf);
+                if (ovf) {
+                    st = CWC_ST_OVERFLOW;
+                } else {
+                    t = tn;
+                    e += 1;
+                    if (p.want_digest) dig = (dig ^ (u64)(u32)j) * 0x100000001b3ull;
+                    if (e == (u64)p.max_events) st = CWC_ST_EVENT_CAP;
+                }
+            }
+        }
+        if (st != CWC_ST_RUNNING) {
+            { i32 *fc_ = p.final_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(fc_); }
+            p.events[lg] = (i64)e;
+            p.t_final[lg] = t;
+            p.digest[lg] = p.want_digest ? dig : 0ull;
+            p.status[lg] = (unsigned char)st;
+            p.n_recorded[lg] = kn;
+            atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);
+            active = false;
+        }
+    }
+#undef CWC_BEGIN
+#undef CWC_EMIT
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+cwc_lane_plain_shared(cwc_kparams p) { cwc_lane_main<false, true>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_lane_plain_table(cwc_kparams p) { cwc_lane_main<false, false>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_lane_persistent_shared(cwc_kparams p) { cwc_lane_main<true, true>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_lane_persistent_table(cwc_kparams p) { cwc_lane_main<true, false>(p); }

@@ -1,0 +1,38 @@
+// Kernel parameter block shared by the host runtime (runtime.cpp) and the
+// device engine (engine_lane.h, compiled per model at run time).  Passed by
+// value as the single kernel argument; plain fields only, fixed layout.
+#ifndef CWC_KPARAMS_H
+#define CWC_KPARAMS_H
+
+struct cwc_kparams {
+    unsigned long long seed;
+    long long G;              // trajectories in this launch
+    long long R;              // replicas per instance
+    long long g_base;         // global id of this launch's first trajectory
+    long long max_events;     // 0 = unlimited
+    double dt;
+    int K1;                   // sample points
+    unsigned int cap;         // count cap (<= INT32_MAX)
+    int rate_stride;          // 0: one shared rate row; else n_rules
+    int init_stride;          // 0: one shared init row; else n_cells
+    int want_traj;
+    int want_digest;
+    const double *rates;      // [I or 1][n_rules]
+    const int *init;          // [I or 1][n_cells]
+    // per-trajectory outputs, indexed by local id g - g_base
+    int *final_counts;        // [G][C]
+    long long *events;        // [G]
+    double *t_final;          // [G]
+    unsigned long long *digest;  // [G]
+    unsigned char *status;    // [G]
+    int *n_recorded;          // [G]
+    int *traj;                // [G][K1][C] or null
+    // on-line moments, indexed by instance (g / R) and sample
+    unsigned long long *s1;       // [I][K1][C]
+    unsigned long long *s2_hi32;  // [I][K1][C]
+    unsigned long long *s2_lo32;  // [I][K1][C]
+    unsigned long long *rec_hist; // [I][K1+1] trajectories by recorded count
+    unsigned long long *cursor;   // persistent form: next unclaimed item
+};
+
+#endif

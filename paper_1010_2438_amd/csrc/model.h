@@ -1,0 +1,46 @@
+// Host-side model compilation: validation of a cwc_model_desc, flattening
+// of the fixed compartment tree into rule/context slots and leaf layout,
+// and generation of the model-specific device code.
+#ifndef CWC_MODEL_H
+#define CWC_MODEL_H
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/cwcssa.h"
+
+namespace cwc {
+
+struct Slot {
+    int rule = -1;        // rule index
+    int ctx = -1;         // context compartment
+    int leaf = -1;        // leaf index = ctx * p_local + position
+    int n_react = 0;      // reactant terms (<= 2)
+    int react_cell[2] = {0, 0};
+    int react_mult[2] = {0, 0};
+    std::vector<std::pair<int, int>> delta;   // (cell, net change), cell-sorted
+};
+
+struct Flat {
+    int n_species = 0, n_types = 0, n_comp = 0, n_rules = 0;
+    int n_cells = 0;
+    std::vector<int> comp_type, comp_parent, has_wrap;
+    std::vector<int> content_base, wrap_base;     // per compartment, -1 = none
+    std::vector<int> init;                        // [n_cells]
+    std::vector<double> k;                        // [n_rules]
+    int p_local = 1, p_comp = 1, n_leaves = 1;
+    std::vector<Slot> slots;                      // context-major order
+    std::vector<int> leaf_slot;                   // [n_leaves] slot or -1
+    int layout = 0;                               // 0 lane, 1 wave
+};
+
+// Returns CWC_OK or an error code with *err set.
+cwc_status flatten(const cwc_model_desc *d, Flat *out, std::string *err);
+
+// Device source of the model section for the given layout (to be followed
+// by the engine source).
+std::string codegen_lane(const Flat &f);
+
+}  // namespace cwc
+#endif

@@ -1,0 +1,404 @@
+// Runs: validation, buffers, launch sequence (zero the accumulators ->
+// simulation kernel -> contributor counts -> mean/variance), HIP-graph
+// capture of the persistent form, completion and result fetches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/cwcssa.h"
+#include "runtime.h"
+#include "stats.h"
+
+using namespace cwc;
+
+#define HIPCHK(call)                                                               \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return set_err(CWC_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+template <class T>
+cwc_status alloc_buf(cwc_run *r, T **p, size_t count)
+{
+    cwc_status st = CWC_OK;
+    void *q = r->ctx->alloc(std::max<size_t>(1, count) * sizeof(T), &st);
+    if (!q) return st;
+    r->bufs.push_back(q);
+    *p = (T *)q;
+    return CWC_OK;
+}
+
+void free_run(cwc_run *r)
+{
+    if (!r) return;
+    (void)hipSetDevice(r->ctx->device);
+    if (r->launched && r->ev_end) (void)hipEventSynchronize(r->ev_end);
+    if (r->graph) (void)hipGraphExecDestroy(r->graph);
+    for (void *p : r->bufs) r->ctx->release(p);
+    if (r->ev_start) (void)hipEventDestroy(r->ev_start);
+    if (r->ev_sim) (void)hipEventDestroy(r->ev_sim);
+    if (r->ev_end) (void)hipEventDestroy(r->ev_end);
+    delete r;
+}
+
+// Zero the accumulators and reset the queue cursor.
+cwc_status enqueue_prologue(cwc_run *r, hipStream_t s)
+{
+    const long long mom = r->I * (long long)r->K1 * r->C;
+    HIPCHK(launch_fill_u64(r->kp.s1, 0, mom, s));
+    HIPCHK(launch_fill_u64(r->kp.s2_hi32, 0, mom, s));
+    HIPCHK(launch_fill_u64(r->kp.s2_lo32, 0, mom, s));
+    HIPCHK(launch_fill_u64(r->kp.rec_hist, 0, r->I * (long long)(r->K1 + 1), s));
+    HIPCHK(launch_fill_u64(r->kp.cursor, r->n_threads, 1, s));
+    return CWC_OK;
+}
+
+cwc_status enqueue_kernel(cwc_run *r, hipStream_t s)
+{
+    void *args[] = {&r->kp};
+    HIPCHK(hipModuleLaunchKernel(r->fn, r->grid, 1, 1, r->block, 1, 1, 0, s, args, nullptr));
+    return CWC_OK;
+}
+
+cwc_status enqueue_epilogue(cwc_run *r, hipStream_t s)
+{
+    HIPCHK(launch_hist_to_n(r->kp.rec_hist, r->nk, r->I, r->K1, s));
+    HIPCHK(launch_finalize(r->nk, r->kp.s1, r->kp.s2_hi32, r->kp.s2_lo32, r->I * (long long)r->K1,
+                           r->C, r->mean, r->var, s));
+    return CWC_OK;
+}
+
+cwc_status capture_graph(cwc_run *r)
+{
+    hipStream_t cs = r->ctx->capture_stream;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    cwc_status st = enqueue_prologue(r, cs);
+    if (st == CWC_OK) st = enqueue_kernel(r, cs);
+    if (st == CWC_OK) st = enqueue_epilogue(r, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st != CWC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return set_err(CWC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&r->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+        return set_err(CWC_E_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    return CWC_OK;
+}
+
+cwc_status launch(cwc_run *r, hipStream_t s)
+{
+    HIPCHK(hipSetDevice(r->ctx->device));
+    if (r->mode == CWC_MODE_PERSISTENT) {
+        HIPCHK(hipEventRecord(r->ev_start, s));
+        HIPCHK(hipGraphLaunch(r->graph, s));
+        HIPCHK(hipEventRecord(r->ev_sim, s));
+        HIPCHK(hipEventRecord(r->ev_end, s));
+    } else {
+        cwc_status st = enqueue_prologue(r, s);
+        if (st != CWC_OK) return st;
+        HIPCHK(hipEventRecord(r->ev_start, s));
+        st = enqueue_kernel(r, s);
+        if (st != CWC_OK) return st;
+        HIPCHK(hipEventRecord(r->ev_sim, s));
+        st = enqueue_epilogue(r, s);
+        if (st != CWC_OK) return st;
+        HIPCHK(hipEventRecord(r->ev_end, s));
+    }
+    r->stream = s;
+    r->launched = true;
+    return CWC_OK;
+}
+
+bool valid_rate(double k) { return std::isfinite(k) && k > 0.0 && k <= 1e250; }
+
+cwc_status ready(cwc_run *r)
+{
+    if (!r) return set_err(CWC_E_INVALID, "null run");
+    if (!r->launched) return set_err(CWC_E_NOTREADY, "run not launched");
+    hipError_t e = hipEventQuery(r->ev_end);
+    if (e == hipErrorNotReady) return set_err(CWC_E_NOTREADY, "run still in flight");
+    if (e != hipSuccess) return set_err(CWC_E_DEVICE, "run failed: %s", hipGetErrorString(e));
+    return CWC_OK;
+}
+
+cwc_status copy_out(void *dst, const void *src, size_t bytes, int dst_is_device)
+{
+    if (!dst || bytes == 0) return CWC_OK;
+    HIPCHK(hipMemcpy(dst, src, bytes, dst_is_device ? hipMemcpyDeviceToDevice
+                                                    : hipMemcpyDeviceToHost));
+    return CWC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d,
+                          void *hip_stream, cwc_run **out)
+{
+    if (!ctx || !m || !d || !out) return set_err(CWC_E_INVALID, "null argument");
+    *out = nullptr;
+    if (m->ctx != ctx) return set_err(CWC_E_INVALID, "model belongs to another context");
+    const Flat &f = m->flat;
+    if (d->n_instances < 1 || d->replicas_per_instance < 1)
+        return set_err(CWC_E_INVALID, "n_instances and replicas_per_instance must be >= 1");
+    if (d->n_instances > (1ll << 31) || d->replicas_per_instance > (1ll << 31) ||
+        d->n_instances * d->replicas_per_instance > (1ll << 31))
+        return set_err(CWC_E_INVALID, "at most 2^31 trajectories per run");
+    if (!(std::isfinite(d->dt) && d->dt > 0.0))
+        return set_err(CWC_E_INVALID, "dt must be finite and > 0");
+    if (d->n_samples < 1 || d->n_samples > (1 << 24))
+        return set_err(CWC_E_INVALID, "n_samples must be in [1, 2^24]");
+    if (!std::isfinite(d->dt * (double)(d->n_samples - 1)))
+        return set_err(CWC_E_INVALID, "last sample time is not finite");
+    if (d->count_cap < 1) return set_err(CWC_E_INVALID, "count_cap must be >= 1");
+    if (d->max_events < 0) return set_err(CWC_E_INVALID, "max_events must be >= 0");
+    if (d->mode != CWC_MODE_PLAIN && d->mode != CWC_MODE_PERSISTENT)
+        return set_err(CWC_E_INVALID, "unknown mode %d", d->mode);
+    const long long I = d->n_instances, R = d->replicas_per_instance, G = I * R;
+    const int C = f.n_cells, NR = std::max(1, f.n_rules), K1 = d->n_samples;
+    // host copies of the tables (validated)
+    std::vector<double> rates;
+    std::vector<int> init;
+    if (d->rate_table) {
+        rates.assign(d->rate_table, d->rate_table + I * f.n_rules);
+        for (double k : rates)
+            if (!valid_rate(k)) return set_err(CWC_E_INVALID, "rate table entry not finite, > 0, <= 1e250");
+        if (f.n_rules == 0) rates.assign(1, 1.0);
+    } else {
+        rates = f.k;
+        if (rates.empty()) rates.assign(1, 1.0);
+    }
+    if (d->init_table) {
+        init.assign(d->init_table, d->init_table + I * C);
+    } else {
+        init = f.init;
+    }
+    for (int v : init)
+        if (v < 0 || v > d->count_cap)
+            return set_err(CWC_E_INVALID, "initial count outside [0, count_cap]");
+
+    // launch shape
+    cwc_tuning tun{};
+    if (d->tuning) tun = *d->tuning;
+    if (tun.block_size <= 0) tun.block_size = 256;
+    if (tun.block_size % 64 || tun.block_size > 256)
+        return set_err(CWC_E_INVALID, "block_size must be a multiple of 64, at most 256");
+    if (tun.waves_per_simd <= 0) tun.waves_per_simd = 2;
+    if (tun.waves_per_simd > 16) return set_err(CWC_E_INVALID, "waves_per_simd must be <= 16");
+    if (tun.refill_chunk <= 0) tun.refill_chunk = 1;
+    if (tun.lanes_per_replica <= 0) tun.lanes_per_replica = 1;
+    if (tun.lanes_per_replica != 1)
+        return set_err(CWC_E_UNSUPPORTED, "lanes_per_replica %d not available for this model",
+                       tun.lanes_per_replica);
+
+    auto r = new cwc_run();
+    r->ctx = ctx;
+    r->m = m;
+    r->I = I;
+    r->R = R;
+    r->G = G;
+    r->K1 = K1;
+    r->C = C;
+    r->mode = d->mode;
+    r->tun = tun;
+    cwc_status st = CWC_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        delete r;
+        return set_err(CWC_E_DEVICE, "hipSetDevice failed");
+    }
+    double *d_rates = nullptr;
+    int *d_init = nullptr;
+    cwc_kparams &kp = r->kp;
+    const long long mom = I * (long long)K1 * C;
+#define ALLOC(ptr, n)                                   \
+    do {                                                \
+        st = alloc_buf(r, &(ptr), (size_t)(n));         \
+        if (st != CWC_OK) {                             \
+            free_run(r);                                \
+            return st;                                  \
+        }                                               \
+    } while (0)
+    ALLOC(d_rates, rates.size());
+    ALLOC(d_init, init.size());
+    ALLOC(kp.final_counts, G * C);
+    ALLOC(kp.events, G);
+    ALLOC(kp.t_final, G);
+    ALLOC(kp.digest, G);
+    ALLOC(kp.status, G);
+    ALLOC(kp.n_recorded, G);
+    if (d->want_traj) ALLOC(kp.traj, G * (long long)K1 * C);
+    ALLOC(kp.s1, mom);
+    ALLOC(kp.s2_hi32, mom);
+    ALLOC(kp.s2_lo32, mom);
+    ALLOC(kp.rec_hist, I * (long long)(K1 + 1));
+    ALLOC(kp.cursor, 1);
+    ALLOC(r->nk, I * (long long)K1);
+    ALLOC(r->mean, mom);
+    ALLOC(r->var, mom);
+#undef ALLOC
+    if (hipMemcpy(d_rates, rates.data(), rates.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(d_init, init.data(), init.size() * sizeof(int), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        free_run(r);
+        return set_err(CWC_E_DEVICE, "table upload failed");
+    }
+    kp.seed = d->seed;
+    kp.G = G;
+    kp.R = R;
+    kp.g_base = 0;
+    kp.max_events = d->max_events;
+    kp.dt = d->dt;
+    kp.K1 = K1;
+    kp.cap = (unsigned)d->count_cap;
+    kp.rate_stride = d->rate_table ? NR : 0;
+    kp.init_stride = d->init_table ? C : 0;
+    kp.want_traj = d->want_traj ? 1 : 0;
+    kp.want_digest = d->want_digest ? 1 : 0;
+    kp.rates = d_rates;
+    kp.init = d_init;
+
+    const bool shared = kp.rate_stride == 0;
+    r->block = (unsigned)tun.block_size;
+    const long long need_blocks = (G + r->block - 1) / r->block;
+    if (d->mode == CWC_MODE_PERSISTENT) {
+        r->fn = m->fn[shared ? 2 : 3];
+        long long resident = (long long)ctx->n_cu * 4 * tun.waves_per_simd * 64 / r->block;
+        r->grid = (unsigned)std::max(1ll, std::min(need_blocks, resident));
+    } else {
+        r->fn = m->fn[shared ? 0 : 1];
+        r->grid = (unsigned)need_blocks;
+    }
+    r->n_threads = (unsigned long long)r->grid * r->block;
+
+    if (hipEventCreate(&r->ev_start) != hipSuccess || hipEventCreate(&r->ev_sim) != hipSuccess ||
+        hipEventCreate(&r->ev_end) != hipSuccess) {
+        free_run(r);
+        return set_err(CWC_E_DEVICE, "hipEventCreate failed");
+    }
+    if (d->mode == CWC_MODE_PERSISTENT) {
+        st = capture_graph(r);
+        if (st != CWC_OK) {
+            free_run(r);
+            return st;
+        }
+    }
+    st = launch(r, (hipStream_t)hip_stream);
+    if (st != CWC_OK) {
+        free_run(r);
+        return st;
+    }
+    *out = r;
+    return CWC_OK;
+}
+
+cwc_status cwc_run_relaunch(cwc_run *r, void *hip_stream)
+{
+    if (!r) return set_err(CWC_E_INVALID, "null run");
+    return launch(r, (hipStream_t)hip_stream);
+}
+
+cwc_status cwc_run_query(cwc_run *r, int *done)
+{
+    if (!r || !done) return set_err(CWC_E_INVALID, "null argument");
+    cwc_status st = ready(r);
+    if (st == CWC_E_NOTREADY) {
+        *done = 0;
+        return CWC_OK;
+    }
+    if (st != CWC_OK) return st;
+    *done = 1;
+    return CWC_OK;
+}
+
+cwc_status cwc_run_wait(cwc_run *r)
+{
+    if (!r) return set_err(CWC_E_INVALID, "null run");
+    if (!r->launched) return set_err(CWC_E_NOTREADY, "run not launched");
+    HIPCHK(hipEventSynchronize(r->ev_end));
+    return ready(r);
+}
+
+cwc_status cwc_run_elapsed(cwc_run *r, float *sim_ms, float *total_ms)
+{
+    cwc_status st = ready(r);
+    if (st != CWC_OK) return st;
+    if (sim_ms) HIPCHK(hipEventElapsedTime(sim_ms, r->ev_start, r->ev_sim));
+    if (total_ms) HIPCHK(hipEventElapsedTime(total_ms, r->ev_start, r->ev_end));
+    return CWC_OK;
+}
+
+cwc_status cwc_run_fetch_stats(cwc_run *r, double *mean, double *var, int64_t *n,
+                               int dst_is_device)
+{
+    cwc_status st = ready(r);
+    if (st != CWC_OK) return st;
+    const size_t mom = (size_t)r->I * r->K1 * r->C;
+    if ((st = copy_out(mean, r->mean, mom * sizeof(double), dst_is_device))) return st;
+    if ((st = copy_out(var, r->var, mom * sizeof(double), dst_is_device))) return st;
+    return copy_out(n, r->nk, (size_t)r->I * r->K1 * sizeof(int64_t), dst_is_device);
+}
+
+cwc_status cwc_run_fetch_moments(cwc_run *r, uint64_t *s1, uint64_t *s2_hi32, uint64_t *s2_lo32,
+                                 int64_t *n, int dst_is_device)
+{
+    cwc_status st = ready(r);
+    if (st != CWC_OK) return st;
+    const size_t mom = (size_t)r->I * r->K1 * r->C * sizeof(uint64_t);
+    if ((st = copy_out(s1, r->kp.s1, mom, dst_is_device))) return st;
+    if ((st = copy_out(s2_hi32, r->kp.s2_hi32, mom, dst_is_device))) return st;
+    if ((st = copy_out(s2_lo32, r->kp.s2_lo32, mom, dst_is_device))) return st;
+    return copy_out(n, r->nk, (size_t)r->I * r->K1 * sizeof(int64_t), dst_is_device);
+}
+
+cwc_status cwc_run_fetch_trajectories(cwc_run *r, int32_t *dst, int dst_is_device)
+{
+    cwc_status st = ready(r);
+    if (st != CWC_OK) return st;
+    if (!r->kp.traj) return set_err(CWC_E_INVALID, "run was submitted without want_traj");
+    return copy_out(dst, r->kp.traj, (size_t)r->G * r->K1 * r->C * sizeof(int32_t), dst_is_device);
+}
+
+cwc_status cwc_run_fetch_counters(cwc_run *r, int64_t *events, uint8_t *status, uint64_t *digest,
+                                  double *t_final, int32_t *n_recorded, int32_t *final_counts,
+                                  int dst_is_device)
+{
+    cwc_status st = ready(r);
+    if (st != CWC_OK) return st;
+    const size_t G = (size_t)r->G;
+    if ((st = copy_out(events, r->kp.events, G * 8, dst_is_device))) return st;
+    if ((st = copy_out(status, r->kp.status, G, dst_is_device))) return st;
+    if ((st = copy_out(digest, r->kp.digest, G * 8, dst_is_device))) return st;
+    if ((st = copy_out(t_final, r->kp.t_final, G * 8, dst_is_device))) return st;
+    if ((st = copy_out(n_recorded, r->kp.n_recorded, G * 4, dst_is_device))) return st;
+    return copy_out(final_counts, r->kp.final_counts, G * r->C * 4, dst_is_device);
+}
+
+void cwc_run_destroy(cwc_run *r) { free_run(r); }
+
+cwc_status cwc_stats_finalize(cwc_ctx *ctx, const int64_t *n, const uint64_t *s1,
+                              const uint64_t *s2_hi32, const uint64_t *s2_lo32, int64_t rows,
+                              int32_t n_cells, double *mean, double *var, void *hip_stream)
+{
+    if (!ctx || !n || !s1 || !s2_hi32 || !s2_lo32 || !mean || !var || rows < 0 || n_cells < 1)
+        return set_err(CWC_E_INVALID, "bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(launch_finalize((const long long *)n, (const unsigned long long *)s1,
+                           (const unsigned long long *)s2_hi32,
+                           (const unsigned long long *)s2_lo32, rows, n_cells, mean, var,
+                           (hipStream_t)hip_stream));
+    return CWC_OK;
+}
+
+}  // extern "C"

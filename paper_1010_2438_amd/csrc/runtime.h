@@ -1,0 +1,65 @@
+// Internal definitions of the opaque C-ABI objects.
+#ifndef CWC_RUNTIME_H
+#define CWC_RUNTIME_H
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cwcssa.h"
+#include "kparams.h"
+#include "model.h"
+
+struct cwc_ctx {
+    int device = 0;
+    int n_cu = 0;
+    std::string arch;
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    size_t used = 0;
+    std::map<size_t, size_t> free_blocks;     // arena offset -> size
+    std::map<void *, size_t> sizes;           // live allocations
+    std::mutex mu;
+    hipStream_t capture_stream = nullptr;
+    void *alloc(size_t bytes, cwc_status *st);
+    void release(void *p);
+};
+
+struct cwc_model {
+    cwc_ctx *ctx = nullptr;
+    cwc::Flat flat;
+    std::string source;
+    hipModule_t module = nullptr;
+    hipFunction_t fn[4] = {nullptr, nullptr, nullptr, nullptr};  // plain/persistent x shared/table
+};
+
+struct cwc_run {
+    cwc_ctx *ctx = nullptr;
+    const cwc_model *m = nullptr;
+    long long I = 0, R = 0, G = 0;
+    int K1 = 0, C = 0, mode = 0;
+    cwc_tuning tun{};
+    cwc_kparams kp{};
+    hipFunction_t fn = nullptr;
+    unsigned grid = 0, block = 0;
+    unsigned long long n_threads = 0;
+    // device buffers
+    std::vector<void *> bufs;
+    long long *nk = nullptr;
+    double *mean = nullptr, *var = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_start = nullptr, ev_sim = nullptr, ev_end = nullptr;
+    hipGraphExec_t graph = nullptr;
+    bool launched = false;
+};
+
+namespace cwc {
+extern thread_local std::string g_err;
+cwc_status set_err(cwc_status code, const char *fmt, ...);
+cwc_status compile_source(const std::string &src, const std::string &arch,
+                          std::vector<char> *code);
+std::string model_source(const Flat &f);
+}  // namespace cwc
+#endif

@@ -1,0 +1,67 @@
+"""Helpers shared by the GPU tests: run a model through the C-ABI library and
+through the oracle on the same seeded inputs, and compare element by element."""
+import math
+
+import numpy as np
+
+import oracle
+
+RESULT_KEYS = ("events", "status", "digest", "n_recorded", "final_counts")
+
+
+def gpu_run(ctx, model_obj, run, mode="plain", want_traj=True, want_digest=True,
+            tuning=None):
+    from paper_1010_2438_amd import Run
+    r = Run(ctx, model_obj, run, mode=mode, want_traj=want_traj,
+            want_digest=want_digest, tuning=tuning)
+    r.wait()
+    out = r.counters()
+    out["mean"], out["var"], out["n"] = r.stats()
+    out["s1"], out["s2_hi32"], out["s2_lo32"], _ = r.moments()
+    if want_traj:
+        out["samples"] = r.trajectories()
+    r.close()
+    return out
+
+
+def same_float(a, b):
+    """Bitwise equality of float arrays, NaN == NaN."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def compare_trajectories(gpu, orc, g_index=None, check_samples=True):
+    """Per-trajectory results equal bit for bit.  g_index: rows of the GPU
+    arrays that correspond to the oracle's rows (default: all)."""
+    sel = slice(None) if g_index is None else g_index
+    for key in RESULT_KEYS:
+        a = np.asarray(gpu[key])[sel]
+        b = np.asarray(orc[key])
+        assert np.array_equal(a, b), "%s differs at %s" % (
+            key, np.argwhere(a != b)[:5].tolist())
+    assert same_float(np.asarray(gpu["t_final"])[sel], orc["t_final"]), "t_final differs"
+    if check_samples and "samples" in orc and "samples" in gpu:
+        gs = np.asarray(gpu["samples"])[sel]
+        for i, nr in enumerate(orc["n_recorded"]):
+            assert np.array_equal(gs[i, :nr], orc["samples"][i, :nr]), "samples differ row %d" % i
+
+
+def compare_stats(gpu, orc):
+    """Exact integer moments equal; mean and variance within 1e-12 relative
+    (both NaN where fewer than 1 / 2 trajectories contributed)."""
+    assert np.array_equal(gpu["n"], orc["n"].astype(np.int64))
+    assert np.array_equal(gpu["s1"], orc["s1"])
+    s2_gpu = [int(h) * 2 ** 32 + int(l) for h, l in
+              zip(gpu["s2_hi32"].ravel(), gpu["s2_lo32"].ravel())]
+    s2_orc = [int(h) * 2 ** 64 + int(l) for h, l in
+              zip(orc["s2_hi"].ravel(), orc["s2_lo"].ravel())]
+    assert s2_gpu == s2_orc
+    for key in ("mean", "var"):
+        a, b = gpu[key], orc[key]
+        both_nan = np.isnan(a) & np.isnan(b)
+        ok = both_nan | (a == b)
+        if not ok.all():
+            rel = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+            rel[both_nan] = 0
+            assert np.nanmax(rel) <= 1e-12, (key, np.nanmax(rel))

@@ -1,0 +1,132 @@
+"""GPU parity: the C-ABI library against the CPU oracle on identical seeded
+inputs.  Integer results (counts, events, statuses, fired-leaf digests,
+samples, moments) must match bit for bit, simulation times bit for bit,
+mean/variance within 1e-12 relative."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_common import compare_stats, compare_trajectories, gpu_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1010_2438_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+_models = {}
+
+
+def model(ctx, m):
+    from paper_1010_2438_amd import Model
+    key = repr(m)
+    if key not in _models:
+        _models[key] = Model(ctx, m)
+    return _models[key]
+
+
+def check(ctx, m, run, modes=("plain", "persistent"), tuning=None, threads=8):
+    orc = oracle.simulate(m, run, want_samples=True, threads=threads)
+    mo = model(ctx, m)
+    for mode in modes:
+        print("case", m["name"], "mode", mode, "G", run["n_instances"] * run["replicas"], flush=True)
+        g = gpu_run(ctx, mo, run, mode=mode, tuning=tuning)
+        compare_trajectories(g, orc)
+        compare_stats(g, orc)
+    return orc
+
+
+def test_config0_lotka_volterra_full(ctx):
+    """Configuration 0 at its full size: 64 LV replicas to t = 5."""
+    m, run = W.config(0)
+    check(ctx, m, run)
+
+
+@pytest.mark.parametrize("name", ["birth_death", "isomerisation", "dimerisation",
+                                  "paper_example", "transport", "receptor_binding"])
+def test_small_models(ctx, name):
+    m = getattr(W, name)()
+    run = W.make_run(seed=3, replicas=300, dt=0.25, n_samples=41)
+    check(ctx, m, run)
+
+
+def test_gene_regulation_ragged(ctx):
+    """Configuration 1's model, 333 replicas (not a multiple of the block)."""
+    m, run = W.config(1, replicas=333)
+    run = dict(run, n_samples=41)          # t_end = 20
+    check(ctx, m, run)
+
+
+def test_sweep_rate_table(ctx):
+    """Configuration 2's sweep: per-instance rate rows (first 24 instances,
+    5 replicas each) in both execution forms."""
+    m, _ = W.config(1)
+    tab, _ = W.sweep_rate_table(m, 4096, 2)
+    run = W.make_run(seed=0, n_instances=24, replicas=5, dt=0.5, n_samples=21,
+                     rate_table=tab[:24])
+    check(ctx, m, run)
+
+
+def test_init_table(ctx):
+    m = W.lotka_volterra(x0=100, y0=100, k=(1.0, 0.01, 1.0))
+    init = np.array([[100, 100], [50, 20], [0, 30], [7, 0]], np.int32)
+    run = W.make_run(seed=11, n_instances=4, replicas=17, dt=0.1, n_samples=31,
+                     init_table=init)
+    check(ctx, m, run)
+
+
+def test_terminal_statuses(ctx):
+    m, run = W.config(0, replicas=70)
+    check(ctx, m, dict(run, max_events=20000))                 # EVENT_CAP
+    check(ctx, m, dict(run, count_cap=1010))                   # OVERFLOW
+    check(ctx, W.pure_decay(2.0, 5), W.make_run(replicas=65, dt=0.5, n_samples=30))  # ABSORBED
+
+
+def test_degenerate_sizes(ctx):
+    m = W.isomerisation()
+    check(ctx, m, W.make_run(seed=1, replicas=1, dt=0.1, n_samples=1))     # one sample, one replica
+    check(ctx, m, W.make_run(seed=2, replicas=64, dt=0.1, n_samples=2))
+    z = W.isomerisation(a0=0, b0=0)                                          # empty: absorbed at t=0
+    check(ctx, z, W.make_run(seed=2, replicas=10, dt=0.1, n_samples=5))
+
+
+@pytest.mark.parametrize("tuning", [{"block_size": 64, "waves_per_simd": 1},
+                                    {"block_size": 128, "waves_per_simd": 4},
+                                    {"block_size": 256, "waves_per_simd": 8}])
+def test_persistent_tuning_invariance(ctx, tuning):
+    """Launch shape changes nothing: bit-identical to the oracle for any
+    block shape and resident-wave count."""
+    m, run = W.config(0, replicas=200)
+    run = dict(run, n_samples=21)
+    check(ctx, m, run, modes=("persistent",), tuning=tuning)
+
+
+def test_config1_full_size_sampled(ctx):
+    """Configuration 1 at full size (16384 replicas, t_end 100) in the
+    launch configuration the benchmark times: 16 trajectories spread over
+    the id range match the oracle one by one; the moments are exactly the
+    integer sums of the fetched samples."""
+    m, run = W.config(1)
+    mo = model(ctx, m)
+    g = gpu_run(ctx, mo, run, mode="persistent", want_traj=True)
+    ids = np.linspace(0, run["replicas"] - 1, 16).astype(int)
+    for i in ids:
+        o = oracle.simulate(m, run, g0=int(i), g1=int(i) + 1, want_samples=True,
+                            want_stats=False)
+        compare_trajectories(g, o, g_index=[int(i)])
+    S = g["samples"].astype(np.int64)
+    assert (g["n_recorded"] == run["n_samples"]).all() and (g["status"] == 0).all()
+    assert np.array_equal(g["s1"][0], S.sum(axis=0).astype(np.uint64))
+    sq = (S * S).sum(axis=0)
+    assert np.array_equal(g["s2_hi32"][0].astype(np.int64) * 2 ** 32 + g["s2_lo32"][0].astype(np.int64), sq)
+    mean = S.mean(axis=0)
+    assert np.allclose(g["mean"][0], mean, rtol=1e-12, atol=0)
