@@ -151,6 +151,13 @@ typedef struct {
     int32_t p_local;     /* leaves per compartment block                   */
     int32_t n_rules;
     int32_t layout;      /* 0 = lane per replica, 1 = wave per replica     */
+    double alg_slots_per_event;  /* algorithmic VALU issue slots of one
+                                    applied event (roofline work unit):
+                                    Philox4x32-10 + uniforms + log + time
+                                    (215), selection (1 + 5 log2 P), update
+                                    (2 per changed cell), re-evaluation of
+                                    the slots whose reactants changed and of
+                                    their tree paths, averaged over slots  */
 } cwc_model_info;
 
 /* Validates and flattens `d` into rule/context slots, generates the model's

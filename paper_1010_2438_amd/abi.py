@@ -63,7 +63,8 @@ class cwc_model_desc(ctypes.Structure):
 
 class cwc_model_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("n_cells", "n_slots", "n_leaves", "p_local", "n_rules", "layout")]
+                ("n_cells", "n_slots", "n_leaves", "p_local", "n_rules", "layout")] + \
+        [("alg_slots_per_event", ctypes.c_double)]
 
 
 class cwc_tuning(ctypes.Structure):

@@ -158,9 +158,16 @@ __device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
     // begin trajectory `item` (local id): counts, rates, tree, clocks
 #define CWC_BEGIN(item)                                                       \
     do {                                                                      \
-        lg = (item);                                                          \
+        if (PERSIST && p.order) {                                             \
+            const u32 grp_ = (u32)(item) / (u32)p.R;                          \
+            const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
+            inst = p.order[grp_];                                             \
+            lg = inst * p.R + rep_;                                           \
+        } else {                                                              \
+            lg = (item);                                                      \
+            inst = (i64)((u32)lg / (u32)p.R);                                 \
+        }                                                                     \
         g = p.g_base + lg;                                                    \
-        inst = g / p.R;                                                       \
         { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
           CWC_LOAD_COUNTS(ini_); }                                            \
         if (!SHARED_K) {                                                      \

@@ -27,12 +27,14 @@ struct cwc_kparams {
     unsigned char *status;    // [G]
     int *n_recorded;          // [G]
     int *traj;                // [G][K1][C] or null
-    // on-line moments, indexed by instance (g / R) and sample
+    // on-line moments, indexed by instance ((g - g_base) / R) and sample
     unsigned long long *s1;       // [I][K1][C]
     unsigned long long *s2_hi32;  // [I][K1][C]
     unsigned long long *s2_lo32;  // [I][K1][C]
     unsigned long long *rec_hist; // [I][K1+1] trajectories by recorded count
     unsigned long long *cursor;   // persistent form: next unclaimed item
+    const int *order;             // persistent form: instance claimed by the
+                                  // i-th group of R items (null = identity)
 };
 
 #endif

@@ -188,6 +188,54 @@ cwc_status flatten(const cwc_model_desc *d, Flat *f, std::string *err)
     return CWC_OK;
 }
 
+// ------------------------------------------------------ algorithmic work
+// VALU issue slots (wave64 instruction = one slot per lane; quarter-rate
+// instructions -- 32x32->64 multiplies, the f64 reciprocal inside a
+// division -- count 4) that one applied event of the direct method needs,
+// independent of how the kernels are organised:
+//   draw:  Philox4x32-10, 10 rounds x (2 wide multiplies [4 each], 4 xor,
+//          2 key adds) = 140; two 53-bit uniforms 14; ssa_log 45 (split,
+//          fold, atanh series of 11 terms, one division); tau = -l/a0 and
+//          t + tau 15; one sample-time compare 1                     = 215
+//   select: x = u*a0, then 5 per tree level (compare, zero test, and,
+//          subtract, select)                                  = 1 + 5 log2 P
+//   update: 2 per changed cell (add, cap compare)
+//   match:  only the slots whose reactants changed are re-evaluated (a
+//          count conversion and a multiply per factor, an extra subtract
+//          and halving for C(n,2)), plus one add per distinct tree node on
+//          their paths to the root.
+// The update/match terms are averaged uniformly over the model's slots.
+double algorithmic_slots_per_event(const Flat &f)
+{
+    const int P = f.n_leaves;
+    int D = 0;
+    while ((1 << D) < P) ++D;
+    double fixed = 215.0 + 1.0 + 5.0 * D;
+    if (f.slots.empty()) return fixed;
+    auto cost = [](const Slot &s) {
+        if (s.n_react == 0) return 0.0;
+        if (s.n_react == 2) return 4.0;
+        return s.react_mult[0] == 2 ? 6.0 : 2.0;
+    };
+    double acc = 0.0;
+    for (const Slot &j : f.slots) {
+        double w = 2.0 * (double)j.delta.size();
+        std::vector<char> changed(f.n_cells, 0);
+        for (auto &dv : j.delta) changed[dv.first] = 1;
+        std::vector<char> node(2 * P, 0);
+        for (const Slot &s : f.slots) {
+            bool dep = false;
+            for (int t = 0; t < s.n_react; ++t) dep |= changed[s.react_cell[t]] != 0;
+            if (!dep) continue;
+            w += cost(s);
+            for (int i = (P + s.leaf) / 2; i >= 1; i /= 2) node[i] = 1;
+        }
+        for (int i = 1; i < P; ++i) w += node[i];
+        acc += w;
+    }
+    return fixed + acc / (double)f.slots.size();
+}
+
 // ------------------------------------------------------------------ codegen
 
 static std::string dlit(double v)
@@ -335,23 +383,44 @@ std::string codegen_lane(const Flat &f)
     w.line("}");
     w.end();
 
-    // --- net change of the chosen slot, selected per cell; nothing is
-    // written if any count would exceed the cap
+    // --- net change of the chosen leaf, branch-free: for every cell and
+    // every binary digit b of the |change| values it receives, a P-bit mask
+    // of the leaves whose change has that digit (one mask for increases,
+    // one for decreases), so d = sum_b ((M+_b >> j) & 1) << b - (...).
+    // Nothing is written if any count would exceed the cap.
     std::vector<std::vector<std::pair<int, int>>> per_cell(C);   // (leaf, delta)
     for (auto &s : f.slots)
         for (auto &dv : s.delta) per_cell[dv.first].push_back({s.leaf, dv.second});
+    const bool wide = P > 32;
+    auto mask_lit = [&](unsigned long long m) {
+        char b[40];
+        std::snprintf(b, sizeof b, wide ? "0x%llxull" : "0x%llxu", m);
+        return std::string(b);
+    };
     w.begin("CWC_APPLY(j, cap, ovf)");
     w.line("{");
     w.line("bool o_ = false;");
+    w.line(wide ? "const unsigned js_ = (unsigned)(j);" : "const unsigned js_ = (unsigned)(j);");
     for (int c = 0; c < C; ++c) {
         if (per_cell[c].empty()) continue;
-        std::string e = "0";
         bool pos = false;
-        for (auto it = per_cell[c].rbegin(); it != per_cell[c].rend(); ++it) {
-            e = "((j) == " + I(it->first) + " ? " + I(it->second) + " : " + e + ")";
-            pos |= it->second > 0;
+        std::string e = "(unsigned)n" + I(c);
+        for (int sign = 1; sign >= -1; sign -= 2) {
+            for (int b = 0; b < 21; ++b) {
+                unsigned long long m = 0;
+                for (auto &ld : per_cell[c]) {
+                    int v = ld.second * sign;
+                    if (v > 0 && ((v >> b) & 1)) m |= 1ull << ld.first;
+                }
+                if (!m) continue;
+                if (sign > 0) pos = true;
+                std::string bit = wide ? "(unsigned)((" + mask_lit(m) + " >> js_) & 1ull)"
+                                       : "((" + mask_lit(m) + " >> js_) & 1u)";
+                if (b) bit = "(" + bit + " << " + I(b) + ")";
+                e += (sign > 0 ? " + " : " - ") + bit;
+            }
         }
-        w.line("const unsigned v" + I(c) + "_ = (unsigned)n" + I(c) + " + (unsigned)" + e + ";");
+        w.line("const unsigned v" + I(c) + "_ = " + e + ";");
         if (pos) w.line("o_ = o_ || (v" + I(c) + "_ > (cap));");
     }
     w.line("if (!o_) {");

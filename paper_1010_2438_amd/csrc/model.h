@@ -38,6 +38,10 @@ struct Flat {
 // Returns CWC_OK or an error code with *err set.
 cwc_status flatten(const cwc_model_desc *d, Flat *out, std::string *err);
 
+// Algorithmic VALU issue slots per applied event of the direct method on
+// this model (see model.cpp); the roofline's work unit.
+double algorithmic_slots_per_event(const Flat &f);
+
 // Device source of the model section for the given layout (to be followed
 // by the engine source).
 std::string codegen_lane(const Flat &f);

@@ -119,6 +119,33 @@ cwc_status launch(cwc_run *r, hipStream_t s)
     return CWC_OK;
 }
 
+// Total propensity of each instance's initial state (host, for scheduling
+// only) and the instance order by decreasing value.
+std::vector<int> instance_order(const Flat &f, const std::vector<double> &rates,
+                                const std::vector<int> &init, int I, bool rate_rows,
+                                bool init_rows)
+{
+    std::vector<double> cost(I, 0.0);
+    for (int i = 0; i < I; ++i) {
+        const double *k = rates.data() + (rate_rows ? (size_t)i * f.n_rules : 0);
+        const int *n = init.data() + (init_rows ? (size_t)i * f.n_cells : 0);
+        double a0 = 0.0;
+        for (const Slot &s : f.slots) {
+            double h = 1.0;
+            for (int t = 0; t < s.n_react; ++t) {
+                const double x = n[s.react_cell[t]];
+                h *= s.react_mult[t] == 2 ? x * std::max(x - 1.0, 0.0) * 0.5 : x;
+            }
+            a0 += k[s.rule] * h;
+        }
+        cost[i] = a0;
+    }
+    std::vector<int> order(I);
+    for (int i = 0; i < I; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    return order;
+}
+
 bool valid_rate(double k) { return std::isfinite(k) && k > 0.0 && k <= 1e250; }
 
 cwc_status ready(cwc_run *r)
@@ -191,7 +218,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     // launch shape
     cwc_tuning tun{};
     if (d->tuning) tun = *d->tuning;
-    if (tun.block_size <= 0) tun.block_size = 256;
+    if (tun.block_size <= 0) tun.block_size = 64;
     if (tun.block_size % 64 || tun.block_size > 256)
         return set_err(CWC_E_INVALID, "block_size must be a multiple of 64, at most 256");
     if (tun.waves_per_simd <= 0) tun.waves_per_simd = 2;
@@ -243,6 +270,8 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     ALLOC(kp.s2_lo32, mom);
     ALLOC(kp.rec_hist, I * (long long)(K1 + 1));
     ALLOC(kp.cursor, 1);
+    int *d_order = nullptr;
+    if (d->mode == CWC_MODE_PERSISTENT && I > 1) ALLOC(d_order, I);
     ALLOC(r->nk, I * (long long)K1);
     ALLOC(r->mean, mom);
     ALLOC(r->var, mom);
@@ -268,6 +297,21 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     kp.want_digest = d->want_digest ? 1 : 0;
     kp.rates = d_rates;
     kp.init = d_init;
+    if (d_order) {
+        // Longest-first claim order (the paper's predictive scheduling of
+        // instances, Sec. 5.2 schema ii): instances are claimed in
+        // decreasing order of their total propensity at t = 0, a proxy for
+        // their event count, so the heaviest start first and the queue's
+        // tail holds the lightest.  Trajectory results do not depend on it.
+        std::vector<int> order = instance_order(f, rates, init, (int)I, d->rate_table != nullptr,
+                                                d->init_table != nullptr);
+        if (hipMemcpy(d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            free_run(r);
+            return set_err(CWC_E_DEVICE, "order upload failed");
+        }
+        kp.order = d_order;
+    }
 
     const bool shared = kp.rate_stride == 0;
     r->block = (unsigned)tun.block_size;
