@@ -1,0 +1,223 @@
+// Device engine, wavefront-per-replica layout, for models whose state does
+// not fit one lane (many compartments: e.g. 32 cells in an outer
+// compartment).  Lane q owns compartment q: its content (nc), wrap (nw), a
+// copy of its parent's content (np) and the P_local leaves of its slot block
+// with their subtree; lanes beyond the model's compartments hold zeros.
+// Requires engine_common.h and the generated model section (CWC_NS,
+// CWC_PL, CWC_PC, CWC_LP, tables cwc_kind / cwc_parent / cwc_cbase /
+// cwc_wbase and the macros CWC_LEAVES, CWC_LOCAL_DESCEND, CWC_APPLY, ...).
+//
+// One event (paper Sec. 2.3 Match / Resolve / Update), all lanes together:
+//   Match    - every lane evaluates its leaves k * prod C(n, m) (Sec. 2.2)
+//              and its subtree; a butterfly over the wavefront adds the
+//              compartment blocks level by level (xor-partner sums are the
+//              canonical tree's node = left + right, by commutativity);
+//   Resolve  - the draws come in batches of 64: lane i holds draw e0 + i
+//              (Philox4x32-10 keyed by seed at counter (e0 + i, g)), with
+//              -ssa_log(u_tau) and u_sel precomputed; tau and the selection
+//              are wavefront-uniform: the descent reads the level sums and
+//              then lane b's subtree with readlane under uniform branches;
+//   Update   - a scalar switch over the chosen (kind, position) applies the
+//              net change in the owner lanes and in the parent copies of
+//              the children, after a wavefront-wide cap check.
+// Samples: every lane reduces its own cells (exact 64-bit moments).
+
+__device__ __forceinline__ double cwc_rl(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double cwc_xor_shfl(double v, int mask)
+{
+    return __shfl_xor(v, mask, 64);
+}
+
+#define CWC_NCELL_LANE (CWC_HAS_WRAP ? 2 * CWC_NS : CWC_NS)
+
+__device__ __forceinline__ void cwc_wave_emit(const cwc_kparams &p, const i32 *col, i64 row,
+                                              i32 *tr, int cb, int wb)
+{
+#pragma unroll 1
+    for (int s = 0; s < CWC_NCELL_LANE; ++s) {
+        const int cell = s < CWC_NS ? cb + s : wb + (s - CWC_NS);
+        if (s >= CWC_NS && wb < 0) break;
+        const i32 v = col[s * 64];
+        const u64 x = (u64)(u32)v;
+        const u64 q = x * x;
+        atomicAdd(p.s1 + row + cell, x);
+        atomicAdd(p.s2_lo32 + row + cell, q & 0xFFFFFFFFull);
+        if (q >> 32) atomicAdd(p.s2_hi32 + row + cell, q >> 32);
+        if (tr) tr[cell] = v;
+    }
+}
+
+template <bool PERSIST, bool SHARED_K>
+__device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p)
+{
+    const double INF = __longlong_as_double(0x7FF0000000000000ll);
+    const int lane = (int)__lane_id();
+    const int wib = (int)(threadIdx.x >> 6);
+    __shared__ i32 stage[4 * CWC_NCELL_LANE * 64];       // [wave][cell][lane]
+    i32 *const col = stage + wib * (CWC_NCELL_LANE * 64) + lane;
+    const int kind = cwc_kind[lane];          // -1: no compartment
+    const int mypar = cwc_parent[lane];
+    const int cb = kind >= 0 ? cwc_cbase[lane] : -1;
+    const int wb = kind >= 0 ? cwc_wbase[lane] : -1;
+    const int pbase = (kind >= 0 && mypar >= 0) ? cwc_cbase[mypar] : -1;
+    CWC_DECL_K;
+    CWC_DECL_STATE;
+    if (SHARED_K) { CWC_LOAD_K(p.rates); }
+
+    const i64 waves_per_block = (i64)(blockDim.x >> 6);
+    i64 item = (i64)blockIdx.x * waves_per_block + wib;
+    for (;;) {
+        if (item >= p.G) break;
+        // ---- begin trajectory
+        i64 lg, inst;
+        if (PERSIST && p.order) {
+            const u32 grp = (u32)item / (u32)p.R;
+            const u32 rep = (u32)item - grp * (u32)p.R;
+            inst = p.order[grp];
+            lg = inst * p.R + rep;
+        } else {
+            lg = item;
+            inst = (i64)((u32)lg / (u32)p.R);
+        }
+        const i64 g = p.g_base + lg;
+        {
+            const i32 *ini = p.init + (i64)p.init_stride * inst;
+            CWC_LOAD_COUNTS(ini, cb, wb, pbase);
+        }
+        if (!SHARED_K) {
+            const double *kr = p.rates + (i64)p.rate_stride * inst;
+            CWC_LOAD_K(kr);
+        }
+        double t = 0.0, t_next = 0.0;
+        u64 e = 0, e0 = 0, dig = 0xcbf29ce484222325ull;
+        i32 kn = 0;
+        bool have_batch = false;
+        double Eb = 0.0, Ub = 0.0;          // this lane's draw of the batch
+        int st = CWC_ST_RUNNING;
+
+#define CWC_WEMIT()                                                           \
+    do {                                                                      \
+        if (kind >= 0) {                                                      \
+            const i64 row_ = (inst * (i64)p.K1 + kn) * (i64)CWC_C;            \
+            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+            CWC_STAGE(col, 64);                                               \
+            cwc_wave_emit(p, col, row_, tr_, cb, wb);                         \
+        }                                                                     \
+        kn += 1;                                                              \
+        t_next = (kn < p.K1) ? (double)kn * p.dt : INF;                       \
+    } while (0)
+
+        while (st == CWC_ST_RUNNING) {
+            // ---- Match: leaves, subtree, butterfly over compartment blocks
+            CWC_LEAVES(kind);
+            const double v0 = a1;
+            const double v1 = CWC_LP >= 1 ? v0 + cwc_xor_shfl(v0, 1) : v0;
+            const double v2 = CWC_LP >= 2 ? v1 + cwc_xor_shfl(v1, 2) : v1;
+            const double v3 = CWC_LP >= 3 ? v2 + cwc_xor_shfl(v2, 4) : v2;
+            const double v4 = CWC_LP >= 4 ? v3 + cwc_xor_shfl(v3, 8) : v3;
+            const double v5 = CWC_LP >= 5 ? v4 + cwc_xor_shfl(v4, 16) : v4;
+            const double v6 = CWC_LP >= 6 ? v5 + cwc_xor_shfl(v5, 32) : v5;
+            const double a0 = cwc_rl(v6, 0);
+            // ---- draws, 64 at a time
+            if (!have_batch || e - e0 >= 64ull) {
+                e0 = e;
+                have_batch = true;
+                const u64 ed = e0 + (u64)lane;
+                u32 x0, x1, x2, x3;
+                cwc_philox((u32)ed, (u32)(ed >> 32), (u32)g, (u32)((u64)g >> 32),
+                           (u32)p.seed, (u32)(p.seed >> 32), x0, x1, x2, x3);
+                Eb = -cwc_ssa_log(cwc_u_open0(x0, x1));
+                Ub = cwc_u_open1(x2, x3);
+            }
+            const int di = (int)(e - e0);
+            if (a0 == 0.0) {
+                while (kn < p.K1) CWC_WEMIT();
+                st = CWC_ST_ABSORBED;
+                break;
+            }
+            const double tau = cwc_rl(Eb, di) / a0;
+            const double tn = t + tau;
+            while (t_next < tn) CWC_WEMIT();
+            if (kn >= p.K1) {
+                st = CWC_ST_OK;
+                break;
+            }
+            // ---- selection: uniform descent over the compartment levels
+            double x = cwc_rl(Ub, di) * a0;
+            int base = 0;
+            // level l splits the current block of 2^l lanes into halves whose
+            // sums sit in the level-(l-1) butterfly values of their first lanes
+#define CWC_XLEVEL(l, v)                                                      \
+            if (CWC_LP >= (l)) {                                              \
+                const int half_ = 1 << ((l) - 1);                             \
+                const double L_ = cwc_rl((v), base);                          \
+                const double R_ = cwc_rl((v), base + half_);                  \
+                if (x >= L_ && R_ != 0.0) {                                   \
+                    x = x - L_;                                               \
+                    base += half_;                                            \
+                }                                                             \
+            }
+            CWC_XLEVEL(6, v5)
+            CWC_XLEVEL(5, v4)
+            CWC_XLEVEL(4, v3)
+            CWC_XLEVEL(3, v2)
+            CWC_XLEVEL(2, v1)
+            CWC_XLEVEL(1, v0)
+#undef CWC_XLEVEL
+            const int b = __builtin_amdgcn_readfirstlane(base);
+            int jl = 0;
+            CWC_LOCAL_DESCEND(x, b, jl);
+            jl = __builtin_amdgcn_readfirstlane(jl);
+            const int kb = cwc_kind[b];
+            const int pb = cwc_parent[b];
+            bool ovf = false;
+            CWC_APPLY(kb, jl, b, pb, lane, mypar, p.cap, ovf);
+            if (ovf) {
+                st = CWC_ST_OVERFLOW;
+                break;
+            }
+            t = tn;
+            e += 1;
+            const u32 j = (u32)(b * CWC_PL + jl);
+            if (p.want_digest) dig = (dig ^ (u64)j) * 0x100000001b3ull;
+            if (e == (u64)p.max_events) {
+                st = CWC_ST_EVENT_CAP;
+                break;
+            }
+        }
+#undef CWC_WEMIT
+        // ---- finish trajectory
+        if (kind >= 0) {
+            i32 *fc = p.final_counts + lg * (i64)CWC_C;
+            CWC_STORE_COUNTS(fc, cb, wb);
+        }
+        if (lane == 0) {
+            p.events[lg] = (i64)e;
+            p.t_final[lg] = t;
+            p.digest[lg] = p.want_digest ? dig : 0ull;
+            p.status[lg] = (unsigned char)st;
+            p.n_recorded[lg] = kn;
+            atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);
+        }
+        if (!PERSIST) break;
+        u64 nxt = 0;
+        if (lane == 0) nxt = atomicAdd(p.cursor, 1ull);
+        item = (i64)__shfl(nxt, 0);
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+cwc_wave_plain_shared(cwc_kparams p) { cwc_wave_main<false, true>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_wave_plain_table(cwc_kparams p) { cwc_wave_main<false, false>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_wave_persistent_shared(cwc_kparams p) { cwc_wave_main<true, true>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_wave_persistent_table(cwc_kparams p) { cwc_wave_main<true, false>(p); }

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <functional>
 #include <sstream>
 
 namespace cwc {
@@ -434,6 +435,285 @@ std::string codegen_lane(const Flat &f)
     // --- stage the counts for the on-line reduction (see CWC_EMIT)
     w.begin("CWC_STAGE(ptr, stride)");
     for (int c = 0; c < C; ++c) w.line("(ptr)[" + I(c) + " * (stride)] = n" + I(c) + ";");
+    w.end();
+    return o.str();
+}
+
+}  // namespace cwc
+
+namespace cwc {
+
+bool fits_lane(const Flat &f) { return f.n_leaves <= 64 && f.n_cells <= 64; }
+
+bool fits_wave(const Flat &f)
+{
+    int ns_w = 0;
+    for (int t = 0; t < f.n_types; ++t) ns_w |= f.has_wrap[t];
+    return f.p_comp <= 64 && f.p_local <= 64 && f.n_species * (2 + ns_w) <= 96;
+}
+
+int choose_layout(const Flat &f)
+{
+    if (fits_lane(f)) return 0;
+    if (fits_wave(f)) return 1;
+    return -1;
+}
+
+// ------------------------------------------------------------ wave layout
+// One wavefront per trajectory; lane q owns compartment q: its content
+// counts nc<s>, its wrap counts nw<s>, a copy np<s> of its parent's
+// content, and the P_local leaves of its slot block (a<P_local + pos>)
+// with their local subtree (a<1..P_local-1>).  Lanes whose compartments
+// run the same slot list share a "kind"; leaf formulas are selected per
+// kind.  The selected slot is uniform across the wavefront, so the update
+// is a scalar switch over (kind, position).
+std::string codegen_wave(const Flat &f)
+{
+    std::ostringstream o;
+    MacroWriter w(o);
+    auto I = [](int v) { return std::to_string(v); };
+    const int NS = f.n_species, PL = f.p_local, PC = f.p_comp;
+    int LP = 0;
+    while ((1 << LP) < PC) ++LP;
+    int DL = 0;
+    while ((1 << DL) < PL) ++DL;
+    bool any_wrap = false;
+    for (int t = 0; t < f.n_types; ++t) any_wrap |= f.has_wrap[t] != 0;
+    const int NR = std::max(1, f.n_rules);
+
+    // kinds: distinct slot lists (sequence of rules) among compartments
+    std::vector<std::vector<int>> kinds;
+    std::vector<int> kind_of(f.n_comp, -1);
+    for (int q = 0; q < f.n_comp; ++q) {
+        std::vector<int> lst;
+        for (int l = 0; l < PL; ++l) {
+            int si = f.leaf_slot[q * PL + l];
+            lst.push_back(si < 0 ? -1 : f.slots[si].rule);
+        }
+        int k = -1;
+        for (size_t i = 0; i < kinds.size(); ++i)
+            if (kinds[i] == lst) k = (int)i;
+        if (k < 0) {
+            k = (int)kinds.size();
+            kinds.push_back(lst);
+        }
+        kind_of[q] = k;
+    }
+    // region of a global cell relative to context q: 0 own content, 1 own
+    // wrap, 2 parent content
+    std::vector<int> cell_comp(f.n_cells), cell_wrap(f.n_cells), cell_sp(f.n_cells);
+    for (int q = 0; q < f.n_comp; ++q)
+        for (int s = 0; s < NS; ++s) {
+            cell_comp[f.content_base[q] + s] = q;
+            cell_wrap[f.content_base[q] + s] = 0;
+            cell_sp[f.content_base[q] + s] = s;
+            if (f.wrap_base[q] >= 0) {
+                cell_comp[f.wrap_base[q] + s] = q;
+                cell_wrap[f.wrap_base[q] + s] = 1;
+                cell_sp[f.wrap_base[q] + s] = s;
+            }
+        }
+    auto var_of = [&](int q, int cell) -> std::string {
+        const int cq = cell_comp[cell], sp = cell_sp[cell];
+        if (cq == q) return (cell_wrap[cell] ? "nw" : "nc") + std::to_string(sp);
+        return "np" + std::to_string(sp);   // parent content
+    };
+
+    o << "// ---- generated model section (wavefront-per-replica layout)\n";
+    o << "#define CWC_C " << f.n_cells << "\n#define CWC_NS " << NS << "\n#define CWC_PL " << PL
+      << "\n#define CWC_PC " << PC << "\n#define CWC_LP " << LP << "\n#define CWC_NR " << NR
+      << "\n#define CWC_HAS_WRAP " << (any_wrap ? 1 : 0) << "\n";
+    auto table = [&](const char *name, std::vector<int> v) {
+        v.resize(64, -1);
+        o << "__constant__ int " << name << "[64] = {";
+        for (int i = 0; i < 64; ++i) o << (i ? "," : "") << v[i];
+        o << "};\n";
+    };
+    std::vector<int> kt(f.n_comp), par(f.comp_parent), cb(f.content_base), wb(f.wrap_base);
+    for (int q = 0; q < f.n_comp; ++q) kt[q] = kind_of[q];
+    table("cwc_kind", kt);
+    table("cwc_parent", par);
+    table("cwc_cbase", cb);
+    table("cwc_wbase", wb);
+
+    w.begin("CWC_DECL_K");
+    for (int r = 0; r < NR; ++r) w.line("double k" + I(r) + " = 0.0;");
+    w.end();
+    w.begin("CWC_LOAD_K(ptr)");
+    for (int r = 0; r < f.n_rules; ++r) w.line("k" + I(r) + " = (ptr)[" + I(r) + "];");
+    w.end();
+    w.begin("CWC_DECL_STATE");
+    for (int s = 0; s < NS; ++s) w.line("int nc" + I(s) + " = 0; int np" + I(s) + " = 0;");
+    if (any_wrap)
+        for (int s = 0; s < NS; ++s) w.line("int nw" + I(s) + " = 0;");
+    for (int i = 1; i < 2 * PL; ++i) w.line("double a" + I(i) + " = 0.0;");
+    w.end();
+    // per-lane loads: own content/wrap and parent content from a cell row
+    w.begin("CWC_LOAD_COUNTS(ptr, cb, wb, pb)");
+    w.line("if ((cb) >= 0) {");
+    for (int s = 0; s < NS; ++s) w.line("    nc" + I(s) + " = (ptr)[(cb) + " + I(s) + "];");
+    w.line("}");
+    if (any_wrap) {
+        w.line("if ((wb) >= 0) {");
+        for (int s = 0; s < NS; ++s) w.line("    nw" + I(s) + " = (ptr)[(wb) + " + I(s) + "];");
+        w.line("}");
+    }
+    w.line("if ((pb) >= 0) {");
+    for (int s = 0; s < NS; ++s) w.line("    np" + I(s) + " = (ptr)[(pb) + " + I(s) + "];");
+    w.line("}");
+    w.end();
+    w.begin("CWC_STORE_COUNTS(ptr, cb, wb)");
+    w.line("if ((cb) >= 0) {");
+    for (int s = 0; s < NS; ++s) w.line("    (ptr)[(cb) + " + I(s) + "] = nc" + I(s) + ";");
+    w.line("}");
+    if (any_wrap) {
+        w.line("if ((wb) >= 0) {");
+        for (int s = 0; s < NS; ++s) w.line("    (ptr)[(wb) + " + I(s) + "] = nw" + I(s) + ";");
+        w.line("}");
+    }
+    w.end();
+    w.begin("CWC_STAGE(ptr, stride)");
+    for (int s = 0; s < NS; ++s) w.line("(ptr)[" + I(s) + " * (stride)] = nc" + I(s) + ";");
+    if (any_wrap)
+        for (int s = 0; s < NS; ++s)
+            w.line("(ptr)[" + I(NS + s) + " * (stride)] = nw" + I(s) + ";");
+    w.end();
+
+    // leaves: per position, the formula of the lane's kind (0 if none)
+    w.begin("CWC_LEAVES(kind)");
+    w.line("{");
+    std::vector<char> used_c(NS, 0), used_d(NS, 0), used_p(NS, 0), used_pd(NS, 0), used_w(NS, 0),
+        used_wd(NS, 0);
+    // representative compartment of each kind, to resolve regions
+    std::vector<int> rep(kinds.size(), -1);
+    for (int q = 0; q < f.n_comp; ++q)
+        if (rep[kind_of[q]] < 0) rep[kind_of[q]] = q;
+    std::vector<std::vector<std::string>> form(PL, std::vector<std::string>(kinds.size(), "0.0"));
+    for (size_t kd = 0; kd < kinds.size(); ++kd) {
+        const int q = rep[kd];
+        for (int l = 0; l < PL; ++l) {
+            int si = f.leaf_slot[q * PL + l];
+            if (si < 0) continue;
+            const Slot &s = f.slots[si];
+            std::string h;
+            auto cv = [&](int cell, bool dec) {
+                std::string v = var_of(q, cell);
+                std::string tag = v.substr(0, 2), sp = v.substr(2);
+                int spi = std::stoi(sp);
+                if (tag == "nc") (dec ? used_d : used_c)[spi] = 1;
+                else if (tag == "np") (dec ? used_pd : used_p)[spi] = 1;
+                else (dec ? used_wd : used_w)[spi] = 1;
+                return (dec ? "m" : "x") + v + "_";
+            };
+            if (s.n_react == 1 && s.react_mult[0] == 1) {
+                h = cv(s.react_cell[0], false);
+            } else if (s.n_react == 1 && s.react_mult[0] == 2) {
+                h = "((" + cv(s.react_cell[0], false) + " * " + cv(s.react_cell[0], true) + ") * 0.5)";
+            } else if (s.n_react == 2) {
+                h = "(" + cv(s.react_cell[0], false) + " * " + cv(s.react_cell[1], false) + ")";
+            }
+            form[l][kd] = "k" + I(s.rule) + (h.empty() ? "" : " * " + h);
+        }
+    }
+    for (int s = 0; s < NS; ++s) {
+        if (used_c[s] || used_d[s]) w.line("const double xnc" + I(s) + "_ = (double)nc" + I(s) + ";");
+        if (used_d[s]) w.line("const double mnc" + I(s) + "_ = (double)(nc" + I(s) + " > 0 ? nc" + I(s) + " - 1 : 0);");
+        if (used_p[s] || used_pd[s]) w.line("const double xnp" + I(s) + "_ = (double)np" + I(s) + ";");
+        if (used_pd[s]) w.line("const double mnp" + I(s) + "_ = (double)(np" + I(s) + " > 0 ? np" + I(s) + " - 1 : 0);");
+        if (used_w[s] || used_wd[s]) w.line("const double xnw" + I(s) + "_ = (double)nw" + I(s) + ";");
+        if (used_wd[s]) w.line("const double mnw" + I(s) + "_ = (double)(nw" + I(s) + " > 0 ? nw" + I(s) + " - 1 : 0);");
+    }
+    std::vector<char> zero(2 * PL, 1);
+    for (int l = 0; l < PL; ++l) {
+        bool any = false;
+        for (size_t kd = 0; kd < kinds.size(); ++kd) any |= form[l][kd] != "0.0";
+        zero[PL + l] = !any;
+        if (!any) continue;
+        std::string e = "0.0";
+        for (size_t kd = kinds.size(); kd-- > 0;)
+            if (form[l][kd] != "0.0") e = "((kind) == " + I((int)kd) + " ? " + form[l][kd] + " : " + e + ")";
+        w.line("a" + I(PL + l) + " = " + e + ";");
+    }
+    for (int i = PL - 1; i >= 1; --i) {
+        zero[i] = zero[2 * i] && zero[2 * i + 1];
+        if (zero[i]) continue;
+        if (!zero[2 * i] && !zero[2 * i + 1]) w.line("a" + I(i) + " = a" + I(2 * i) + " + a" + I(2 * i + 1) + ";");
+        else if (!zero[2 * i]) w.line("a" + I(i) + " = a" + I(2 * i) + ";");
+        else w.line("a" + I(i) + " = a" + I(2 * i + 1) + ";");
+    }
+    if (zero[1]) w.line("a1 = 0.0;");
+    w.line("}");
+    w.end();
+
+    // local descent inside lane b, uniform branches; node values read with
+    // readlane.  The recursion emits one block per internal node.
+    w.begin("CWC_LOCAL_DESCEND(x, b, jl)");
+    w.line("{");
+    std::function<void(int, int)> emit = [&](int i, int depth) {
+        std::string ind(2 * depth + 2, ' ');
+        if (i >= PL) {
+            w.line(ind + "(jl) = " + I(i - PL) + ";");
+            return;
+        }
+        const int L = 2 * i, R = 2 * i + 1;
+        if (zero[R]) {
+            emit(L, depth + 1);
+            return;
+        }
+        const std::string Lv = zero[L] ? "0.0" : "cwc_rl(a" + I(L) + ", (b))";
+        w.line(ind + "{ const double L_ = " + Lv + "; const double R_ = cwc_rl(a" + I(R) + ", (b));");
+        w.line(ind + "if ((x) >= L_ && R_ != 0.0) { (x) = (x) - L_;");
+        emit(R, depth + 1);
+        w.line(ind + "} else {");
+        emit(L, depth + 1);
+        w.line(ind + "} }");
+    };
+    emit(1, 0);
+    w.line("}");
+    w.end();
+
+    // update: uniform switch over (kind, position)
+    w.begin("CWC_APPLY(kind, pos, b, pb, lane, mypar, cap, ovf)");
+    w.line("switch ((kind) * " + I(PL) + " + (pos)) {");
+    for (size_t kd = 0; kd < kinds.size(); ++kd) {
+        const int q = rep[kd];
+        for (int l = 0; l < PL; ++l) {
+            int si = f.leaf_slot[q * PL + l];
+            if (si < 0) continue;
+            const Slot &s = f.slots[si];
+            w.line("case " + I((int)kd * PL + l) + ": {");
+            w.line("  bool o_ = false;");
+            // new values and overflow checks, owner lanes only
+            for (auto &dv : s.delta) {
+                const int cell = dv.first, d = dv.second;
+                std::string v = var_of(q, cell);
+                std::string role = (v[1] == 'p') ? "(pb)" : "(b)";
+                std::string own = (v[1] == 'p') ? "nc" + v.substr(2) : v;
+                if (d > 0)
+                    w.line("  if ((lane) == " + role + ") o_ = o_ || ((unsigned)" + own + " + " +
+                           I(d) + "u > (cap));");
+            }
+            w.line("  (ovf) = __any(o_);");
+            w.line("  if (!(ovf)) {");
+            for (auto &dv : s.delta) {
+                const int cell = dv.first, d = dv.second;
+                std::string v = var_of(q, cell);
+                const bool wrap = v[1] == 'w';
+                const std::string sp = v.substr(2);
+                std::string role = (v[1] == 'p') ? "(pb)" : "(b)";
+                if (wrap) {
+                    w.line("    if ((lane) == " + role + ") nw" + sp + " += " + I(d) + ";");
+                } else {
+                    w.line("    if ((lane) == " + role + ") nc" + sp + " += " + I(d) + ";");
+                    w.line("    if ((mypar) == " + role + ") np" + sp + " += " + I(d) + ";");
+                }
+            }
+            w.line("  }");
+            w.line("  break; }");
+        }
+    }
+    w.line("default: (ovf) = false; break;");
+    w.line("}");
     w.end();
     return o.str();
 }

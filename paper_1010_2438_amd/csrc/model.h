@@ -45,6 +45,14 @@ double algorithmic_slots_per_event(const Flat &f);
 // Device source of the model section for the given layout (to be followed
 // by the engine source).
 std::string codegen_lane(const Flat &f);
+std::string codegen_wave(const Flat &f);
+
+// Layout the library picks for a flattened model: 0 = lane per replica
+// (all state of a trajectory in one lane's registers), 1 = wavefront per
+// replica (lane q owns compartment q), -1 = neither fits.
+int choose_layout(const Flat &f);
+bool fits_lane(const Flat &f);
+bool fits_wave(const Flat &f);
 
 }  // namespace cwc
 #endif

@@ -224,10 +224,16 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     if (tun.waves_per_simd <= 0) tun.waves_per_simd = 2;
     if (tun.waves_per_simd > 16) return set_err(CWC_E_INVALID, "waves_per_simd must be <= 16");
     if (tun.refill_chunk <= 0) tun.refill_chunk = 1;
-    if (tun.lanes_per_replica <= 0) tun.lanes_per_replica = 1;
-    if (tun.lanes_per_replica != 1)
-        return set_err(CWC_E_UNSUPPORTED, "lanes_per_replica %d not available for this model",
-                       tun.lanes_per_replica);
+    int layout = f.layout;
+    if (tun.lanes_per_replica == 1) layout = 0;
+    else if (tun.lanes_per_replica == 64) layout = 1;
+    else if (tun.lanes_per_replica != 0)
+        return set_err(CWC_E_UNSUPPORTED, "lanes_per_replica must be 0 (auto), 1 or 64");
+    {
+        cwc_status lst = ensure_layout(const_cast<cwc_model *>(m), layout);
+        if (lst != CWC_OK) return lst;
+    }
+    tun.lanes_per_replica = layout == 1 ? 64 : 1;
 
     auto r = new cwc_run();
     r->ctx = ctx;
@@ -314,17 +320,21 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     }
 
     const bool shared = kp.rate_stride == 0;
+    const bool wave = layout == 1;
+    if (wave && (!d->tuning || d->tuning->block_size <= 0)) tun.block_size = 256;
     r->block = (unsigned)tun.block_size;
-    const long long need_blocks = (G + r->block - 1) / r->block;
+    // lane layout: one trajectory per lane; wavefront layout: one per wave
+    const long long per_block = wave ? r->block / 64 : r->block;
+    const long long need_blocks = (G + per_block - 1) / per_block;
     if (d->mode == CWC_MODE_PERSISTENT) {
-        r->fn = m->fn[shared ? 2 : 3];
+        r->fn = m->fn[layout][shared ? 2 : 3];
         long long resident = (long long)ctx->n_cu * 4 * tun.waves_per_simd * 64 / r->block;
         r->grid = (unsigned)std::max(1ll, std::min(need_blocks, resident));
     } else {
-        r->fn = m->fn[shared ? 0 : 1];
+        r->fn = m->fn[layout][shared ? 0 : 1];
         r->grid = (unsigned)need_blocks;
     }
-    r->n_threads = (unsigned long long)r->grid * r->block;
+    r->n_threads = (unsigned long long)r->grid * (unsigned long long)per_block;
 
     if (hipEventCreate(&r->ev_start) != hipSuccess || hipEventCreate(&r->ev_sim) != hipSuccess ||
         hipEventCreate(&r->ev_end) != hipSuccess) {

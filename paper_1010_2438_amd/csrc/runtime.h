@@ -29,11 +29,18 @@ struct cwc_ctx {
 
 struct cwc_model {
     cwc_ctx *ctx = nullptr;
-    cwc::Flat flat;
-    std::string source;
-    hipModule_t module = nullptr;
-    hipFunction_t fn[4] = {nullptr, nullptr, nullptr, nullptr};  // plain/persistent x shared/table
+    cwc::Flat flat;                     // flat.layout = the default layout
+    int fits[2] = {0, 0};               // layouts the model fits (lane, wave)
+    std::string source[2];              // per layout, generated on demand
+    hipModule_t module[2] = {nullptr, nullptr};
+    hipFunction_t fn[2][4] = {};        // [layout][plain/persistent x shared/table]
+    std::mutex mu;
 };
+
+namespace cwc {
+// Compiles and loads the model's device code for `layout` if needed.
+cwc_status ensure_layout(cwc_model *m, int layout);
+}
 
 struct cwc_run {
     cwc_ctx *ctx = nullptr;
@@ -60,6 +67,6 @@ extern thread_local std::string g_err;
 cwc_status set_err(cwc_status code, const char *fmt, ...);
 cwc_status compile_source(const std::string &src, const std::string &arch,
                           std::vector<char> *code);
-std::string model_source(const Flat &f);
+std::string model_source(const Flat &f, int layout);
 }  // namespace cwc
 #endif

@@ -130,3 +130,52 @@ def test_config1_full_size_sampled(ctx):
     assert np.array_equal(g["s2_hi32"][0].astype(np.int64) * 2 ** 32 + g["s2_lo32"][0].astype(np.int64), sq)
     mean = S.mean(axis=0)
     assert np.allclose(g["mean"][0], mean, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------- wave layout
+
+def test_config3_multicompartment(ctx):
+    """Configuration 3's model (32 cells in an outer compartment, 396
+    cells, 836 slots): wavefront-per-replica layout, 24 replicas to t = 10."""
+    m, run = W.config(3, replicas=24)
+    run = dict(run, n_samples=21)
+    mo = model(ctx, m)
+    assert mo.info["layout"] == 1
+    check(ctx, m, run)
+
+
+@pytest.mark.parametrize("name", ["birth_death", "lotka_volterra", "paper_example",
+                                  "transport", "receptor_binding", "gene_regulation"])
+def test_small_models_wave_layout(ctx, name):
+    """The same models forced into the wavefront layout match the oracle
+    (and therefore the lane layout) bit for bit."""
+    m = getattr(W, name)()
+    run = W.make_run(seed=5, replicas=40, dt=0.25, n_samples=21)
+    check(ctx, m, run, tuning={"lanes_per_replica": 64})
+
+
+def test_wave_layout_statuses(ctx):
+    m = W.multi_compartment(3, n_cells_=5)
+    run = W.make_run(seed=9, replicas=20, dt=0.5, n_samples=11)
+    check(ctx, m, dict(run, max_events=700), tuning={"lanes_per_replica": 64})
+    cap = max(max(r) for r in m["init"]) + 2          # first overflow comes quickly
+    check(ctx, m, dict(run, count_cap=cap), tuning={"lanes_per_replica": 64})
+    check(ctx, W.pure_decay(3.0, 4), W.make_run(replicas=9, dt=0.5, n_samples=12),
+          tuning={"lanes_per_replica": 64})
+
+
+def test_config3_full_size_sampled(ctx):
+    """Configuration 3 at full size (2048 replicas, t_end 50, persistent):
+    6 trajectories match the oracle one by one; moments equal the integer
+    sums of the fetched samples."""
+    m, run = W.config(3)
+    mo = model(ctx, m)
+    g = gpu_run(ctx, mo, run, mode="persistent", want_traj=True)
+    for i in (0, 409, 1024, 2047):
+        o = oracle.simulate(m, run, g0=i, g1=i + 1, want_samples=True, want_stats=False)
+        compare_trajectories(g, o, g_index=[i])
+    S = g["samples"].astype(np.int64)
+    assert (g["status"] == 0).all()
+    assert np.array_equal(g["s1"][0], S.sum(axis=0).astype(np.uint64))
+    sq = (S * S).sum(axis=0)
+    assert np.array_equal(g["s2_hi32"][0].astype(np.int64) * 2 ** 32 + g["s2_lo32"][0].astype(np.int64), sq)
