@@ -173,6 +173,9 @@ cwc_status cwc_model_get_info(const cwc_model *m, cwc_model_info *info);
 cwc_status cwc_model_source(const cwc_model *m, char *buf, size_t cap,
                             size_t *len);
 void cwc_model_destroy(cwc_model *m);
+/* Host-only: validates and flattens `d` and fills `info` (no device, no
+ * compilation). */
+cwc_status cwc_model_describe(const cwc_model_desc *d, cwc_model_info *info);
 /* Host-only: flattens and validates `d` and returns the generated device
  * source (as cwc_model_source) without a device or a compilation. */
 cwc_status cwc_codegen(const cwc_model_desc *d, char *buf, size_t cap,

@@ -26,7 +26,7 @@ REGION = {"p": 0, "w": 1, "c": 2}
 SYMBOLS = [
     "cwc_abi_version", "cwc_last_error", "cwc_ctx_create", "cwc_ctx_destroy",
     "cwc_model_create", "cwc_model_get_info", "cwc_model_source",
-    "cwc_model_destroy", "cwc_codegen", "cwc_run_submit", "cwc_run_relaunch",
+    "cwc_model_destroy", "cwc_model_describe", "cwc_codegen", "cwc_run_submit", "cwc_run_relaunch",
     "cwc_run_query", "cwc_run_wait", "cwc_run_elapsed", "cwc_run_fetch_stats",
     "cwc_run_fetch_moments", "cwc_run_fetch_trajectories",
     "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_stats_finalize",
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
         "cwc_model_get_info": [P, ctypes.POINTER(cwc_model_info)],
         "cwc_model_source": [P, ctypes.c_char_p, S, ctypes.POINTER(S)],
         "cwc_codegen": [ctypes.POINTER(cwc_model_desc), ctypes.c_char_p, S, ctypes.POINTER(S)],
+        "cwc_model_describe": [ctypes.POINTER(cwc_model_desc), ctypes.POINTER(cwc_model_info)],
         "cwc_run_submit": [P, P, ctypes.POINTER(cwc_run_desc), P, ctypes.POINTER(P)],
         "cwc_run_relaunch": [P, P],
         "cwc_run_query": [P, ctypes.POINTER(ctypes.c_int)],
@@ -177,6 +178,14 @@ def cwc_codegen(model: Dict) -> str:
     buf = ctypes.create_string_buffer(n.value)
     check(L.cwc_codegen(ctypes.byref(md.desc), buf, n.value, ctypes.byref(n)))
     return buf.value.decode()
+
+
+def cwc_model_describe(model: Dict) -> Dict:
+    """Flattened structure of a model (host only, no device)."""
+    md = _ModelDesc(model)
+    info = cwc_model_info()
+    check(load().cwc_model_describe(ctypes.byref(md.desc), ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in cwc_model_info._fields_}
 
 
 def _stream_handle(stream):
