@@ -248,6 +248,70 @@ cwc_status cwc_run_fetch_counters(cwc_run *r, int64_t *events,
                                   int32_t *final_counts, int dst_is_device);
 void cwc_run_destroy(cwc_run *r);
 
+/* ------------------------------------------------------------- serving */
+
+/* Continuous batching (paper Sec. 5.2 schema ii: instances as objects that
+ * can be stopped and restarted, time-sliced, scheduled on line).  A server
+ * owns a device pool of `hbm_budget` bytes and a scheduler thread that runs
+ * ticks: jobs waiting in the queue are admitted (FIFO) when a job slot and
+ * pool memory are free; then, for every model with admitted jobs, one
+ * launch advances every unfinished trajectory of all those jobs by at most
+ * `slice_events` draws, suspending the rest to a device checkpoint.  Jobs
+ * therefore join and leave between ticks while others are on the GPU, and
+ * their work shares each launch.  A job's trajectories and statistics are
+ * bit-identical to the same run submitted alone (counter-based stream).
+ * Job memory stays on the device until cwc_server_release. */
+
+#define CWC_JOB_QUEUED 0
+#define CWC_JOB_ACTIVE 1
+#define CWC_JOB_DONE   2
+
+typedef struct {
+    int32_t state;        /* CWC_JOB_*                                    */
+    int32_t n_ticks;      /* ticks the job took part in                   */
+    double t_submit;      /* seconds since server creation                */
+    double t_admit;
+    double t_done;        /* results ready (statistics finalised)         */
+    int64_t events;       /* applied events (valid once done)             */
+    int64_t bytes;        /* device memory held                           */
+} cwc_job_info;
+
+typedef struct {
+    int64_t jobs_submitted, jobs_done, ticks;
+    int64_t events;              /* applied events of finished jobs       */
+    int64_t pool_bytes, pool_used, pool_peak;
+    double busy_s;               /* wall time spent in ticks              */
+} cwc_server_stats;
+
+/* hbm_budget: device bytes for the pool (from the context's arena or
+ * hipMalloc).  max_active: job slots (1..1024).  slice_events: draws per
+ * trajectory per tick (>= 1).  Errors: CWC_E_INVALID, CWC_E_NOMEM. */
+cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active,
+                             int64_t slice_events, cwc_server **out);
+/* Queues a job (never blocks).  Tables are copied.  mode and tuning of `d`
+ * are ignored (the server's time-sliced form is used).  CWC_E_NOMEM if the
+ * job alone exceeds the pool; CWC_E_INVALID as cwc_run_submit. */
+cwc_status cwc_server_submit(cwc_server *s, const cwc_model *m, const cwc_run_desc *d,
+                             uint64_t *job_id);
+/* Ids of jobs completed since the last poll (each reported once). */
+cwc_status cwc_server_poll(cwc_server *s, uint64_t *done_ids, int32_t max, int32_t *n_done);
+cwc_status cwc_server_job_info(cwc_server *s, uint64_t job, cwc_job_info *info);
+/* As cwc_run_fetch_stats / cwc_run_fetch_counters for a completed job. */
+cwc_status cwc_server_fetch_stats(cwc_server *s, uint64_t job, double *mean, double *var,
+                                  int64_t *n, int dst_is_device);
+cwc_status cwc_server_fetch_counters(cwc_server *s, uint64_t job, int64_t *events,
+                                     uint8_t *status, uint64_t *digest, double *t_final,
+                                     int32_t *n_recorded, int32_t *final_counts,
+                                     int dst_is_device);
+/* Frees a completed job's device memory; its id becomes invalid. */
+cwc_status cwc_server_release(cwc_server *s, uint64_t job);
+/* Blocks until no job is queued or active, or timeout_s elapses
+ * (CWC_E_NOTREADY). */
+cwc_status cwc_server_wait_idle(cwc_server *s, double timeout_s);
+cwc_status cwc_server_get_stats(cwc_server *s, cwc_server_stats *st);
+/* Stops the scheduler after the current tick and frees everything. */
+void cwc_server_destroy(cwc_server *s);
+
 /* --------------------------------------------------------------- stats */
 
 /* Finalises exact moments into mean/var on the device (the same routine the

@@ -29,7 +29,11 @@ SYMBOLS = [
     "cwc_model_destroy", "cwc_model_describe", "cwc_codegen", "cwc_run_submit", "cwc_run_relaunch",
     "cwc_run_query", "cwc_run_wait", "cwc_run_elapsed", "cwc_run_fetch_stats",
     "cwc_run_fetch_moments", "cwc_run_fetch_trajectories",
-    "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_stats_finalize",
+    "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_server_create",
+    "cwc_server_submit", "cwc_server_poll", "cwc_server_job_info",
+    "cwc_server_fetch_stats", "cwc_server_fetch_counters", "cwc_server_release",
+    "cwc_server_wait_idle", "cwc_server_get_stats", "cwc_server_destroy",
+    "cwc_stats_finalize",
 ]
 
 
@@ -83,6 +87,19 @@ class cwc_run_desc(ctypes.Structure):
                 ("tuning", ctypes.POINTER(cwc_tuning))]
 
 
+class cwc_job_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("n_ticks", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("events", ctypes.c_int64),
+                ("bytes", ctypes.c_int64)]
+
+
+class cwc_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("jobs_submitted", "jobs_done", "ticks", "events", "pool_bytes",
+                 "pool_used", "pool_peak")] + [("busy_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -115,12 +132,22 @@ def load(path: str = LIB_PATH):
         "cwc_run_fetch_trajectories": [P, P, ctypes.c_int],
         "cwc_run_fetch_counters": [P, P, P, P, P, P, P, ctypes.c_int],
         "cwc_stats_finalize": [P, P, P, P, P, I64, I32, P, P, P],
+        "cwc_server_create": [P, S, I32, I64, ctypes.POINTER(P)],
+        "cwc_server_submit": [P, P, ctypes.POINTER(cwc_run_desc), ctypes.POINTER(ctypes.c_uint64)],
+        "cwc_server_poll": [P, P, I32, ctypes.POINTER(I32)],
+        "cwc_server_job_info": [P, ctypes.c_uint64, ctypes.POINTER(cwc_job_info)],
+        "cwc_server_fetch_stats": [P, ctypes.c_uint64, P, P, P, ctypes.c_int],
+        "cwc_server_fetch_counters": [P, ctypes.c_uint64, P, P, P, P, P, P, ctypes.c_int],
+        "cwc_server_release": [P, ctypes.c_uint64],
+        "cwc_server_wait_idle": [P, ctypes.c_double],
+        "cwc_server_get_stats": [P, ctypes.POINTER(cwc_server_stats)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int32
-    for name in ("cwc_ctx_destroy", "cwc_model_destroy", "cwc_run_destroy"):
+    for name in ("cwc_ctx_destroy", "cwc_model_destroy", "cwc_run_destroy",
+                 "cwc_server_destroy"):
         getattr(L, name).argtypes = [P]
         getattr(L, name).restype = None
     _lib = L
@@ -351,6 +378,100 @@ class Run:
     def close(self):
         if getattr(self, "h", None):
             load().cwc_run_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _run_desc(run: Dict, want_digest=False):
+    """cwc_run_desc for a workloads.make_run dictionary (tables kept alive by
+    the returned tuple)."""
+    rate = run.get("rate_table")
+    init = run.get("init_table")
+    if rate is not None:
+        rate = np.ascontiguousarray(rate, dtype=np.float64)
+    if init is not None:
+        init = np.ascontiguousarray(init, dtype=np.int32)
+    d = cwc_run_desc(run["seed"], run["n_instances"], run["replicas"],
+                     None if rate is None else rate.ctypes.data,
+                     None if init is None else init.ctypes.data,
+                     run["dt"], run["n_samples"], MODE_PERSISTENT, 0, int(want_digest),
+                     run["count_cap"], run["max_events"], None)
+    return d, rate, init
+
+
+class Server:
+    """cwc_server_*: continuous batching of jobs within an HBM budget."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_active: int = 64,
+                 slice_events: int = 4096):
+        h = ctypes.c_void_p()
+        check(load().cwc_server_create(ctx.h, int(hbm_budget), int(max_active),
+                                       int(slice_events), ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        self.shapes = {}
+
+    def submit(self, model: Model, run: Dict, want_digest=False) -> int:
+        d, _r, _i = _run_desc(run, want_digest)
+        jid = ctypes.c_uint64()
+        check(load().cwc_server_submit(self.h, model.h, ctypes.byref(d), ctypes.byref(jid)))
+        self.shapes[jid.value] = (run["n_instances"], run["replicas"], run["n_samples"],
+                                  model.info["n_cells"])
+        return jid.value
+
+    def poll(self, max_n=4096):
+        ids = (ctypes.c_uint64 * max_n)()
+        n = ctypes.c_int32()
+        check(load().cwc_server_poll(self.h, ids, max_n, ctypes.byref(n)))
+        return list(ids[:n.value])
+
+    def wait_idle(self, timeout_s=600.0):
+        check(load().cwc_server_wait_idle(self.h, float(timeout_s)))
+
+    def info(self, jid):
+        i = cwc_job_info()
+        check(load().cwc_server_job_info(self.h, jid, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in cwc_job_info._fields_}
+
+    def stats(self, jid):
+        I, R, K1, C = self.shapes[jid]
+        mean = np.empty((I, K1, C), np.float64)
+        var = np.empty_like(mean)
+        n = np.empty((I, K1), np.int64)
+        check(load().cwc_server_fetch_stats(self.h, jid, mean.ctypes.data, var.ctypes.data,
+                                            n.ctypes.data, 0))
+        return mean, var, n
+
+    def counters(self, jid):
+        I, R, K1, C = self.shapes[jid]
+        G = I * R
+        out = {"events": np.empty(G, np.int64), "status": np.empty(G, np.uint8),
+               "digest": np.empty(G, np.uint64), "t_final": np.empty(G, np.float64),
+               "n_recorded": np.empty(G, np.int32),
+               "final_counts": np.empty((G, C), np.int32)}
+        check(load().cwc_server_fetch_counters(
+            self.h, jid, *[out[k].ctypes.data for k in ("events", "status", "digest",
+                                                        "t_final", "n_recorded",
+                                                        "final_counts")], 0))
+        return out
+
+    def release(self, jid):
+        check(load().cwc_server_release(self.h, jid))
+        self.shapes.pop(jid, None)
+
+    def server_stats(self):
+        st = cwc_server_stats()
+        check(load().cwc_server_get_stats(self.h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in cwc_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().cwc_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

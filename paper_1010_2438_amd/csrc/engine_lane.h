@@ -52,45 +52,45 @@ __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const i32
 
 // ------------------------------------------------------------- main loop
 
-template <bool PERSIST, bool SHARED_K>
-__device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
-{
-    const double INF = __longlong_as_double(0x7FF0000000000000ll);
-    __shared__ i32 stage[4 * CWC_C * 64];          // [wave][cell][lane]
-    i32 *const col = stage + (threadIdx.x >> 6) * (CWC_C * 64) + (threadIdx.x & 63);
-    CWC_DECL_K;
-    CWC_DECL_STATE;
-    if (SHARED_K) { CWC_LOAD_K(p.rates); }
+// ------------------------------------------------------------- per-lane state
+// The statement macros below operate on the locals declared by
+// CWC_LANE_LOCALS; they are shared by the run-to-completion kernels and the
+// time-sliced kernel of the serving form.
 
-    double t = 0.0, t_next = 0.0;   // current time, time of the next sample
-    u64 e = 0, dig = 0;             // applied events (= next draw), digest
-    i64 g = 0, lg = 0, inst = 0;    // global / local trajectory id, instance
-    i32 kn = 0;                     // next sample index
+#define CWC_LANE_LOCALS                                                       \
+    const double INF = __longlong_as_double(0x7FF0000000000000ll);            \
+    __shared__ i32 stage[4 * CWC_C * 64];          /* [wave][cell][lane] */    \
+    i32 *const col = stage + (threadIdx.x >> 6) * (CWC_C * 64) + (threadIdx.x & 63); \
+    CWC_DECL_K;                                                               \
+    CWC_DECL_STATE;                                                           \
+    double t = 0.0, t_next = 0.0;   /* current time, next sample time */      \
+    u64 e = 0, dig = 0;             /* applied events (= next draw), digest */ \
+    i64 g = 0, lg = 0, inst = 0;    /* global / local id, instance */         \
+    i32 kn = 0;                     /* next sample index */                   \
+    (void)INF;
 
-    // begin trajectory `item` (local id): counts, rates, tree, clocks
-#define CWC_BEGIN(item)                                                       \
+// identify trajectory lg of the run (instance, global id, rates)
+#define CWC_IDENT(LG, SHARED_K)                                               \
     do {                                                                      \
-        if (PERSIST && p.order) {                                             \
-            const u32 grp_ = (u32)(item) / (u32)p.R;                          \
-            const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
-            inst = p.order[grp_];                                             \
-            lg = inst * p.R + rep_;                                           \
-        } else {                                                              \
-            lg = (item);                                                      \
-            inst = (i64)((u32)lg / (u32)p.R);                                 \
-        }                                                                     \
+        lg = (LG);                                                            \
+        inst = (i64)((u32)lg / (u32)p.R);                                     \
         g = p.g_base + lg;                                                    \
-        { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
-          CWC_LOAD_COUNTS(ini_); }                                            \
-        if (!SHARED_K) {                                                      \
+        if (!(SHARED_K)) {                                                    \
             const double *kr_ = p.rates + (i64)p.rate_stride * inst;          \
             CWC_LOAD_K(kr_);                                                  \
         }                                                                     \
+    } while (0)
+
+// start the identified trajectory from the run's initial state
+#define CWC_START()                                                           \
+    do {                                                                      \
+        { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
+          CWC_LOAD_COUNTS(ini_); }                                            \
         t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
         dig = 0xcbf29ce484222325ull;                                          \
     } while (0)
 
-    // emit sample kn of the current state and move to the next sample time
+// emit sample kn of the current state and move to the next sample time
 #define CWC_EMIT()                                                            \
     do {                                                                      \
         const i64 row_ = (inst * (i64)p.K1 + kn) * (i64)CWC_C;                \
@@ -99,6 +99,73 @@ __device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
         cwc_emit_moments(p, col, row_, tr_);                                  \
         kn += 1;                                                              \
         t_next = (kn < p.K1) ? (double)kn * p.dt : INF;                       \
+    } while (0)
+
+// one draw and, unless the trajectory ends, one applied event
+#define CWC_STEP(st)                                                          \
+    do {                                                                      \
+        CWC_TREE;                       /* Match: propensities of the state */ \
+        u32 x0_, x1_, x2_, x3_;                                               \
+        cwc_philox((u32)e, (u32)(e >> 32), (u32)g, (u32)((u64)g >> 32),       \
+                   (u32)p.seed, (u32)(p.seed >> 32), x0_, x1_, x2_, x3_);     \
+        const double a0_ = CWC_ROOT;                                          \
+        if (a0_ == 0.0) {                                                     \
+            /* absorbing state: remaining samples hold the current counts */  \
+            while (kn < p.K1) CWC_EMIT();                                     \
+            (st) = CWC_ST_ABSORBED;                                           \
+        } else {                                                              \
+            const double tau_ = (-cwc_ssa_log(cwc_u_open0(x0_, x1_))) / a0_;   \
+            const double tn_ = t + tau_;                                      \
+            while (t_next < tn_) CWC_EMIT();                                  \
+            if (kn >= p.K1) {                                                 \
+                (st) = CWC_ST_OK;                                             \
+            } else {                                                          \
+                double x_ = cwc_u_open1(x2_, x3_) * a0_;                      \
+                i32 j_;                                                       \
+                CWC_DESCEND(x_, j_);                                          \
+                bool ovf_;                                                    \
+                CWC_APPLY(j_, p.cap, ovf_);                                   \
+                if (ovf_) {                                                   \
+                    (st) = CWC_ST_OVERFLOW;                                   \
+                } else {                                                      \
+                    t = tn_;                                                  \
+                    e += 1;                                                   \
+                    if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
+                    if (e == (u64)p.max_events) (st) = CWC_ST_EVENT_CAP;      \
+                }                                                             \
+            }                                                                 \
+        }                                                                     \
+    } while (0)
+
+// terminal outputs of the trajectory
+#define CWC_FINISH(st)                                                        \
+    do {                                                                      \
+        { i32 *fc_ = p.final_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(fc_); } \
+        p.events[lg] = (i64)e;                                                \
+        p.t_final[lg] = t;                                                    \
+        p.digest[lg] = p.want_digest ? dig : 0ull;                            \
+        p.status[lg] = (unsigned char)(st);                                   \
+        p.n_recorded[lg] = kn;                                                \
+        atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);            \
+    } while (0)
+
+template <bool PERSIST, bool SHARED_K>
+__device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
+{
+    CWC_LANE_LOCALS;
+    if (SHARED_K) { CWC_LOAD_K(p.rates); }
+
+    // begin the trajectory of claimed item `item`
+#define CWC_BEGIN(item)                                                       \
+    do {                                                                      \
+        i64 lg0_ = (item);                                                    \
+        if (PERSIST && p.order) {                                             \
+            const u32 grp_ = (u32)(item) / (u32)p.R;                          \
+            const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
+            lg0_ = (i64)p.order[grp_] * p.R + rep_;                           \
+        }                                                                     \
+        CWC_IDENT(lg0_, SHARED_K);                                            \
+        CWC_START();                                                          \
     } while (0)
 
     const i64 tid = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -133,52 +200,65 @@ __device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
             if (!__any(active)) break;
         }
         if (!active) continue;
-
         int st = CWC_ST_RUNNING;
-        CWC_TREE;                       // Match: propensities of the state
-        u32 x0, x1, x2, x3;
-        cwc_philox((u32)e, (u32)(e >> 32), (u32)g, (u32)((u64)g >> 32),
-                   (u32)p.seed, (u32)(p.seed >> 32), x0, x1, x2, x3);
-        const double a0 = CWC_ROOT;
-        if (a0 == 0.0) {
-            // absorbing state: the remaining samples hold the current counts
-            while (kn < p.K1) CWC_EMIT();
-            st = CWC_ST_ABSORBED;
-        } else {
-            const double tau = (-cwc_ssa_log(cwc_u_open0(x0, x1))) / a0;
-            const double tn = t + tau;
-            while (t_next < tn) CWC_EMIT();
-            if (kn >= p.K1) {
-                st = CWC_ST_OK;
-            } else {
-                double x = cwc_u_open1(x2, x3) * a0;
-                i32 j;
-                CWC_DESCEND(x, j);
-                bool ovf;
-                CWC_APPLY(j, p.cap, ovf);
-                if (ovf) {
-                    st = CWC_ST_OVERFLOW;
-                } else {
-                    t = tn;
-                    e += 1;
-                    if (p.want_digest) dig = (dig ^ (u64)(u32)j) * 0x100000001b3ull;
-                    if (e == (u64)p.max_events) st = CWC_ST_EVENT_CAP;
-                }
-            }
-        }
+        CWC_STEP(st);
         if (st != CWC_ST_RUNNING) {
-            { i32 *fc_ = p.final_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(fc_); }
-            p.events[lg] = (i64)e;
-            p.t_final[lg] = t;
-            p.digest[lg] = p.want_digest ? dig : 0ull;
-            p.status[lg] = (unsigned char)st;
-            p.n_recorded[lg] = kn;
-            atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);
+            CWC_FINISH(st);
             active = false;
         }
     }
 #undef CWC_BEGIN
-#undef CWC_EMIT
+}
+
+// Time-sliced form (serving): the launch covers many jobs of this model;
+// wavefront w works on job wave_job[w], trajectories wave_first[w] + lane.
+// A trajectory resumes from its checkpoint (or starts), runs at most
+// `budget` draws, then either finishes or is suspended back to its
+// checkpoint.  The counter-based random stream makes the split invisible:
+// the trajectory is identical to an uninterrupted run.
+template <bool SHARED_K>
+__device__ __forceinline__ void cwc_lane_slice(const cwc_kparams *jobs, const int *wave_job,
+                                               const long long *wave_first, long long budget)
+{
+    const int w = (int)((blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6);
+    const cwc_kparams &p = jobs[wave_job[w]];
+    CWC_LANE_LOCALS;
+    if (SHARED_K) { CWC_LOAD_K(p.rates); }
+    const i64 my = wave_first[w] + (i64)(threadIdx.x & 63);
+    bool active = my < p.G && p.ck_state[my] != 2;
+    if (active) {
+        CWC_IDENT(my, SHARED_K);
+        if (p.ck_state[my] == 0) {
+            CWC_START();
+        } else {
+            { const i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_LOAD_COUNTS(ck_); }
+            t = p.ck_t[lg];
+            e = p.ck_e[lg];
+            dig = p.ck_dig[lg];
+            kn = p.ck_kn[lg];
+            t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
+        }
+    }
+    long long n = 0;
+    while (__any(active)) {
+        if (!active) continue;
+        int st = CWC_ST_RUNNING;
+        CWC_STEP(st);
+        if (st != CWC_ST_RUNNING) {
+            CWC_FINISH(st);
+            p.ck_state[lg] = 2;
+            atomicAdd(p.done_count, 1ull);
+            active = false;
+        } else if (++n == budget) {
+            { i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(ck_); }
+            p.ck_t[lg] = t;
+            p.ck_e[lg] = e;
+            p.ck_dig[lg] = dig;
+            p.ck_kn[lg] = kn;
+            p.ck_state[lg] = 1;
+            active = false;
+        }
+    }
 }
 
 extern "C" __global__ void __launch_bounds__(256)
@@ -189,3 +269,9 @@ extern "C" __global__ void __launch_bounds__(256)
 cwc_lane_persistent_shared(cwc_kparams p) { cwc_lane_main<true, true>(p); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_lane_persistent_table(cwc_kparams p) { cwc_lane_main<true, false>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_lane_slice_shared(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
+                      long long budget) { cwc_lane_slice<true>(jobs, wave_job, wave_first, budget); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_lane_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
+                     long long budget) { cwc_lane_slice<false>(jobs, wave_job, wave_first, budget); }

@@ -54,12 +54,24 @@ __device__ __forceinline__ void cwc_wave_emit(const cwc_kparams &p, const i32 *c
     }
 }
 
-template <bool PERSIST, bool SHARED_K>
-__device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p)
+#define CWC_FORM_PLAIN 0
+#define CWC_FORM_PERSIST 1
+#define CWC_FORM_SLICE 2
+
+// FORM: run to completion (plain: one trajectory per wavefront of the grid;
+// persistent: wavefronts claim trajectories from the queue) or time-sliced
+// (serving: wavefront w works on job wave_job[w], trajectory wave_first[w],
+// for at most `budget` draws, resuming from and suspending to a checkpoint).
+template <int FORM, bool SHARED_K>
+__device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_kparams *jobs,
+                                              const int *wave_job, const long long *wave_first,
+                                              long long budget)
 {
     const double INF = __longlong_as_double(0x7FF0000000000000ll);
     const int lane = (int)__lane_id();
     const int wib = (int)(threadIdx.x >> 6);
+    const i64 gw = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;   // global wave
+    const cwc_kparams &p = FORM == CWC_FORM_SLICE ? jobs[wave_job[gw]] : p0;
     __shared__ i32 stage[4 * CWC_NCELL_LANE * 64];       // [wave][cell][lane]
     i32 *const col = stage + wib * (CWC_NCELL_LANE * 64) + lane;
     const int kind = cwc_kind[lane];          // -1: no compartment
@@ -71,26 +83,18 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p)
     CWC_DECL_STATE;
     if (SHARED_K) { CWC_LOAD_K(p.rates); }
 
-    const i64 waves_per_block = (i64)(blockDim.x >> 6);
-    i64 item = (i64)blockIdx.x * waves_per_block + wib;
+    i64 item = FORM == CWC_FORM_SLICE ? wave_first[gw] : gw;
     for (;;) {
         if (item >= p.G) break;
-        // ---- begin trajectory
-        i64 lg, inst;
-        if (PERSIST && p.order) {
+        // ---- begin (or resume) trajectory
+        i64 lg = item;
+        if (FORM == CWC_FORM_PERSIST && p.order) {
             const u32 grp = (u32)item / (u32)p.R;
             const u32 rep = (u32)item - grp * (u32)p.R;
-            inst = p.order[grp];
-            lg = inst * p.R + rep;
-        } else {
-            lg = item;
-            inst = (i64)((u32)lg / (u32)p.R);
+            lg = (i64)p.order[grp] * p.R + rep;
         }
+        const i64 inst = (i64)((u32)lg / (u32)p.R);
         const i64 g = p.g_base + lg;
-        {
-            const i32 *ini = p.init + (i64)p.init_stride * inst;
-            CWC_LOAD_COUNTS(ini, cb, wb, pbase);
-        }
         if (!SHARED_K) {
             const double *kr = p.rates + (i64)p.rate_stride * inst;
             CWC_LOAD_K(kr);
@@ -98,9 +102,24 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p)
         double t = 0.0, t_next = 0.0;
         u64 e = 0, e0 = 0, dig = 0xcbf29ce484222325ull;
         i32 kn = 0;
+        const int cks = FORM == CWC_FORM_SLICE ? (int)p.ck_state[lg] : 0;
+        if (cks == 2) break;                          // already finished
+        if (cks == 1) {
+            const i32 *ck = p.ck_counts + lg * (i64)CWC_C;
+            CWC_LOAD_COUNTS(ck, cb, wb, pbase);
+            t = p.ck_t[lg];
+            e = p.ck_e[lg];
+            dig = p.ck_dig[lg];
+            kn = p.ck_kn[lg];
+            t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
+        } else {
+            const i32 *ini = p.init + (i64)p.init_stride * inst;
+            CWC_LOAD_COUNTS(ini, cb, wb, pbase);
+        }
         bool have_batch = false;
         double Eb = 0.0, Ub = 0.0;          // this lane's draw of the batch
         int st = CWC_ST_RUNNING;
+        long long n = 0;                    // draws in this slice
 
 #define CWC_WEMIT()                                                           \
     do {                                                                      \
@@ -115,6 +134,8 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p)
     } while (0)
 
         while (st == CWC_ST_RUNNING) {
+            if (FORM == CWC_FORM_SLICE && n == budget) break;
+            ++n;
             // ---- Match: leaves, subtree, butterfly over compartment blocks
             CWC_LEAVES(kind);
             const double v0 = a1;
@@ -193,6 +214,19 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p)
             }
         }
 #undef CWC_WEMIT
+        if (st == CWC_ST_RUNNING) {
+            // ---- suspend (time-sliced form): back to the checkpoint
+            i32 *ck = p.ck_counts + lg * (i64)CWC_C;
+            if (kind >= 0) { CWC_STORE_COUNTS(ck, cb, wb); }
+            if (lane == 0) {
+                p.ck_t[lg] = t;
+                p.ck_e[lg] = e;
+                p.ck_dig[lg] = dig;
+                p.ck_kn[lg] = kn;
+                p.ck_state[lg] = 1;
+            }
+            break;
+        }
         // ---- finish trajectory
         if (kind >= 0) {
             i32 *fc = p.final_counts + lg * (i64)CWC_C;
@@ -205,8 +239,12 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p)
             p.status[lg] = (unsigned char)st;
             p.n_recorded[lg] = kn;
             atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);
+            if (FORM == CWC_FORM_SLICE) {
+                p.ck_state[lg] = 2;
+                atomicAdd(p.done_count, 1ull);
+            }
         }
-        if (!PERSIST) break;
+        if (FORM != CWC_FORM_PERSIST) break;
         u64 nxt = 0;
         if (lane == 0) nxt = atomicAdd(p.cursor, 1ull);
         item = (i64)__shfl(nxt, 0);
@@ -214,10 +252,22 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p)
 }
 
 extern "C" __global__ void __launch_bounds__(256)
-cwc_wave_plain_shared(cwc_kparams p) { cwc_wave_main<false, true>(p); }
+cwc_wave_plain_shared(cwc_kparams p)
+{ cwc_wave_main<CWC_FORM_PLAIN, true>(p, nullptr, nullptr, nullptr, 0); }
 extern "C" __global__ void __launch_bounds__(256)
-cwc_wave_plain_table(cwc_kparams p) { cwc_wave_main<false, false>(p); }
+cwc_wave_plain_table(cwc_kparams p)
+{ cwc_wave_main<CWC_FORM_PLAIN, false>(p, nullptr, nullptr, nullptr, 0); }
 extern "C" __global__ void __launch_bounds__(256)
-cwc_wave_persistent_shared(cwc_kparams p) { cwc_wave_main<true, true>(p); }
+cwc_wave_persistent_shared(cwc_kparams p)
+{ cwc_wave_main<CWC_FORM_PERSIST, true>(p, nullptr, nullptr, nullptr, 0); }
 extern "C" __global__ void __launch_bounds__(256)
-cwc_wave_persistent_table(cwc_kparams p) { cwc_wave_main<true, false>(p); }
+cwc_wave_persistent_table(cwc_kparams p)
+{ cwc_wave_main<CWC_FORM_PERSIST, false>(p, nullptr, nullptr, nullptr, 0); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_wave_slice_shared(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
+                      long long budget)
+{ cwc_wave_main<CWC_FORM_SLICE, true>(jobs[0], jobs, wave_job, wave_first, budget); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_wave_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
+                     long long budget)
+{ cwc_wave_main<CWC_FORM_SLICE, false>(jobs[0], jobs, wave_job, wave_first, budget); }

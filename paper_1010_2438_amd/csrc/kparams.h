@@ -35,6 +35,14 @@ struct cwc_kparams {
     unsigned long long *cursor;   // persistent form: next unclaimed item
     const int *order;             // persistent form: instance claimed by the
                                   // i-th group of R items (null = identity)
+    // time-sliced (serving) form: per-trajectory checkpoint and progress
+    int *ck_counts;               // [G][C] counts of a suspended trajectory
+    double *ck_t;                 // [G]
+    unsigned long long *ck_e;     // [G] applied events
+    unsigned long long *ck_dig;   // [G]
+    int *ck_kn;                   // [G] next sample index
+    unsigned char *ck_state;      // [G] 0 not started, 1 suspended, 2 finished
+    unsigned long long *done_count;  // trajectories finished so far
 };
 
 #endif

@@ -168,14 +168,13 @@ cwc_status copy_out(void *dst, const void *src, size_t bytes, int dst_is_device)
 
 }  // namespace
 
-extern "C" {
+namespace cwc {
 
-cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d,
-                          void *hip_stream, cwc_run **out)
+// Checks a run descriptor against the model and returns host copies of the
+// rate and initial-state tables (one shared row when not given).
+cwc_status validate_run(const cwc_model *m, const cwc_run_desc *d, std::vector<double> *rates_out,
+                        std::vector<int> *init_out)
 {
-    if (!ctx || !m || !d || !out) return set_err(CWC_E_INVALID, "null argument");
-    *out = nullptr;
-    if (m->ctx != ctx) return set_err(CWC_E_INVALID, "model belongs to another context");
     const Flat &f = m->flat;
     if (d->n_instances < 1 || d->replicas_per_instance < 1)
         return set_err(CWC_E_INVALID, "n_instances and replicas_per_instance must be >= 1");
@@ -190,13 +189,10 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
         return set_err(CWC_E_INVALID, "last sample time is not finite");
     if (d->count_cap < 1) return set_err(CWC_E_INVALID, "count_cap must be >= 1");
     if (d->max_events < 0) return set_err(CWC_E_INVALID, "max_events must be >= 0");
-    if (d->mode != CWC_MODE_PLAIN && d->mode != CWC_MODE_PERSISTENT)
-        return set_err(CWC_E_INVALID, "unknown mode %d", d->mode);
-    const long long I = d->n_instances, R = d->replicas_per_instance, G = I * R;
-    const int C = f.n_cells, NR = std::max(1, f.n_rules), K1 = d->n_samples;
-    // host copies of the tables (validated)
-    std::vector<double> rates;
-    std::vector<int> init;
+    const long long I = d->n_instances;
+    const int C = f.n_cells;
+    std::vector<double> &rates = *rates_out;
+    std::vector<int> &init = *init_out;
     if (d->rate_table) {
         rates.assign(d->rate_table, d->rate_table + I * f.n_rules);
         for (double k : rates)
@@ -214,6 +210,31 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     for (int v : init)
         if (v < 0 || v > d->count_cap)
             return set_err(CWC_E_INVALID, "initial count outside [0, count_cap]");
+
+    return CWC_OK;
+}
+
+}  // namespace cwc
+
+extern "C" {
+
+cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d,
+                          void *hip_stream, cwc_run **out)
+{
+    if (!ctx || !m || !d || !out) return set_err(CWC_E_INVALID, "null argument");
+    *out = nullptr;
+    if (m->ctx != ctx) return set_err(CWC_E_INVALID, "model belongs to another context");
+    if (d->mode != CWC_MODE_PLAIN && d->mode != CWC_MODE_PERSISTENT)
+        return set_err(CWC_E_INVALID, "unknown mode %d", d->mode);
+    const Flat &f = m->flat;
+    std::vector<double> rates;
+    std::vector<int> init;
+    {
+        cwc_status vst = validate_run(m, d, &rates, &init);
+        if (vst != CWC_OK) return vst;
+    }
+    const long long I = d->n_instances, R = d->replicas_per_instance, G = I * R;
+    const int C = f.n_cells, NR = std::max(1, f.n_rules), K1 = d->n_samples;
 
     // launch shape
     cwc_tuning tun{};
@@ -297,7 +318,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     kp.dt = d->dt;
     kp.K1 = K1;
     kp.cap = (unsigned)d->count_cap;
-    kp.rate_stride = d->rate_table ? NR : 0;
+    kp.rate_stride = (d->rate_table && f.n_rules > 0) ? NR : 0;
     kp.init_stride = d->init_table ? C : 0;
     kp.want_traj = d->want_traj ? 1 : 0;
     kp.want_digest = d->want_digest ? 1 : 0;

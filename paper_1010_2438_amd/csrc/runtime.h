@@ -33,13 +33,16 @@ struct cwc_model {
     int fits[2] = {0, 0};               // layouts the model fits (lane, wave)
     std::string source[2];              // per layout, generated on demand
     hipModule_t module[2] = {nullptr, nullptr};
-    hipFunction_t fn[2][4] = {};        // [layout][plain/persistent x shared/table]
+    hipFunction_t fn[2][6] = {};        // [layout][plain/persistent/slice x shared/table]
     std::mutex mu;
 };
 
 namespace cwc {
 // Compiles and loads the model's device code for `layout` if needed.
 cwc_status ensure_layout(cwc_model *m, int layout);
+// Checks a run descriptor; host copies of the rate / initial-state tables.
+cwc_status validate_run(const cwc_model *m, const cwc_run_desc *d, std::vector<double> *rates,
+                        std::vector<int> *init);
 }
 
 struct cwc_run {

@@ -1,0 +1,678 @@
+// Serving: continuous batching of simulation jobs on one device.
+//
+// The paper's schema ii (Sec. 5.2) makes each simulation instance an object
+// that can be stopped and restarted so that an on-line scheduler can
+// time-slice instances across workers.  Here the scheduler is a host thread
+// and the "workers" are one kernel launch per model per tick:
+//   tick:  admit queued jobs (FIFO) while a job slot and pool memory are
+//          free -> for every (model, layout, rate-table) group of admitted
+//          jobs, one launch advances every unfinished trajectory of those
+//          jobs by at most slice_events draws, suspending the rest to a
+//          device checkpoint -> read the per-job finished counters -> jobs
+//          whose trajectories all finished get their statistics finalised
+//          and leave their slot.
+// Groups are launched on separate streams so different models' slices run
+// concurrently.  A trajectory's events do not depend on how it was sliced
+// or which jobs shared a launch (counter-based random stream), so every job
+// is bit-identical to the same run submitted alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/cwcssa.h"
+#include "runtime.h"
+#include "stats.h"
+
+using namespace cwc;
+
+namespace {
+
+constexpr int kStreams = 4;
+
+// First-fit sub-allocator over the server's device pool.
+struct Pool {
+    char *base = nullptr;
+    size_t bytes = 0, used = 0, peak = 0;
+    std::map<size_t, size_t> free_blocks;   // offset -> size
+    std::map<size_t, size_t> live;          // offset -> size
+
+    void init(void *p, size_t n)
+    {
+        base = (char *)p;
+        bytes = n & ~size_t(255);
+        free_blocks.clear();
+        free_blocks[0] = bytes;
+    }
+    void *alloc(size_t n)
+    {
+        n = std::max<size_t>(256, (n + 255) & ~size_t(255));
+        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+            if (it->second < n) continue;
+            size_t off = it->first, sz = it->second;
+            free_blocks.erase(it);
+            if (sz > n) free_blocks[off + n] = sz - n;
+            live[off] = n;
+            used += n;
+            return base + off;
+        }
+        return nullptr;
+    }
+    void release(void *p)
+    {
+        size_t off = (char *)p - base;
+        auto it = live.find(off);
+        if (it == live.end()) return;
+        size_t n = it->second;
+        live.erase(it);
+        used -= n;
+        auto nx = free_blocks.lower_bound(off);
+        if (nx != free_blocks.end() && off + n == nx->first) {
+            n += nx->second;
+            nx = free_blocks.erase(nx);
+        }
+        if (nx != free_blocks.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += n;
+                return;
+            }
+        }
+        free_blocks[off] = n;
+    }
+};
+
+size_t rounded(size_t n) { return std::max<size_t>(256, (n + 255) & ~size_t(255)); }
+
+struct Job {
+    uint64_t id = 0;
+    cwc_model *m = nullptr;
+    int layout = 0;
+    bool shared_k = true;
+    long long I = 0, R = 0, G = 0;
+    int K1 = 0, C = 0, NR = 1;
+    cwc_run_desc d{};
+    std::vector<double> rates;
+    std::vector<int> init;
+    cwc_kparams kp{};
+    long long *nk = nullptr;
+    double *mean = nullptr, *var = nullptr;
+    std::vector<void *> bufs;
+    size_t bytes = 0;
+    int state = CWC_JOB_QUEUED;
+    int slot = -1;
+    int n_ticks = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    long long events = 0;
+};
+
+// Device bytes a job holds while admitted (same list as admit()).
+size_t job_bytes(const Job &j)
+{
+    const size_t G = j.G, C = j.C, mom = (size_t)j.I * j.K1 * j.C, I = j.I, K1 = j.K1;
+    size_t b = 0;
+    b += rounded(j.rates.size() * 8) + rounded(j.init.size() * 4);
+    b += rounded(G * C * 4) * 2;                                         // final, checkpoint counts
+    b += rounded(G * 8) * 6;                                             // events t digest ck_t ck_e ck_dig
+    b += rounded(G) * 2 + rounded(G * 4) * 2;                            // status ck_state, n_rec ck_kn
+    b += rounded(mom * 8) * 5;                                           // s1 s2hi s2lo mean var
+    b += rounded(I * (K1 + 1) * 8) + rounded(I * K1 * 8);                // hist, n
+    return b;
+}
+
+double now_s(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct cwc_server {
+    cwc_ctx *ctx = nullptr;
+    void *pool_mem = nullptr;
+    Pool pool;
+    int max_active = 0;
+    long long slice = 0;
+    std::chrono::steady_clock::time_point t0;
+    std::thread th;
+    std::mutex mu;                       // guards everything below
+    std::condition_variable cv, idle_cv;
+    bool stop = false;
+    std::string error;
+    uint64_t next_id = 1;
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, std::unique_ptr<Job>> jobs;
+    std::vector<uint64_t> unreported;
+    std::vector<Job *> active;
+    std::vector<int> free_slots;
+    cwc_server_stats stats{};
+    // device side (scheduler thread only)
+    cwc_kparams *d_jobs = nullptr;           // [max_active]
+    unsigned long long *d_done = nullptr;    // [max_active]
+    hipStream_t streams[kStreams] = {};
+    hipStream_t aux = nullptr;
+    int *d_wave_job[kStreams] = {};
+    long long *d_wave_first[kStreams] = {};
+    size_t wave_cap[kStreams] = {};
+};
+
+namespace {
+
+void fail_locked(cwc_server *s, const std::string &msg)
+{
+    if (s->error.empty()) s->error = msg;
+}
+
+#define SCHK(call)                                                                  \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            std::lock_guard<std::mutex> lk_(s->mu);                                 \
+            fail_locked(s, std::string(#call) + ": " + hipGetErrorString(e_));      \
+            return false;                                                           \
+        }                                                                           \
+    } while (0)
+
+template <class T>
+bool take(cwc_server *s, Job *j, T **p, size_t count)
+{
+    void *q = s->pool.alloc(std::max<size_t>(1, count) * sizeof(T));
+    if (!q) return false;
+    j->bufs.push_back(q);
+    *p = (T *)q;
+    return true;
+}
+
+void drop(cwc_server *s, Job *j)
+{
+    for (void *p : j->bufs) s->pool.release(p);
+    j->bufs.clear();
+}
+
+// Reserves an admitted job's device buffers in the pool (mutex held).
+// Returns false (nothing held) if the pool is too full right now.
+bool reserve(cwc_server *s, Job *j)
+{
+    if (s->pool.bytes - s->pool.used < job_bytes(*j)) return false;
+    cwc_kparams &kp = j->kp;
+    std::memset(&kp, 0, sizeof kp);
+    const long long G = j->G, mom = j->I * (long long)j->K1 * j->C;
+    double *d_rates = nullptr;
+    int *d_init = nullptr;
+    bool ok = take(s, j, &d_rates, j->rates.size()) && take(s, j, &d_init, j->init.size()) &&
+              take(s, j, &kp.final_counts, G * j->C) && take(s, j, &kp.ck_counts, G * j->C) &&
+              take(s, j, &kp.events, G) && take(s, j, &kp.t_final, G) &&
+              take(s, j, &kp.digest, G) && take(s, j, &kp.ck_t, G) && take(s, j, &kp.ck_e, G) &&
+              take(s, j, &kp.ck_dig, G) && take(s, j, &kp.status, G) &&
+              take(s, j, &kp.ck_state, G) && take(s, j, &kp.n_recorded, G) &&
+              take(s, j, &kp.ck_kn, G) && take(s, j, &kp.s1, mom) &&
+              take(s, j, &kp.s2_hi32, mom) && take(s, j, &kp.s2_lo32, mom) &&
+              take(s, j, &j->mean, mom) && take(s, j, &j->var, mom) &&
+              take(s, j, &kp.rec_hist, j->I * (long long)(j->K1 + 1)) &&
+              take(s, j, &j->nk, j->I * (long long)j->K1);
+    if (!ok) {
+        drop(s, j);
+        return false;
+    }
+    kp.rates = d_rates;
+    kp.init = d_init;
+    j->bytes = 0;
+    for (void *p : j->bufs) j->bytes += s->pool.live[(char *)p - s->pool.base];
+    s->pool.peak = std::max(s->pool.peak, s->pool.used);   // committed reservations only
+    return true;
+}
+
+// Uploads tables, zeroes accumulators and checkpoint states and publishes
+// the job's parameters in its slot (scheduler thread, mutex not held).
+bool init_job(cwc_server *s, Job *j, int slot)
+{
+    cwc_kparams &kp = j->kp;
+    const long long G = j->G, mom = j->I * (long long)j->K1 * j->C;
+    kp.seed = j->d.seed;
+    kp.G = G;
+    kp.R = j->R;
+    kp.g_base = 0;
+    kp.max_events = j->d.max_events;
+    kp.dt = j->d.dt;
+    kp.K1 = j->K1;
+    kp.cap = (unsigned)j->d.count_cap;
+    kp.rate_stride = j->shared_k ? 0 : j->NR;
+    kp.init_stride = j->d.init_table ? j->C : 0;
+    kp.want_traj = 0;
+    kp.want_digest = j->d.want_digest ? 1 : 0;
+    kp.done_count = s->d_done + slot;
+    hipStream_t a = s->aux;
+    SCHK(hipMemcpyAsync((void *)kp.rates, j->rates.data(), j->rates.size() * 8,
+                        hipMemcpyHostToDevice, a));
+    SCHK(hipMemcpyAsync((void *)kp.init, j->init.data(), j->init.size() * 4,
+                        hipMemcpyHostToDevice, a));
+    SCHK(launch_fill_u64(kp.s1, 0, mom, a));
+    SCHK(launch_fill_u64(kp.s2_hi32, 0, mom, a));
+    SCHK(launch_fill_u64(kp.s2_lo32, 0, mom, a));
+    SCHK(launch_fill_u64(kp.rec_hist, 0, j->I * (long long)(j->K1 + 1), a));
+    SCHK(launch_fill_u64((unsigned long long *)kp.ck_state, 0, (G + 7) / 8, a));
+    SCHK(launch_fill_u64(kp.done_count, 0, 1, a));
+    SCHK(hipMemcpyAsync(s->d_jobs + slot, &kp, sizeof kp, hipMemcpyHostToDevice, a));
+    SCHK(hipStreamSynchronize(a));
+    j->slot = slot;
+    return true;
+}
+
+struct Group {
+    cwc_model *m;
+    int layout;
+    bool shared_k;
+    std::vector<int> wave_job;
+    std::vector<long long> wave_first;
+};
+
+// One tick over the admitted jobs (scheduler thread, mutex not held).
+bool run_tick(cwc_server *s, std::vector<Job *> &act)
+{
+    std::vector<Group> groups;
+    for (Job *j : act) {
+        Group *gp = nullptr;
+        for (auto &g : groups)
+            if (g.m == j->m && g.layout == j->layout && g.shared_k == j->shared_k) gp = &g;
+        if (!gp) {
+            groups.push_back(Group{j->m, j->layout, j->shared_k, {}, {}});
+            gp = &groups.back();
+        }
+        if (j->layout == 0) {
+            for (long long f = 0; f < j->G; f += 64) {
+                gp->wave_job.push_back(j->slot);
+                gp->wave_first.push_back(f);
+            }
+        } else {
+            for (long long f = 0; f < j->G; ++f) {
+                gp->wave_job.push_back(j->slot);
+                gp->wave_first.push_back(f);
+            }
+        }
+        j->n_ticks += 1;
+    }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        Group &g = groups[gi];
+        // four wavefronts per block; pad with entries that start past the end
+        while (g.wave_job.size() % 4) {
+            g.wave_job.push_back(g.wave_job.back());
+            g.wave_first.push_back(1ll << 40);
+        }
+        const int si = (int)(gi % kStreams);
+        hipStream_t st = s->streams[si];
+        if (gi >= (size_t)kStreams) SCHK(hipStreamSynchronize(st));   // reuse of its buffers
+        const size_t n = g.wave_job.size();
+        if (n > s->wave_cap[si]) {
+            if (s->d_wave_job[si]) {
+                SCHK(hipStreamSynchronize(st));
+                SCHK(hipFree(s->d_wave_job[si]));
+                SCHK(hipFree(s->d_wave_first[si]));
+            }
+            size_t cap = std::max<size_t>(n, 2 * s->wave_cap[si]);
+            SCHK(hipMalloc(&s->d_wave_job[si], cap * sizeof(int)));
+            SCHK(hipMalloc(&s->d_wave_first[si], cap * sizeof(long long)));
+            s->wave_cap[si] = cap;
+        }
+        SCHK(hipMemcpyAsync(s->d_wave_job[si], g.wave_job.data(), n * sizeof(int),
+                            hipMemcpyHostToDevice, st));
+        SCHK(hipMemcpyAsync(s->d_wave_first[si], g.wave_first.data(), n * sizeof(long long),
+                            hipMemcpyHostToDevice, st));
+        hipFunction_t fn = g.m->fn[g.layout][g.shared_k ? 4 : 5];
+        long long budget = s->slice;
+        void *args[] = {&s->d_jobs, &s->d_wave_job[si], &s->d_wave_first[si], &budget};
+        SCHK(hipModuleLaunchKernel(fn, (unsigned)(n / 4), 1, 1, 256, 1, 1, 0, st, args, nullptr));
+    }
+    // (the host vectors of `groups` outlive every copy: all streams are
+    // drained before they go out of scope)
+    for (int i = 0; i < kStreams; ++i) SCHK(hipStreamSynchronize(s->streams[i]));
+    return true;
+}
+
+bool finish_job(cwc_server *s, Job *j)
+{
+    hipStream_t a = s->aux;
+    SCHK(launch_hist_to_n(j->kp.rec_hist, j->nk, j->I, j->K1, a));
+    SCHK(launch_finalize(j->nk, j->kp.s1, j->kp.s2_hi32, j->kp.s2_lo32, j->I * (long long)j->K1,
+                         j->C, j->mean, j->var, a));
+    std::vector<long long> ev(j->G);
+    SCHK(hipMemcpyAsync(ev.data(), j->kp.events, j->G * 8, hipMemcpyDeviceToHost, a));
+    SCHK(hipStreamSynchronize(a));
+    long long tot = 0;
+    for (long long v : ev) tot += v;
+    j->events = tot;
+    return true;
+}
+
+void scheduler(cwc_server *s)
+{
+    if (hipSetDevice(s->ctx->device) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        fail_locked(s, "hipSetDevice failed in the scheduler");
+        return;
+    }
+    std::vector<unsigned long long> done(s->max_active);
+    std::vector<Job *> admitted;
+    for (;;) {
+        std::vector<Job *> act;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
+            if (s->stop) return;
+            if (!s->error.empty()) {
+                s->idle_cv.notify_all();
+                s->cv.wait(lk, [&] { return s->stop; });
+                return;
+            }
+            // admission: FIFO, while a slot and pool memory are free
+            while (!s->queue.empty() && !s->free_slots.empty()) {
+                Job *j = s->jobs[s->queue.front()].get();
+                if (!reserve(s, j)) break;
+                j->slot = s->free_slots.back();
+                s->free_slots.pop_back();
+                s->queue.pop_front();
+                admitted.push_back(j);
+            }
+        }
+        bool ok = true;
+        for (Job *j : admitted)
+            if (ok) ok = init_job(s, j, j->slot);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (Job *j : admitted) {
+                j->state = CWC_JOB_ACTIVE;
+                j->t_admit = now_s(s->t0);
+                s->active.push_back(j);
+            }
+            admitted.clear();
+            if (!ok) continue;
+            act = s->active;
+        }
+        if (act.empty()) {
+            // nothing admissible yet (pool held by finished, unreleased
+            // jobs): sleep until a submit or release
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait_for(lk, std::chrono::milliseconds(20));
+            continue;
+        }
+        const double tb = now_s(s->t0);
+        ok = run_tick(s, act);
+        if (ok && hipMemcpy(done.data(), s->d_done, s->max_active * 8, hipMemcpyDeviceToHost) !=
+                      hipSuccess) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            fail_locked(s, "reading job progress failed");
+            ok = false;
+        }
+        std::vector<Job *> finished;
+        if (ok)
+            for (Job *j : act)
+                if ((long long)done[j->slot] == j->G) {
+                    if (!finish_job(s, j)) {
+                        ok = false;
+                        break;
+                    }
+                    finished.push_back(j);
+                }
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stats.ticks += 1;
+        s->stats.busy_s += now_s(s->t0) - tb;
+        for (Job *j : finished) {
+            j->state = CWC_JOB_DONE;
+            j->t_done = now_s(s->t0);
+            s->free_slots.push_back(j->slot);
+            s->active.erase(std::find(s->active.begin(), s->active.end(), j));
+            s->unreported.push_back(j->id);
+            s->stats.jobs_done += 1;
+            s->stats.events += j->events;
+        }
+        if (s->queue.empty() && s->active.empty()) s->idle_cv.notify_all();
+        if (!ok) s->idle_cv.notify_all();
+    }
+}
+
+Job *find_done(cwc_server *s, uint64_t id, cwc_status *st)
+{
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) {
+        *st = set_err(CWC_E_INVALID, "unknown job %llu", (unsigned long long)id);
+        return nullptr;
+    }
+    if (it->second->state != CWC_JOB_DONE) {
+        *st = set_err(CWC_E_NOTREADY, "job %llu not finished", (unsigned long long)id);
+        return nullptr;
+    }
+    return it->second.get();
+}
+
+cwc_status copy_out(void *dst, const void *src, size_t bytes, int dev, hipStream_t st)
+{
+    if (!dst || !bytes) return CWC_OK;
+    if (hipMemcpyAsync(dst, src, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                       st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return set_err(CWC_E_DEVICE, "result copy failed");
+    return CWC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active,
+                             int64_t slice_events, cwc_server **out)
+{
+    if (!ctx || !out) return set_err(CWC_E_INVALID, "null argument");
+    *out = nullptr;
+    if (max_active < 1 || max_active > 1024) return set_err(CWC_E_INVALID, "max_active must be in [1, 1024]");
+    if (slice_events < 1) return set_err(CWC_E_INVALID, "slice_events must be >= 1");
+    if (hbm_budget < (1u << 20)) return set_err(CWC_E_NOMEM, "hbm_budget below 1 MiB");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(CWC_E_DEVICE, "hipSetDevice failed");
+    auto s = std::make_unique<cwc_server>();
+    s->ctx = ctx;
+    s->max_active = max_active;
+    s->slice = slice_events;
+    cwc_status st = CWC_OK;
+    s->pool_mem = ctx->alloc(hbm_budget, &st);
+    if (!s->pool_mem) return st;
+    s->pool.init(s->pool_mem, hbm_budget);
+    bool ok = hipMalloc(&s->d_jobs, sizeof(cwc_kparams) * max_active) == hipSuccess &&
+              hipMalloc(&s->d_done, 8 * max_active) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < kStreams; ++i)
+        ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        ctx->release(s->pool_mem);
+        return set_err(CWC_E_DEVICE, "server device setup failed");
+    }
+    for (int i = max_active - 1; i >= 0; --i) s->free_slots.push_back(i);
+    s->stats.pool_bytes = (int64_t)s->pool.bytes;
+    s->t0 = std::chrono::steady_clock::now();
+    cwc_server *raw = s.release();
+    raw->th = std::thread(scheduler, raw);
+    *out = raw;
+    return CWC_OK;
+}
+
+cwc_status cwc_server_submit(cwc_server *s, const cwc_model *m, const cwc_run_desc *d,
+                             uint64_t *job_id)
+{
+    if (!s || !m || !d || !job_id) return set_err(CWC_E_INVALID, "null argument");
+    if (m->ctx != s->ctx) return set_err(CWC_E_INVALID, "model belongs to another context");
+    auto j = std::make_unique<Job>();
+    cwc_status st = validate_run(m, d, &j->rates, &j->init);
+    if (st != CWC_OK) return st;
+    st = ensure_layout(const_cast<cwc_model *>(m), m->flat.layout);
+    if (st != CWC_OK) return st;
+    j->m = const_cast<cwc_model *>(m);
+    j->layout = m->flat.layout;
+    j->d = *d;
+    j->d.tuning = nullptr;
+    j->I = d->n_instances;
+    j->R = d->replicas_per_instance;
+    j->G = j->I * j->R;
+    j->K1 = d->n_samples;
+    j->C = m->flat.n_cells;
+    j->NR = std::max(1, m->flat.n_rules);
+    j->shared_k = !(d->rate_table && m->flat.n_rules > 0);
+    if (job_bytes(*j) > s->pool.bytes)
+        return set_err(CWC_E_NOMEM, "job needs %zu bytes, the server pool has %zu", job_bytes(*j),
+                       s->pool.bytes);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->error.empty()) return set_err(CWC_E_DEVICE, "server failed: %s", s->error.c_str());
+    j->id = s->next_id++;
+    j->t_submit = now_s(s->t0);
+    *job_id = j->id;
+    s->queue.push_back(j->id);
+    s->jobs[j->id] = std::move(j);
+    s->stats.jobs_submitted += 1;
+    s->cv.notify_all();
+    return CWC_OK;
+}
+
+cwc_status cwc_server_poll(cwc_server *s, uint64_t *done_ids, int32_t max, int32_t *n_done)
+{
+    if (!s || !n_done || (max > 0 && !done_ids)) return set_err(CWC_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->error.empty()) return set_err(CWC_E_DEVICE, "server failed: %s", s->error.c_str());
+    int n = std::min<int>(max, (int)s->unreported.size());
+    for (int i = 0; i < n; ++i) done_ids[i] = s->unreported[i];
+    s->unreported.erase(s->unreported.begin(), s->unreported.begin() + n);
+    *n_done = n;
+    return CWC_OK;
+}
+
+cwc_status cwc_server_job_info(cwc_server *s, uint64_t job, cwc_job_info *info)
+{
+    if (!s || !info) return set_err(CWC_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(job);
+    if (it == s->jobs.end()) return set_err(CWC_E_INVALID, "unknown job");
+    const Job &j = *it->second;
+    info->state = j.state;
+    info->n_ticks = j.n_ticks;
+    info->t_submit = j.t_submit;
+    info->t_admit = j.t_admit;
+    info->t_done = j.t_done;
+    info->events = j.events;
+    info->bytes = (int64_t)j.bytes;
+    return CWC_OK;
+}
+
+cwc_status cwc_server_fetch_stats(cwc_server *s, uint64_t job, double *mean, double *var,
+                                  int64_t *n, int dst_is_device)
+{
+    if (!s) return set_err(CWC_E_INVALID, "null server");
+    cwc_status st = CWC_OK;
+    Job *j;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        j = find_done(s, job, &st);
+    }
+    if (!j) return st;
+    const size_t mom = (size_t)j->I * j->K1 * j->C;
+    hipStream_t a;
+    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess)
+        return set_err(CWC_E_DEVICE, "stream");
+    if ((st = copy_out(mean, j->mean, mom * 8, dst_is_device, a)) == CWC_OK &&
+        (st = copy_out(var, j->var, mom * 8, dst_is_device, a)) == CWC_OK)
+        st = copy_out(n, j->nk, (size_t)j->I * j->K1 * 8, dst_is_device, a);
+    (void)hipStreamDestroy(a);
+    return st;
+}
+
+cwc_status cwc_server_fetch_counters(cwc_server *s, uint64_t job, int64_t *events,
+                                     uint8_t *status, uint64_t *digest, double *t_final,
+                                     int32_t *n_recorded, int32_t *final_counts,
+                                     int dst_is_device)
+{
+    if (!s) return set_err(CWC_E_INVALID, "null server");
+    cwc_status st = CWC_OK;
+    Job *j;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        j = find_done(s, job, &st);
+    }
+    if (!j) return st;
+    const size_t G = (size_t)j->G;
+    hipStream_t a;
+    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess)
+        return set_err(CWC_E_DEVICE, "stream");
+    int dv = dst_is_device;
+    if ((st = copy_out(events, j->kp.events, G * 8, dv, a)) == CWC_OK &&
+        (st = copy_out(status, j->kp.status, G, dv, a)) == CWC_OK &&
+        (st = copy_out(digest, j->kp.digest, G * 8, dv, a)) == CWC_OK &&
+        (st = copy_out(t_final, j->kp.t_final, G * 8, dv, a)) == CWC_OK &&
+        (st = copy_out(n_recorded, j->kp.n_recorded, G * 4, dv, a)) == CWC_OK)
+        st = copy_out(final_counts, j->kp.final_counts, G * j->C * 4, dv, a);
+    (void)hipStreamDestroy(a);
+    return st;
+}
+
+cwc_status cwc_server_release(cwc_server *s, uint64_t job)
+{
+    if (!s) return set_err(CWC_E_INVALID, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    cwc_status st = CWC_OK;
+    Job *j = find_done(s, job, &st);
+    if (!j) return st;
+    drop(s, j);
+    s->jobs.erase(job);
+    s->cv.notify_all();            // freed memory may admit queued jobs
+    return CWC_OK;
+}
+
+cwc_status cwc_server_wait_idle(cwc_server *s, double timeout_s)
+{
+    if (!s) return set_err(CWC_E_INVALID, "null server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    bool ok = s->idle_cv.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] {
+        return (s->queue.empty() && s->active.empty()) || !s->error.empty();
+    });
+    if (!s->error.empty()) return set_err(CWC_E_DEVICE, "server failed: %s", s->error.c_str());
+    if (!ok) return set_err(CWC_E_NOTREADY, "jobs still queued or active");
+    return CWC_OK;
+}
+
+cwc_status cwc_server_get_stats(cwc_server *s, cwc_server_stats *st)
+{
+    if (!s || !st) return set_err(CWC_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *st = s->stats;
+    st->pool_used = (int64_t)s->pool.used;
+    st->pool_peak = (int64_t)s->pool.peak;
+    return CWC_OK;
+}
+
+void cwc_server_destroy(cwc_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->th.joinable()) s->th.join();
+    (void)hipSetDevice(s->ctx->device);
+    for (int i = 0; i < kStreams; ++i) {
+        if (s->streams[i]) {
+            (void)hipStreamSynchronize(s->streams[i]);
+            (void)hipStreamDestroy(s->streams[i]);
+        }
+        if (s->d_wave_job[i]) (void)hipFree(s->d_wave_job[i]);
+        if (s->d_wave_first[i]) (void)hipFree(s->d_wave_first[i]);
+    }
+    if (s->aux) (void)hipStreamDestroy(s->aux);
+    if (s->d_jobs) (void)hipFree(s->d_jobs);
+    if (s->d_done) (void)hipFree(s->d_done);
+    s->ctx->release(s->pool_mem);
+    delete s;
+}
+
+}  // extern "C"
