@@ -80,6 +80,86 @@ def cpu_baseline(model, run, budget_s=15.0):
                       "with the on-line moments)" % (n, run["n_instances"] * run["replicas"], ev, dt)}
 
 
+def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=64):
+    """Replays the first n_jobs of the serving trace (Poisson arrivals, mixed
+    configurations 0-3, 64..8192 replicas, t_end 5..100) against the
+    continuous-batching server; arrival times are multiplied by time_scale.
+    Returns latency percentiles (submit -> statistics ready) and rates."""
+    import threading
+    import numpy as np
+    import workloads as W
+    from paper_1010_2438_amd import Model, Server
+    trace = W.arrival_trace()[:n_jobs]
+    models = {0: W.lotka_volterra(), 1: W.gene_regulation(1), 3: W.multi_compartment(3)}
+    models[2] = models[1]
+    mo = {}
+    for c, m in models.items():
+        key = id(m)
+        if key not in mo:
+            mo[key] = Model(ctx, m)
+    tab, _ = W.sweep_rate_table(models[1], 4096, 2)
+    srv = Server(ctx, hbm_budget=budget, max_active=max_active, slice_events=slice_events)
+
+    def run_of(job):
+        c = job["config"]
+        if c == 2:
+            ni = (job["replicas"] + 63) // 64
+            lo = (job["job"] * 37) % (4096 - ni)
+            return W.make_run(seed=job["seed"], n_instances=ni, replicas=64, dt=job["dt"],
+                              n_samples=job["n_samples"], rate_table=tab[lo:lo + ni],
+                              count_cap=job["count_cap"])
+        return W.make_run(seed=job["seed"], replicas=job["replicas"], dt=job["dt"],
+                          n_samples=job["n_samples"], count_cap=job["count_cap"])
+
+    runs = [run_of(j) for j in trace]
+    ids = [None] * len(trace)
+    t_start = time.perf_counter()
+    err = []
+
+    def submitter():
+        try:
+            for i, job in enumerate(trace):
+                target = job["arrival_s"] * time_scale
+                dt = target - (time.perf_counter() - t_start)
+                if dt > 0:
+                    time.sleep(dt)
+                ids[i] = srv.submit(mo[id(models[job["config"]])], runs[i])
+        except Exception as e:       # surfaced below
+            err.append(e)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    infos = {}
+    last = time.perf_counter()
+    while len(infos) < len(trace):
+        if err:
+            raise err[0]
+        for jid in srv.poll():
+            infos[jid] = srv.info(jid)
+            srv.release(jid)
+        if time.perf_counter() - last > 10.0:
+            last = time.perf_counter()
+            log("  serving: %d/%d jobs done after %.0f s" % (len(infos), len(trace),
+                                                          last - t_start))
+        time.sleep(0.001)
+    th.join()
+    wall = time.perf_counter() - t_start
+    st = srv.server_stats()
+    srv.close()
+    lat = np.array([infos[j]["t_done"] - infos[j]["t_submit"] for j in ids])
+    ev = sum(infos[j]["events"] for j in ids)
+    span = trace[-1]["arrival_s"] * time_scale
+    return {"jobs": len(trace), "arrival_span_s": span,
+            "offered_jobs_per_s": len(trace) / max(span, 1e-9),
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "max_latency_s": float(lat.max()),
+            "events": int(ev), "achieved_events_per_s": ev / wall,
+            "offered_events_per_s": ev / max(span, 1e-9),
+            "makespan_s": wall, "ticks": st["ticks"],
+            "hbm_budget_bytes": st["pool_bytes"], "pool_peak_bytes": st["pool_peak"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +167,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=150)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build simulates on one GPU only; --gpus %d is not supported "
@@ -123,6 +205,22 @@ def main():
                  "plain_events_per_s": sq["events_per_s"],
                  "persistent_over_plain": sp["events_per_s"] / sq["events_per_s"]}
 
+    serving = None
+    if not args.no_serve:
+        sat = serve_trace(ctx, args.serve_jobs, 1.0, 16 << 30)
+        log("serving (trace rate)", sat)
+        # a labelled sub-saturation run: arrivals stretched so the offered
+        # load is about 70% of the achieved rate above
+        scale = max(1.0, sat["offered_events_per_s"] / (0.7 * sat["achieved_events_per_s"]))
+        sub = serve_trace(ctx, args.serve_jobs, scale, 16 << 30)
+        log("serving (sub-saturation)", sub)
+        small = serve_trace(ctx, args.serve_jobs, scale, 2 << 30)
+        log("serving (sub-saturation, 2 GiB budget)", small)
+        serving = {"trace": "first %d jobs of %s" % (args.serve_jobs, W.CONFIG_NAMES[4]),
+                   "at_trace_rate": sat, "sub_saturation": dict(sub, time_scale=scale),
+                   "sub_saturation_2GiB": small,
+                   "p50_latency_s": sub["p50_latency_s"], "p99_latency_s": sub["p99_latency_s"]}
+
     achieved = pers["events_per_step"] * alg / (pers["kernel_ms"] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
@@ -145,6 +243,7 @@ def main():
         "plain": {"events_per_s": plain["events_per_s"], "ms_per_step": plain["ms_per_step"],
                   "persistent_over_plain": pers["events_per_s"] / plain["events_per_s"]},
         "sweep": sweep,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

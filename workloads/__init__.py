@@ -302,7 +302,10 @@ def arrival_trace(n_jobs=2000, mean_gap_s=0.005, seed=4):
     """Serving trace: Poisson arrivals (exponential gaps, mean 5 ms), each
     job draws a config in {0,1,2,3}, replicas round(exp(U(ln 64, ln 8192)))
     and t_end ~ U(5,100) snapped down to that config's sample grid; the job
-    seed is the job index."""
+    seed is the job index.  Lotka-Volterra jobs carry a count cap of 10^5:
+    over horizons this long a replica's predators can die out, after which
+    prey grow without bound (about 2^31 birth events to overflow int32); the
+    cap ends such a replica with status OVERFLOW instead."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(mean_gap_s, size=n_jobs)
     t_arr = np.cumsum(gaps)
@@ -316,7 +319,7 @@ def arrival_trace(n_jobs=2000, mean_gap_s=0.005, seed=4):
         K = int(math.floor(t_end[j] / dt + 1e-9))
         jobs.append({"job": j, "arrival_s": float(t_arr[j]), "config": c,
                      "replicas": int(reps[j]), "dt": dt, "n_samples": K + 1,
-                     "seed": j})
+                     "seed": j, "count_cap": 100000 if c == 0 else 2**31 - 1})
     return jobs
 
 
