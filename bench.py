@@ -1,13 +1,19 @@
 """Benchmark: applied SSA events per second on one MI355X.
 
-Workload (one "step" = the whole hot path over one batch): the
-gene-regulation model (two compartments, 10 species, 20 rules, four of them
-across the nuclear membrane), 16384 replicas simulated to t = 100 with 201
-sample points and the on-line reduction into per-sample mean/variance.
-Inputs are resident on the device before the timed region.  The headline
-value is the persistent form (lane refill from a work queue, replayed as a
-HIP graph); the plain one-lane-per-replica launch is timed on the same
-inputs beside it, as is the 4096-instance x 64-replica parameter sweep.
+Headline workload (one "step" = the whole hot path over one batch): the
+batched parameter sweep -- the gene-regulation model (two compartments, 10
+species, 20 rules, four across the nuclear membrane) in 4096 instances whose
+kinetic constants are scaled by a per-instance factor 10^U(-1,1), 64
+replicas each (262144 trajectories, ~100x spread of events per trajectory),
+simulated to t = 100 with 201 sample points and reduced on line into
+per-instance, per-sample mean/variance.  Inputs are resident on the device
+before the timed region.  `value` is the batched persistent form (resident
+grid, lane refill from a longest-first work queue, replayed as a HIP graph,
+autotuned launch shape); the plain one-lane-per-trajectory launch is timed
+on the same inputs beside it.  Also reported: the 16384-replica
+gene-regulation run in both forms, the 32-cell multi-compartment run, the
+serving trace (continuous batching, p50/p99 latency), the VALU roofline of
+the headline kernel and the CPU oracle on the host cores.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on
 one GPU.
@@ -29,13 +35,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_form(ctx, model, run, mode, steps, warmup, stream):
+def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None):
     """Warm up, then time exactly `steps` launches bracketed by device
     synchronisation; per-launch simulation time from the library's HIP events
     on the launch stream."""
     import torch
     from paper_1010_2438_amd import Run
-    r = Run(ctx, model, run, mode=mode, stream=stream)
+    r = Run(ctx, model, run, mode=mode, stream=stream, tuning=tuning)
     r.wait()
     for _ in range(warmup):
         r.relaunch(stream)
@@ -60,24 +66,43 @@ def time_form(ctx, model, run, mode, steps, warmup, stream):
 
 
 def cpu_baseline(model, run, budget_s=15.0):
-    """The oracle (plain C direct method, one trajectory per call) on the
-    host cores: trajectories 0..n-1 of the same workload, n sized for about
-    `budget_s` seconds of work."""
+    """The oracle (plain C direct method) on the host cores over a bounded
+    sample of the same workload: replica 0 of every s-th instance, s chosen
+    for about `budget_s` seconds of work, the instances spread over the
+    whole sweep (events per trajectory vary ~100x across it)."""
+    import numpy as np
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    probe = oracle.simulate(model, run, g0=0, g1=threads, want_stats=False, threads=threads)
-    t0 = time.perf_counter()
-    probe = oracle.simulate(model, run, g0=0, g1=threads, want_stats=False, threads=threads)
-    dt = time.perf_counter() - t0
-    n = max(threads, int(threads * budget_s / max(dt, 1e-3)))
-    n = min(n, run["n_instances"] * run["replicas"])
-    t0 = time.perf_counter()
-    res = oracle.simulate(model, run, g0=0, g1=n, want_stats=True, threads=threads)
-    dt = time.perf_counter() - t0
-    ev = int(res["events"].sum())
+    I, R = run["n_instances"], run["replicas"]
+    fm = oracle.FlatModel(model)
+
+    def sample(stride):
+        ids = list(range(0, I, stride))
+        t0 = time.perf_counter()
+        import threading
+        evs = [0] * len(ids)
+
+        def work(k):
+            for q in range(k, len(ids), threads):
+                g = ids[q] * R
+                r = oracle.simulate(model, run, g0=g, g1=g + 1, want_stats=False, flat=fm)
+                evs[q] = int(r["events"][0])
+
+        ts = [threading.Thread(target=work, args=(k,)) for k in range(threads)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        return len(ids), sum(evs), time.perf_counter() - t0
+
+    n, ev, dt = sample(256)                                  # probe: 16 trajectories
+    rate = ev / max(dt, 1e-6) * threads / min(threads, n)    # events/s with all threads busy
+    n_want = budget_s * rate / max(ev / n, 1.0)
+    stride = max(1, int(I / max(n_want, 1.0)))
+    n, ev, dt = sample(stride)
     return {"value": ev / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of %d trajectories of the same workload (%d events, %.1f s, "
-                      "with the on-line moments)" % (n, run["n_instances"] * run["replicas"], ev, dt)}
+            "sample": "replica 0 of every %d-th of %d instances (%d trajectories, %d events, "
+                      "%.1f s)" % (stride, I, n, ev, dt)}
 
 
 def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=64):
@@ -165,7 +190,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=150)
@@ -182,28 +207,44 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     stream = torch.cuda.Stream()
     ctx = Context(0)
-    m1, run1 = W.config(1)
-    model1 = Model(ctx, m1)
-    alg = model1.info["alg_slots_per_event"]
-    log("config 1 model: %s, %.1f algorithmic VALU slots/event" % (model1.info, alg))
-    pers = time_form(ctx, model1, run1, "persistent", args.steps, args.warmup, stream)
-    log("persistent", pers)
-    plain = time_form(ctx, model1, run1, "plain", args.steps, args.warmup, stream)
-    log("plain", plain)
 
-    sweep = None
-    if not args.no_sweep:
-        m2, run2 = W.config(2)
-        model2 = Model(ctx, m2)
-        sw_steps = max(1, args.steps // 4)
-        sp = time_form(ctx, model2, run2, "persistent", sw_steps, 1, stream)
-        sq = time_form(ctx, model2, run2, "plain", sw_steps, 1, stream)
-        log("sweep persistent", sp, "plain", sq)
-        sweep = {"workload": W.CONFIG_NAMES[2], "trajectories": 4096 * 64,
-                 "events_per_step": sp["events_per_step"],
-                 "persistent_events_per_s": sp["events_per_s"],
-                 "plain_events_per_s": sq["events_per_s"],
-                 "persistent_over_plain": sp["events_per_s"] / sq["events_per_s"]}
+    # ---- headline: the batched sweep, persistent vs plain
+    m2, run2 = W.config(2)
+    model2 = Model(ctx, m2)
+    alg2 = model2.info["alg_slots_per_event"]
+    t2p = model2.autotune(run2, "persistent", budget_s=3.0)
+    t2q = model2.autotune(run2, "plain", budget_s=1.0)
+    log("sweep: %s, %.1f algorithmic VALU slots/event; tuned persistent %s plain %s"
+        % (model2.info, alg2, t2p, t2q))
+    pers = time_form(ctx, model2, run2, "persistent", args.steps, args.warmup, stream, t2p)
+    log("sweep persistent", pers)
+    plain = time_form(ctx, model2, run2, "plain", max(1, args.steps // 2), 1, stream, t2q)
+    log("sweep plain", plain)
+
+    # ---- the plain method at GPU scale and the multi-compartment model
+    extra = {}
+    if not args.no_extra:
+        m1, run1 = W.config(1)
+        model1 = Model(ctx, m1)
+        t1p = model1.autotune(run1, "persistent", budget_s=2.0)
+        t1q = model1.autotune(run1, "plain", budget_s=1.0)
+        g1p = time_form(ctx, model1, run1, "persistent", args.steps, args.warmup, stream, t1p)
+        g1q = time_form(ctx, model1, run1, "plain", args.steps, args.warmup, stream, t1q)
+        log("gene regulation persistent", g1p, "plain", g1q)
+        extra[W.CONFIG_NAMES[1]] = {
+            "persistent_events_per_s": g1p["events_per_s"], "plain_events_per_s": g1q["events_per_s"],
+            "events_per_step": g1p["events_per_step"], "tuning_persistent": t1p,
+            "tuning_plain": t1q}
+        m3, run3 = W.config(3)
+        model3 = Model(ctx, m3)
+        t3p = model3.autotune(run3, "persistent", budget_s=2.0)
+        g3p = time_form(ctx, model3, run3, "persistent", max(1, args.steps // 2), 1, stream, t3p)
+        g3q = time_form(ctx, model3, run3, "plain", max(1, args.steps // 2), 1, stream, None)
+        log("multi-compartment persistent", g3p, "plain", g3q)
+        extra[W.CONFIG_NAMES[3]] = {
+            "persistent_events_per_s": g3p["events_per_s"], "plain_events_per_s": g3q["events_per_s"],
+            "events_per_step": g3p["events_per_step"], "layout": "wavefront per trajectory",
+            "tuning_persistent": t3p}
 
     serving = None
     if not args.no_serve:
@@ -221,13 +262,14 @@ def main():
                    "sub_saturation_2GiB": small,
                    "p50_latency_s": sub["p50_latency_s"], "p99_latency_s": sub["p99_latency_s"]}
 
-    achieved = pers["events_per_step"] * alg / (pers["kernel_ms"] * 1e-3)
+    achieved = pers["events_per_step"] * alg2 / (pers["kernel_ms"] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
-                "work_unit": "%.1f VALU issue slots per applied event" % alg}
+                "kernel": "cwc_lane_persistent_table",
+                "work_unit": "%.1f VALU issue slots per applied event" % alg2}
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(m1, run1)
+        cpu = cpu_baseline(m2, run2)
         log("cpu", cpu)
 
     out = {
@@ -236,13 +278,16 @@ def main():
         "ms_per_step": pers["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+i32",
         "data": "synthetic",
-        "config": {"workload": W.CONFIG_NAMES[1], "replicas": run1["replicas"],
-                   "t_end": (run1["n_samples"] - 1) * run1["dt"],
-                   "sample_points": run1["n_samples"], "form": "persistent",
-                   "events_per_step": pers["events_per_step"]},
+        "config": {"workload": W.CONFIG_NAMES[2], "instances": run2["n_instances"],
+                   "replicas_per_instance": run2["replicas"],
+                   "trajectories": run2["n_instances"] * run2["replicas"],
+                   "t_end": (run2["n_samples"] - 1) * run2["dt"],
+                   "sample_points": run2["n_samples"], "form": "persistent",
+                   "events_per_step": pers["events_per_step"], "tuning": t2p},
         "plain": {"events_per_s": plain["events_per_s"], "ms_per_step": plain["ms_per_step"],
+                  "tuning": t2q,
                   "persistent_over_plain": pers["events_per_s"] / plain["events_per_s"]},
-        "sweep": sweep,
+        "other_workloads": extra,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,

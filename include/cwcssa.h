@@ -248,6 +248,21 @@ cwc_status cwc_run_fetch_counters(cwc_run *r, int64_t *events,
                                   int32_t *final_counts, int dst_is_device);
 void cwc_run_destroy(cwc_run *r);
 
+/* ------------------------------------------------------------ autotuner */
+
+/* Times candidate launch shapes for this model and run -- layout (lane or
+ * wavefront per replica, when the model fits both), block size (64, 128,
+ * 256) and, in persistent mode, resident wavefronts per SIMD (1, 2, 4) --
+ * on the run's own inputs with the horizon shortened so that the whole
+ * search takes about `budget_s` seconds, and returns the fastest in *out.
+ * The choice is stored in a tuning table on disk (the library's cache
+ * directory), keyed by the model's generated code, the run's mode, whether
+ * it has a rate table, and log2 of its trajectory count; cwc_run_submit
+ * uses a stored entry when the descriptor's tuning is NULL.  Results never
+ * depend on the tuning.  Errors: as cwc_run_submit. */
+cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d,
+                        double budget_s, cwc_tuning *out);
+
 /* ------------------------------------------------------------- serving */
 
 /* Continuous batching (paper Sec. 5.2 schema ii: instances as objects that

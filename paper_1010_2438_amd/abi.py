@@ -33,6 +33,7 @@ SYMBOLS = [
     "cwc_server_submit", "cwc_server_poll", "cwc_server_job_info",
     "cwc_server_fetch_stats", "cwc_server_fetch_counters", "cwc_server_release",
     "cwc_server_wait_idle", "cwc_server_get_stats", "cwc_server_destroy",
+    "cwc_autotune",
     "cwc_stats_finalize",
 ]
 
@@ -133,6 +134,8 @@ def load(path: str = LIB_PATH):
         "cwc_run_fetch_counters": [P, P, P, P, P, P, P, ctypes.c_int],
         "cwc_stats_finalize": [P, P, P, P, P, I64, I32, P, P, P],
         "cwc_server_create": [P, S, I32, I64, ctypes.POINTER(P)],
+        "cwc_autotune": [P, P, ctypes.POINTER(cwc_run_desc), ctypes.c_double,
+                         ctypes.POINTER(cwc_tuning)],
         "cwc_server_submit": [P, P, ctypes.POINTER(cwc_run_desc), ctypes.POINTER(ctypes.c_uint64)],
         "cwc_server_poll": [P, P, I32, ctypes.POINTER(I32)],
         "cwc_server_job_info": [P, ctypes.c_uint64, ctypes.POINTER(cwc_job_info)],
@@ -268,6 +271,16 @@ class Model:
         info = cwc_model_info()
         check(L.cwc_model_get_info(h, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in cwc_model_info._fields_}
+
+    def autotune(self, run: Dict, mode="persistent", budget_s=5.0) -> Dict:
+        """cwc_autotune: fastest launch shape for this run (stored for later
+        submissions of the same model/mode/size class)."""
+        d, _r, _i = _run_desc(run)
+        d.mode = MODE_PERSISTENT if mode == "persistent" else MODE_PLAIN
+        t = cwc_tuning()
+        check(load().cwc_autotune(self.ctx.h, self.h, ctypes.byref(d), float(budget_s),
+                                  ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in cwc_tuning._fields_}
 
     def source(self) -> str:
         L = load()

@@ -56,6 +56,16 @@ __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const i32
 // The statement macros below operate on the locals declared by
 // CWC_LANE_LOCALS; they are shared by the run-to-completion kernels and the
 // time-sliced kernel of the serving form.
+//
+// The event loop is software-pipelined: the draw of event e (E = -ln u_tau,
+// U = u_sel) is ready when the iteration starts, and the draw of event e+1
+// is computed in the same straight-line block as event e's propensities,
+// waiting time, selection and candidate update, so the independent integer
+// (Philox) and floating-point (tree, division, descent) chains overlap.
+// The update is committed unless something rare happens -- a sample time
+// is crossed, the state is absorbing, a count would exceed the cap, or the
+// event cap is reached -- in which case the slow path handles it in the
+// order the direct method defines.
 
 #define CWC_LANE_LOCALS                                                       \
     const double INF = __longlong_as_double(0x7FF0000000000000ll);            \
@@ -67,7 +77,18 @@ __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const i32
     u64 e = 0, dig = 0;             /* applied events (= next draw), digest */ \
     i64 g = 0, lg = 0, inst = 0;    /* global / local id, instance */         \
     i32 kn = 0;                     /* next sample index */                   \
+    double E = 0.0, U = 0.0;        /* draw e: -ln(u_tau), u_sel */           \
     (void)INF;
+
+// draw e of trajectory g
+#define CWC_DRAW(ee, EO, UO)                                                  \
+    do {                                                                      \
+        u32 x0_, x1_, x2_, x3_;                                               \
+        cwc_philox((u32)(ee), (u32)((ee) >> 32), (u32)g, (u32)((u64)g >> 32), \
+                   (u32)p.seed, (u32)(p.seed >> 32), x0_, x1_, x2_, x3_);     \
+        (EO) = -cwc_ssa_log(cwc_u_open0(x0_, x1_));                           \
+        (UO) = cwc_u_open1(x2_, x3_);                                         \
+    } while (0)
 
 // identify trajectory lg of the run (instance, global id, rates)
 #define CWC_IDENT(LG, SHARED_K)                                               \
@@ -88,6 +109,7 @@ __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const i32
           CWC_LOAD_COUNTS(ini_); }                                            \
         t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
         dig = 0xcbf29ce484222325ull;                                          \
+        CWC_DRAW(e, E, U);                                                    \
     } while (0)
 
 // emit sample kn of the current state and move to the next sample time
@@ -105,34 +127,36 @@ __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const i32
 #define CWC_STEP(st)                                                          \
     do {                                                                      \
         CWC_TREE;                       /* Match: propensities of the state */ \
-        u32 x0_, x1_, x2_, x3_;                                               \
-        cwc_philox((u32)e, (u32)(e >> 32), (u32)g, (u32)((u64)g >> 32),       \
-                   (u32)p.seed, (u32)(p.seed >> 32), x0_, x1_, x2_, x3_);     \
         const double a0_ = CWC_ROOT;                                          \
-        if (a0_ == 0.0) {                                                     \
+        const double tn_ = t + E / a0_; /* Resolve: time of the event */      \
+        double x_ = U * a0_;            /* Resolve: which slot */             \
+        i32 j_;                                                               \
+        CWC_DESCEND(x_, j_);                                                  \
+        CWC_APPLY_TRY(j_, p.cap, ovf_); /* Update, as a candidate */          \
+        const u64 e1_ = e + 1;                                                \
+        double E1_, U1_;                                                      \
+        CWC_DRAW(e1_, E1_, U1_);        /* next draw, independent */          \
+        const bool slow_ = (a0_ == 0.0) | (t_next < tn_) | ovf_ |             \
+                           (e1_ == (u64)p.max_events);                        \
+        if (!slow_) {                                                         \
+            CWC_COMMIT();                                                     \
+            t = tn_; e = e1_; E = E1_; U = U1_;                               \
+            if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
+        } else if (a0_ == 0.0) {                                              \
             /* absorbing state: remaining samples hold the current counts */  \
             while (kn < p.K1) CWC_EMIT();                                     \
             (st) = CWC_ST_ABSORBED;                                           \
         } else {                                                              \
-            const double tau_ = (-cwc_ssa_log(cwc_u_open0(x0_, x1_))) / a0_;   \
-            const double tn_ = t + tau_;                                      \
             while (t_next < tn_) CWC_EMIT();                                  \
             if (kn >= p.K1) {                                                 \
-                (st) = CWC_ST_OK;                                             \
+                (st) = CWC_ST_OK;       /* this draw lies past the horizon */ \
+            } else if (ovf_) {                                                \
+                (st) = CWC_ST_OVERFLOW;                                       \
             } else {                                                          \
-                double x_ = cwc_u_open1(x2_, x3_) * a0_;                      \
-                i32 j_;                                                       \
-                CWC_DESCEND(x_, j_);                                          \
-                bool ovf_;                                                    \
-                CWC_APPLY(j_, p.cap, ovf_);                                   \
-                if (ovf_) {                                                   \
-                    (st) = CWC_ST_OVERFLOW;                                   \
-                } else {                                                      \
-                    t = tn_;                                                  \
-                    e += 1;                                                   \
-                    if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
-                    if (e == (u64)p.max_events) (st) = CWC_ST_EVENT_CAP;      \
-                }                                                             \
+                CWC_COMMIT();                                                 \
+                t = tn_; e = e1_; E = E1_; U = U1_;                           \
+                if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
+                if (e == (u64)p.max_events) (st) = CWC_ST_EVENT_CAP;          \
             }                                                                 \
         }                                                                     \
     } while (0)
@@ -237,6 +261,7 @@ __device__ __forceinline__ void cwc_lane_slice(const cwc_kparams *jobs, const in
             dig = p.ck_dig[lg];
             kn = p.ck_kn[lg];
             t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
+            CWC_DRAW(e, E, U);
         }
     }
     long long n = 0;

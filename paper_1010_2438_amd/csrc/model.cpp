@@ -398,10 +398,11 @@ std::string codegen_lane(const Flat &f)
         std::snprintf(b, sizeof b, wide ? "0x%llxull" : "0x%llxu", m);
         return std::string(b);
     };
-    w.begin("CWC_APPLY(j, cap, ovf)");
-    w.line("{");
-    w.line("bool o_ = false;");
-    w.line(wide ? "const unsigned js_ = (unsigned)(j);" : "const unsigned js_ = (unsigned)(j);");
+    // CWC_APPLY_TRY declares the candidate counts v<c>_ of the event and its
+    // overflow flag in the enclosing scope; CWC_COMMIT makes them current.
+    w.begin("CWC_APPLY_TRY(j, cap, ovf)");
+    w.line("const unsigned js_ = (unsigned)(j);");
+    w.line("bool ovf = false;");
     for (int c = 0; c < C; ++c) {
         if (per_cell[c].empty()) continue;
         bool pos = false;
@@ -422,14 +423,12 @@ std::string codegen_lane(const Flat &f)
             }
         }
         w.line("const unsigned v" + I(c) + "_ = " + e + ";");
-        if (pos) w.line("o_ = o_ || (v" + I(c) + "_ > (cap));");
+        if (pos) w.line("ovf = ovf || (v" + I(c) + "_ > (cap));");
     }
-    w.line("if (!o_) {");
+    w.end();
+    w.begin("CWC_COMMIT()");
     for (int c = 0; c < C; ++c)
-        if (!per_cell[c].empty()) w.line("    n" + I(c) + " = (int)v" + I(c) + "_;");
-    w.line("}");
-    w.line("(ovf) = o_;");
-    w.line("}");
+        if (!per_cell[c].empty()) w.line("n" + I(c) + " = (int)v" + I(c) + "_;");
     w.end();
 
     // --- stage the counts for the on-line reduction (see CWC_EMIT)

@@ -236,9 +236,15 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     const long long I = d->n_instances, R = d->replicas_per_instance, G = I * R;
     const int C = f.n_cells, NR = std::max(1, f.n_rules), K1 = d->n_samples;
 
-    // launch shape
+    // launch shape: the caller's, else the autotuner's stored choice, else
+    // defaults
     cwc_tuning tun{};
-    if (d->tuning) tun = *d->tuning;
+    bool tuned = false;
+    if (d->tuning) {
+        tun = *d->tuning;
+    } else {
+        tuned = tuning_lookup(m, d, &tun);
+    }
     if (tun.block_size <= 0) tun.block_size = 64;
     if (tun.block_size % 64 || tun.block_size > 256)
         return set_err(CWC_E_INVALID, "block_size must be a multiple of 64, at most 256");
@@ -342,15 +348,19 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
 
     const bool shared = kp.rate_stride == 0;
     const bool wave = layout == 1;
-    if (wave && (!d->tuning || d->tuning->block_size <= 0)) tun.block_size = 256;
+    if (wave && !tuned && (!d->tuning || d->tuning->block_size <= 0)) tun.block_size = 256;
     r->block = (unsigned)tun.block_size;
     // lane layout: one trajectory per lane; wavefront layout: one per wave
     const long long per_block = wave ? r->block / 64 : r->block;
     const long long need_blocks = (G + per_block - 1) / per_block;
     if (d->mode == CWC_MODE_PERSISTENT) {
-        r->fn = m->fn[layout][shared ? 2 : 3];
         long long resident = (long long)ctx->n_cu * 4 * tun.waves_per_simd * 64 / r->block;
         r->grid = (unsigned)std::max(1ll, std::min(need_blocks, resident));
+        // a resident grid that already holds every trajectory has nothing
+        // to refill: the queue would stay empty, so the kernel without the
+        // refill bookkeeping runs the same computation
+        const bool covers = (long long)r->grid * per_block >= G;
+        r->fn = m->fn[layout][covers ? (shared ? 0 : 1) : (shared ? 2 : 3)];
     } else {
         r->fn = m->fn[layout][shared ? 0 : 1];
         r->grid = (unsigned)need_blocks;

@@ -40,6 +40,10 @@ struct cwc_model {
 namespace cwc {
 // Compiles and loads the model's device code for `layout` if needed.
 cwc_status ensure_layout(cwc_model *m, int layout);
+// Directory of the compiled-code cache and the tuning table (created).
+std::string cache_dir_path();
+// Stored tuning for this model and run, if the autotuner recorded one.
+bool tuning_lookup(const cwc_model *m, const cwc_run_desc *d, cwc_tuning *out);
 // Checks a run descriptor; host copies of the rate / initial-state tables.
 cwc_status validate_run(const cwc_model *m, const cwc_run_desc *d, std::vector<double> *rates,
                         std::vector<int> *init);
