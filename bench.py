@@ -185,6 +185,27 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
             "hbm_budget_bytes": st["pool_bytes"], "pool_peak_bytes": st["pool_peak"]}
 
 
+def fnv1a64(text):
+    h = 0xcbf29ce484222325
+    for b in text.encode():
+        h = ((h ^ b) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return "%016x" % h
+
+
+def measured_traffic(source):
+    """HBM bytes per launch of the headline kernel from the committed
+    counter runs (profiles/), only if they were taken on this exact kernel
+    (same generated source); else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_gene_regulation_sweep.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_fnv1a64") != fnv1a64(source):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,10 +215,29 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=150)
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time only the headline kernel (for profiler runs)")
+    ap.add_argument("--tuning", default="", metavar="BLOCK,WAVES_PER_SIMD[,REFILL_CHUNK]",
+                    help="pin the headline launch shape instead of autotuning it")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="copy BYTES device-to-device 5 times and exit (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes_per_launch": args.copy_calibration}))
+        return
+    if args.only_headline:
+        args.no_extra = args.no_serve = args.no_cpu = True
     if args.gpus != 1:
-        print("bench.py: this build simulates on one GPU only; --gpus %d is not supported "
-              "(trajectories shard by id across GPUs, see DESIGN.md)" % args.gpus,
+        print("bench.py: the simulator runs on one GPU; --gpus %d is not supported "
+              "(a multi-GPU run would shard trajectories by id across GPUs)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -212,14 +252,22 @@ def main():
     m2, run2 = W.config(2)
     model2 = Model(ctx, m2)
     alg2 = model2.info["alg_slots_per_event"]
-    t2p = model2.autotune(run2, "persistent", budget_s=3.0)
-    t2q = model2.autotune(run2, "plain", budget_s=1.0)
+    if args.tuning:
+        v = [int(x) for x in args.tuning.split(",")]
+        b, w, ch = v[0], v[1], (v[2] if len(v) > 2 else 0)
+        t2p = {"block_size": b, "waves_per_simd": w, "refill_chunk": ch, "lanes_per_replica": 1}
+        t2q = dict(t2p)
+    else:
+        t2p = model2.autotune(run2, "persistent", budget_s=3.0)
+        t2q = model2.autotune(run2, "plain", budget_s=1.0)
     log("sweep: %s, %.1f algorithmic VALU slots/event; tuned persistent %s plain %s"
         % (model2.info, alg2, t2p, t2q))
     pers = time_form(ctx, model2, run2, "persistent", args.steps, args.warmup, stream, t2p)
     log("sweep persistent", pers)
-    plain = time_form(ctx, model2, run2, "plain", max(1, args.steps // 2), 1, stream, t2q)
-    log("sweep plain", plain)
+    plain = None
+    if not args.only_headline:
+        plain = time_form(ctx, model2, run2, "plain", max(1, args.steps // 2), 1, stream, t2q)
+        log("sweep plain", plain)
 
     # ---- the plain method at GPU scale and the multi-compartment model
     extra = {}
@@ -264,7 +312,8 @@ def main():
 
     achieved = pers["events_per_step"] * alg2 / (pers["kernel_ms"] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
+                "unit": "TOP/s", "frac": achieved / PEAK_VALU_SLOTS,
+                "traffic": measured_traffic(model2.source()),
                 "kernel": "cwc_lane_persistent_table",
                 "work_unit": "%.1f VALU issue slots per applied event" % alg2}
     cpu = None
@@ -284,9 +333,9 @@ def main():
                    "t_end": (run2["n_samples"] - 1) * run2["dt"],
                    "sample_points": run2["n_samples"], "form": "persistent",
                    "events_per_step": pers["events_per_step"], "tuning": t2p},
-        "plain": {"events_per_s": plain["events_per_s"], "ms_per_step": plain["ms_per_step"],
-                  "tuning": t2q,
-                  "persistent_over_plain": pers["events_per_s"] / plain["events_per_s"]},
+        "plain": None if plain is None else {
+            "events_per_s": plain["events_per_s"], "ms_per_step": plain["ms_per_step"],
+            "tuning": t2q, "persistent_over_plain": pers["events_per_s"] / plain["events_per_s"]},
         "other_workloads": extra,
         "serving": serving,
         "roofline": roofline,

@@ -186,7 +186,12 @@ cwc_status cwc_codegen(const cwc_model_desc *d, char *buf, size_t cap,
 typedef struct {
     int32_t block_size;        /* threads per block, multiple of 64; 0 = auto */
     int32_t waves_per_simd;    /* persistent grid: resident waves per SIMD    */
-    int32_t refill_chunk;      /* persistent: items taken per queue refill    */
+    int32_t refill_chunk;      /* persistent, lane layout: 1 = each idle lane
+                                  claims one item from the global queue;
+                                  >= 64 = a wavefront claims this many
+                                  consecutive items at once and its idle lanes
+                                  take them first; 0 = auto (64); 2..63 are
+                                  rejected with CWC_E_INVALID                 */
     int32_t lanes_per_replica; /* 1 (lane layout) or 64 (wave layout); 0 = auto */
 } cwc_tuning;
 

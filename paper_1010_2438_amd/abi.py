@@ -112,6 +112,14 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError("cwcssa library not built: %s missing (run "
                           "__graft_entry__.build() or paper_1010_2438_amd/build.py)" % path)
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 under
+    # the same soname.  Loading torch first makes the library bind to that
+    # copy; loading torch after the library would bring in a second runtime,
+    # and the two then fail to share the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     P, I32, I64, S = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     L.cwc_abi_version.restype = ctypes.c_uint32

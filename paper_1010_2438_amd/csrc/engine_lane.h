@@ -29,28 +29,126 @@
 //
 // Requires engine_common.h (Philox4x32-10, uniforms, ssa_log).
 
-// On-line reduction of one sampled state (paper Sec. 5.2 schema iii): exact
-// 64-bit sums of x and of x^2 (split in 32-bit halves, so no sum wraps for
-// fewer than 2^32 trajectories) per (instance, sample, cell), plus the
-// sample itself if trajectories are kept.  The counts arrive through this
-// lane's column of the wavefront's LDS staging area ([cell][lane]), so the
-// per-cell loop stays rolled and short-lived in registers.
-__device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const i32 *col,
-                                              i64 row, i32 *tr)
+// On-line reduction of sampled states (paper Sec. 5.2 schema iii): exact
+// 64-bit sums of x and of x^2 per (instance, sample, cell); x^2 is split in
+// 32-bit halves so no sum wraps for fewer than 2^32 trajectories.
+//
+// Each wavefront keeps a direct-mapped cache of CWC_NSLOT accumulator rows
+// in LDS, tagged by (instance, sample): a lane that records sample k of
+// instance i adds its counts into slot h(i, k) with LDS atomics when the tag
+// matches; otherwise one lane at a time writes the slot's row back to the
+// global sums (device atomics) and re-tags it.  Rows are written back when
+// the wavefront finishes.  Lanes of one instance record the same samples at
+// nearby times, so a row collects many trajectories before it is written
+// back, cutting global atomics by up to the wavefront width.  h maps the
+// consecutive samples of one instance to consecutive slots and scatters
+// instances over the slots, so lanes of different instances (the persistent
+// form mixes them) rarely evict each other.  All sums are exact integers:
+// the result does not depend on the order.
+#define CWC_NSLOT 16
+
+struct cwc_wave_acc {
+    unsigned long long tag[CWC_NSLOT];        // instance * K1 + sample, ~0 = empty
+    unsigned long long s1[CWC_NSLOT][CWC_C];
+    unsigned long long s2[CWC_NSLOT][CWC_C];  // low 32-bit halves of x^2
+};
+
+__device__ __forceinline__ int cwc_acc_slot(i64 inst, i32 kn)
 {
+    return (int)(((u32)kn + (((u32)inst * 0x9E3779B1u) >> 28)) & (CWC_NSLOT - 1));
+}
+
+// keeps the compiler from moving LDS accesses across this point; the
+// hardware executes one wavefront's LDS instructions in order
+__device__ __forceinline__ void cwc_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void cwc_acc_init(cwc_wave_acc *a)
+{
+    const int lane = __lane_id();
+    for (int i = lane; i < CWC_NSLOT; i += 64) a->tag[i] = ~0ull;
+    for (int i = lane; i < CWC_NSLOT * CWC_C; i += 64) {
+        (&a->s1[0][0])[i] = 0ull;
+        (&a->s2[0][0])[i] = 0ull;
+    }
+    cwc_lds_order();
+}
+
+// write slot `sl` back to the global sums (one lane) and empty it
+__device__ __forceinline__ void cwc_acc_flush_slot(const cwc_kparams &p, cwc_wave_acc *a, int sl)
+{
+    const unsigned long long key = a->tag[sl];
+    if (key == ~0ull) return;
+    const i64 row = (i64)key * (i64)CWC_C;
+    // eight cells at a time: their loads are issued together
+    constexpr int B = CWC_C < 8 ? CWC_C : 8;
 #pragma unroll 1
-    for (int c = 0; c < CWC_C; ++c) {
-        const i32 v = col[c * 64];
-        const u64 x = (u64)(u32)v;
-        const u64 q = x * x;
-        atomicAdd(p.s1 + row + c, x);
-        atomicAdd(p.s2_lo32 + row + c, q & 0xFFFFFFFFull);
-        if (q >> 32) atomicAdd(p.s2_hi32 + row + c, q >> 32);
-        if (tr) tr[c] = v;
+    for (int c0 = 0; c0 < CWC_C; c0 += B) {
+        unsigned long long x[B], q[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const int c = c0 + i < CWC_C ? c0 + i : CWC_C - 1;
+            x[i] = a->s1[sl][c];
+            q[i] = a->s2[sl][c];
+        }
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const int c = c0 + i;
+            if (c < CWC_C) {
+                if (x[i]) atomicAdd(p.s1 + row + c, x[i]);
+                if (q[i]) atomicAdd(p.s2_lo32 + row + c, q[i]);
+                a->s1[sl][c] = 0ull;
+                a->s2[sl][c] = 0ull;
+            }
+        }
+    }
+    a->tag[sl] = ~0ull;
+}
+
+// lanes of the calling (possibly partial) set record their staged state
+__device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, cwc_wave_acc *a,
+                                                 const i32 *col, i64 inst, i32 kn, i32 *tr)
+{
+    const unsigned long long key = (unsigned long long)(inst * (i64)p.K1 + kn);
+    const int sl = cwc_acc_slot(inst, kn);
+    bool pending = true;
+    for (;;) {
+        cwc_lds_order();
+        if (pending && a->tag[sl] == key) {
+#pragma unroll 4
+            for (int c = 0; c < CWC_C; ++c) {
+                const i32 v = col[c * 64];
+                const u64 x = (u64)(u32)v;
+                const u64 q = x * x;
+                atomicAdd(&a->s1[sl][c], x);
+                atomicAdd(&a->s2[sl][c], q & 0xFFFFFFFFull);
+                if (q >> 32) atomicAdd(p.s2_hi32 + key * (u64)CWC_C + c, q >> 32);
+                if (tr) tr[c] = v;
+            }
+            pending = false;
+        }
+        cwc_lds_order();
+        // one lane whose slot holds another row writes it back and claims it
+        const u64 want = __ballot(pending);
+        if (!want) break;
+        const int leader = __ffsll((long long)want) - 1;
+        if (__lane_id() == leader) {
+            cwc_acc_flush_slot(p, a, sl);
+            a->tag[sl] = key;
+        }
     }
 }
 
-// ------------------------------------------------------------- main loop
+__device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, cwc_wave_acc *a)
+{
+    cwc_lds_order();
+    if (__lane_id() == 0) {
+        for (int sl = 0; sl < CWC_NSLOT; ++sl) cwc_acc_flush_slot(p, a, sl);
+    }
+}
 
 // ------------------------------------------------------------- per-lane state
 // The statement macros below operate on the locals declared by
@@ -69,8 +167,14 @@ __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const i32
 
 #define CWC_LANE_LOCALS                                                       \
     const double INF = __longlong_as_double(0x7FF0000000000000ll);            \
-    __shared__ i32 stage[4 * CWC_C * 64];          /* [wave][cell][lane] */    \
-    i32 *const col = stage + (threadIdx.x >> 6) * (CWC_C * 64) + (threadIdx.x & 63); \
+    /* dynamic LDS, per wavefront: staging [cell][lane] i32, then the      \
+       accumulator cache (sized by the host: cwc_lane_lds_bytes) */         \
+    extern __shared__ __align__(16) unsigned char cwc_lds[];                  \
+    const int wv_ = (int)(threadIdx.x >> 6);                                  \
+    i32 *const col = (i32 *)cwc_lds + wv_ * (CWC_C * 64) + (threadIdx.x & 63); \
+    cwc_wave_acc *const acc = (cwc_wave_acc *)(cwc_lds +                      \
+        (blockDim.x >> 6) * (CWC_C * 64 * 4)) + wv_;                          \
+    cwc_acc_init(acc);                                                        \
     CWC_DECL_K;                                                               \
     CWC_DECL_STATE;                                                           \
     double t = 0.0, t_next = 0.0;   /* current time, next sample time */      \
@@ -115,10 +219,9 @@ __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const i32
 // emit sample kn of the current state and move to the next sample time
 #define CWC_EMIT()                                                            \
     do {                                                                      \
-        const i64 row_ = (inst * (i64)p.K1 + kn) * (i64)CWC_C;                \
         i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
         CWC_STAGE(col, 64);                                                   \
-        cwc_emit_moments(p, col, row_, tr_);                                  \
+        cwc_emit_moments(p, acc, col, inst, kn, tr_);                         \
         kn += 1;                                                              \
         t_next = (kn < p.K1) ? (double)kn * p.dt : INF;                       \
     } while (0)
@@ -195,22 +298,47 @@ __device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
     const i64 tid = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     bool active = tid < p.G;
     bool live = active;             // persistent form: may still receive work
+    // persistent form with chunked claims: the wavefront's window of
+    // claimed, not yet started items [w_next, w_end) (wave-uniform)
+    i64 w_next = 0, w_end = 0;
     if (active) CWC_BEGIN(tid);
     for (;;) {
         if (PERSIST) {
-            // lanes whose trajectory ended claim the next unclaimed items,
-            // one atomic per wavefront per refill
+            // lanes whose trajectory ended take the next unclaimed items, in
+            // lane order; at most one queue atomic per wavefront per refill.
+            // With chunked claims they drain the wavefront's window first and
+            // claim a new chunk only when it runs short, so a wavefront works
+            // on few instances at a time and its accumulator rows fill up.
             const u64 want = __ballot(live && !active);
             if (want) {
                 const int cnt = __popcll(want);
                 const int lane = __lane_id();
                 const int leader = __ffsll((long long)want) - 1;
-                u64 base = 0;
-                if (lane == leader) base = atomicAdd(p.cursor, (u64)cnt);
-                base = __shfl(base, leader);
+                const int rank = __popcll(want & ((1ull << lane) - 1ull));
+                i64 item;
+                if (p.chunk <= 1) {
+                    u64 base = 0;
+                    if (lane == leader) base = atomicAdd(p.cursor, (u64)cnt);
+                    base = __shfl(base, leader);
+                    item = (i64)base + rank;
+                } else {
+                    const i64 avail = w_end - w_next;   /* >= 0 */
+                    if (avail >= cnt) {
+                        item = w_next + rank;
+                        w_next += cnt;
+                    } else {
+                        // cnt - avail <= 64 <= chunk: one new chunk suffices
+                        u64 base = 0;
+                        if (lane == leader) base = atomicAdd(p.cursor, (u64)p.chunk);
+                        base = __shfl(base, leader);
+                        const i64 nb = (i64)base;
+                        item = rank < avail ? w_next + rank : nb + (rank - avail);
+                        w_end = nb + p.chunk < p.G ? nb + p.chunk : p.G;
+                        w_next = nb + (cnt - avail);
+                        if (w_next > w_end) w_next = w_end;
+                    }
+                }
                 if (live && !active) {
-                    const u64 below = want & ((1ull << lane) - 1ull);
-                    const i64 item = (i64)(base + (u64)__popcll(below));
                     if (item < p.G) {
                         CWC_BEGIN(item);
                         active = true;
@@ -231,6 +359,7 @@ __device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
             active = false;
         }
     }
+    cwc_acc_flush_all(p, acc);
 #undef CWC_BEGIN
 }
 
@@ -284,6 +413,7 @@ __device__ __forceinline__ void cwc_lane_slice(const cwc_kparams *jobs, const in
             active = false;
         }
     }
+    cwc_acc_flush_all(p, acc);
 }
 
 extern "C" __global__ void __launch_bounds__(256)

@@ -35,6 +35,9 @@ struct cwc_kparams {
     unsigned long long *cursor;   // persistent form: next unclaimed item
     const int *order;             // persistent form: instance claimed by the
                                   // i-th group of R items (null = identity)
+    long long chunk;              // persistent lane form: 1 = lanes claim single
+                                  // items; >= 64 = a wavefront claims `chunk`
+                                  // consecutive items into its own window
     // time-sliced (serving) form: per-trajectory checkpoint and progress
     int *ck_counts;               // [G][C] counts of a suspended trajectory
     double *ck_t;                 // [G]

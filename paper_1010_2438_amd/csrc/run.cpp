@@ -62,7 +62,7 @@ cwc_status enqueue_prologue(cwc_run *r, hipStream_t s)
 cwc_status enqueue_kernel(cwc_run *r, hipStream_t s)
 {
     void *args[] = {&r->kp};
-    HIPCHK(hipModuleLaunchKernel(r->fn, r->grid, 1, 1, r->block, 1, 1, 0, s, args, nullptr));
+    HIPCHK(hipModuleLaunchKernel(r->fn, r->grid, 1, 1, r->block, 1, 1, r->lds, s, args, nullptr));
     return CWC_OK;
 }
 
@@ -250,7 +250,9 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
         return set_err(CWC_E_INVALID, "block_size must be a multiple of 64, at most 256");
     if (tun.waves_per_simd <= 0) tun.waves_per_simd = 2;
     if (tun.waves_per_simd > 16) return set_err(CWC_E_INVALID, "waves_per_simd must be <= 16");
-    if (tun.refill_chunk <= 0) tun.refill_chunk = 1;
+    if (tun.refill_chunk <= 0) tun.refill_chunk = 64;
+    if (tun.refill_chunk > 1 && tun.refill_chunk < 64)
+        return set_err(CWC_E_INVALID, "refill_chunk must be 1 or at least 64");
     int layout = f.layout;
     if (tun.lanes_per_replica == 1) layout = 0;
     else if (tun.lanes_per_replica == 64) layout = 1;
@@ -330,6 +332,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     kp.want_digest = d->want_digest ? 1 : 0;
     kp.rates = d_rates;
     kp.init = d_init;
+    kp.chunk = tun.refill_chunk;
     if (d_order) {
         // Longest-first claim order (the paper's predictive scheduling of
         // instances, Sec. 5.2 schema ii): instances are claimed in
@@ -350,6 +353,10 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     const bool wave = layout == 1;
     if (wave && !tuned && (!d->tuning || d->tuning->block_size <= 0)) tun.block_size = 256;
     r->block = (unsigned)tun.block_size;
+    // the lane layout's per-wavefront LDS (staging + accumulator cache)
+    // grows with the cell count: narrow the block until it fits
+    while (!wave && r->block > 64 && cwc_lane_lds_bytes(C, (int)(r->block / 64)) > ctx->max_lds)
+        r->block /= 2;
     // lane layout: one trajectory per lane; wavefront layout: one per wave
     const long long per_block = wave ? r->block / 64 : r->block;
     const long long need_blocks = (G + per_block - 1) / per_block;
@@ -366,6 +373,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
         r->grid = (unsigned)need_blocks;
     }
     r->n_threads = (unsigned long long)r->grid * (unsigned long long)per_block;
+    r->lds = wave ? 0u : (unsigned)cwc_lane_lds_bytes(C, (int)(r->block / 64));
 
     if (hipEventCreate(&r->ev_start) != hipSuccess || hipEventCreate(&r->ev_sim) != hipSuccess ||
         hipEventCreate(&r->ev_end) != hipSuccess) {

@@ -15,6 +15,7 @@
 struct cwc_ctx {
     int device = 0;
     int n_cu = 0;
+    size_t max_lds = 65536;             // LDS bytes one block may allocate
     std::string arch;
     void *arena = nullptr;
     size_t arena_bytes = 0;
@@ -38,6 +39,14 @@ struct cwc_model {
 };
 
 namespace cwc {
+// Dynamic LDS bytes of a lane-layout launch with `waves` wavefronts per
+// block: per wavefront a [cell][lane] int32 staging area and the
+// accumulator cache of engine_lane.h (16 tags + 16 x C x 2 sums, 64-bit).
+inline size_t cwc_lane_lds_bytes(int n_cells, int waves)
+{
+    const size_t slots = 16;
+    return (size_t)waves * ((size_t)n_cells * 64 * 4 + slots * 8 + 2 * slots * (size_t)n_cells * 8);
+}
 // Compiles and loads the model's device code for `layout` if needed.
 cwc_status ensure_layout(cwc_model *m, int layout);
 // Directory of the compiled-code cache and the tuning table (created).
@@ -58,6 +67,7 @@ struct cwc_run {
     cwc_kparams kp{};
     hipFunction_t fn = nullptr;
     unsigned grid = 0, block = 0;
+    unsigned lds = 0;                   // dynamic LDS bytes per block
     unsigned long long n_threads = 0;
     // device buffers
     std::vector<void *> bufs;

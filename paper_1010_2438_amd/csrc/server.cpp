@@ -301,8 +301,13 @@ bool run_tick(cwc_server *s, std::vector<Job *> &act)
     }
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         Group &g = groups[gi];
-        // four wavefronts per block; pad with entries that start past the end
-        while (g.wave_job.size() % 4) {
+        // up to four wavefronts per block (fewer where the lane layout's
+        // LDS would not fit); pad with entries that start past the end
+        int wpb = 4;
+        while (g.layout == 0 && wpb > 1 &&
+               cwc_lane_lds_bytes(g.m->flat.n_cells, wpb) > s->ctx->max_lds)
+            wpb /= 2;
+        while (g.wave_job.size() % wpb) {
             g.wave_job.push_back(g.wave_job.back());
             g.wave_first.push_back(1ll << 40);
         }
@@ -328,7 +333,10 @@ bool run_tick(cwc_server *s, std::vector<Job *> &act)
         hipFunction_t fn = g.m->fn[g.layout][g.shared_k ? 4 : 5];
         long long budget = s->slice;
         void *args[] = {&s->d_jobs, &s->d_wave_job[si], &s->d_wave_first[si], &budget};
-        SCHK(hipModuleLaunchKernel(fn, (unsigned)(n / 4), 1, 1, 256, 1, 1, 0, st, args, nullptr));
+        const unsigned lds =
+            g.layout == 0 ? (unsigned)cwc_lane_lds_bytes(g.m->flat.n_cells, wpb) : 0u;
+        SCHK(hipModuleLaunchKernel(fn, (unsigned)(n / wpb), 1, 1, 64 * wpb, 1, 1, lds, st, args,
+                                   nullptr));
     }
     // (the host vectors of `groups` outlive every copy: all streams are
     // drained before they go out of scope)

@@ -115,9 +115,9 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
         if (!m->fits[lay]) continue;
         for (int bs : {64, 128, 256}) {
             if (d->mode == CWC_MODE_PERSISTENT) {
-                for (int wps : {1, 2, 4}) cands.push_back(cwc_tuning{bs, wps, 1, lay ? 64 : 1});
+                for (int wps : {1, 2, 4}) cands.push_back(cwc_tuning{bs, wps, 0, lay ? 64 : 1});
             } else {
-                cands.push_back(cwc_tuning{bs, 2, 1, lay ? 64 : 1});
+                cands.push_back(cwc_tuning{bs, 2, 0, lay ? 64 : 1});
             }
         }
     }

@@ -110,6 +110,74 @@ def test_persistent_tuning_invariance(ctx, tuning):
     check(ctx, m, run, modes=("persistent",), tuning=tuning)
 
 
+_refill_oracle = {}
+
+
+def refill_case():
+    """A sweep large enough that the persistent grid must refill (more
+    trajectories than 65536 resident lanes at one wave per SIMD): 2800
+    instances x 37 replicas of A <-> B with instance rates scaled over two
+    decades, so trajectory lengths differ by about 100x."""
+    m = W.isomerisation(k1=1.0, k2=3.0, a0=12, b0=0)
+    tab, _ = W.sweep_rate_table(m, 2800, 5)
+    run = W.make_run(seed=21, n_instances=2800, replicas=37, dt=0.2, n_samples=11,
+                     rate_table=tab)
+    if "o" not in _refill_oracle:
+        _refill_oracle["o"] = oracle.simulate(m, run, want_samples=True, threads=8)
+    return m, run, _refill_oracle["o"]
+
+
+@pytest.mark.parametrize("chunk", [1, 64, 100])
+def test_persistent_refill_chunks(ctx, chunk):
+    """The persistent form's queue refill (lanes claiming single items, or
+    wavefronts claiming chunks that cross instance boundaries) gives results
+    bit-identical to the oracle's, trajectory by trajectory and in the
+    per-instance moments."""
+    m, run, orc = refill_case()
+    print("case refill chunk", chunk, flush=True)
+    g = gpu_run(ctx, model(ctx, m), run, mode="persistent",
+                tuning={"block_size": 64, "waves_per_simd": 1, "refill_chunk": chunk})
+    compare_trajectories(g, orc)
+    compare_stats(g, orc)
+
+
+def test_refill_chunk_validation(ctx):
+    from paper_1010_2438_amd import CwcError
+    m, run = W.config(0)
+    with pytest.raises(CwcError) as e:
+        gpu_run(ctx, model(ctx, m), run, mode="persistent",
+                tuning={"block_size": 64, "waves_per_simd": 1, "refill_chunk": 32})
+    assert e.value.code == -1
+
+
+def test_config2_full_size(ctx):
+    """Configuration 2 at full size (4096 instances x 64 replicas, t_end
+    100, 201 samples) in the benchmark's launch form (persistent, default
+    shape with chunked refill): 16 trajectories spread over the id range
+    match the oracle one by one, and every per-instance moment equals the
+    exact integer sums of the fetched samples."""
+    m, run = W.config(2)
+    I, R, K1 = run["n_instances"], run["replicas"], run["n_samples"]
+    print("case config2 full size", flush=True)
+    g = gpu_run(ctx, model(ctx, m), run, mode="persistent", want_digest=True)
+    assert (g["status"] == 0).all() and (g["n_recorded"] == K1).all()
+    ids = np.linspace(0, I * R - 1, 16).astype(int)
+    for i in ids:
+        o = oracle.simulate(m, run, g0=int(i), g1=int(i) + 1, want_samples=True,
+                            want_stats=False)
+        compare_trajectories(g, o, g_index=[int(i)])
+    S = g["samples"].reshape(I, R, K1, -1)
+    for i0 in range(0, I, 256):
+        blk = S[i0:i0 + 256].astype(np.int64)
+        assert np.array_equal(g["s1"][i0:i0 + 256], blk.sum(axis=1).astype(np.uint64))
+        sq = (blk * blk).sum(axis=1)
+        got = g["s2_hi32"][i0:i0 + 256].astype(np.int64) * 2 ** 32 + \
+            g["s2_lo32"][i0:i0 + 256].astype(np.int64)
+        assert np.array_equal(got, sq)
+    mean = S[:64].astype(np.float64).mean(axis=1)
+    assert np.allclose(g["mean"][:64], mean, rtol=1e-12, atol=0)
+
+
 def test_config1_full_size_sampled(ctx):
     """Configuration 1 at full size (16384 replicas, t_end 100) in the
     launch configuration the benchmark times: 16 trajectories spread over
