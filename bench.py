@@ -20,6 +20,7 @@ one GPU.
 """
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -193,17 +194,19 @@ def fnv1a64(text):
 
 
 def measured_traffic(source):
-    """HBM bytes per launch of the headline kernel from the committed
-    counter runs (profiles/), only if they were taken on this exact kernel
-    (same generated source); else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_gene_regulation_sweep.json")
+    """HBM bytes per launch of the headline kernel from its committed counter
+    summary (profiles/), only if the counters were taken on this exact
+    kernel (same generated source); else None."""
+    path = os.path.join(ROOT, "profiles",
+                        "cwc_lane_persistent_table_gene_regulation_sweep_i4096_r64.md")
     try:
-        rec = json.load(open(path))
-    except (OSError, ValueError):
+        text = open(path).read()
+    except OSError:
         return None
-    if rec.get("source_fnv1a64") != fnv1a64(source):
+    fig = dict(re.findall(r"^(source_fnv1a64|traffic_bytes_per_launch): (\S+)$", text, re.M))
+    if fig.get("source_fnv1a64") != fnv1a64(source) or "traffic_bytes_per_launch" not in fig:
         return None
-    return rec["traffic_bytes_per_launch"]
+    return int(fig["traffic_bytes_per_launch"])
 
 
 def main():
@@ -217,7 +220,7 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=150)
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the headline kernel (for profiler runs)")
-    ap.add_argument("--tuning", default="", metavar="BLOCK,WAVES_PER_SIMD[,REFILL_CHUNK]",
+    ap.add_argument("--tuning", default="", metavar="BLOCK,WAVES_PER_SIMD[,REFILL_CHUNK[,SLOTS]]",
                     help="pin the headline launch shape instead of autotuning it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="copy BYTES device-to-device 5 times and exit (counter calibration)")
@@ -254,8 +257,9 @@ def main():
     alg2 = model2.info["alg_slots_per_event"]
     if args.tuning:
         v = [int(x) for x in args.tuning.split(",")]
-        b, w, ch = v[0], v[1], (v[2] if len(v) > 2 else 0)
-        t2p = {"block_size": b, "waves_per_simd": w, "refill_chunk": ch, "lanes_per_replica": 1}
+        b, w, ch, ns = v[0], v[1], (v[2] if len(v) > 2 else 0), (v[3] if len(v) > 3 else 0)
+        t2p = {"block_size": b, "waves_per_simd": w, "refill_chunk": ch, "lanes_per_replica": 1,
+               "sample_slots": ns}
         t2q = dict(t2p)
     else:
         t2p = model2.autotune(run2, "persistent", budget_s=3.0)

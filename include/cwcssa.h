@@ -193,6 +193,11 @@ typedef struct {
                                   take them first; 0 = auto (64); 2..63 are
                                   rejected with CWC_E_INVALID                 */
     int32_t lanes_per_replica; /* 1 (lane layout) or 64 (wave layout); 0 = auto */
+    int32_t sample_slots;      /* lane layout: sampling-buffer depth, i.e. the
+                                  accumulator rows each wavefront keeps in
+                                  LDS before writing moments back; a power of
+                                  two, at most 64; 0 = auto (16).  Results do
+                                  not depend on it.                           */
 } cwc_tuning;
 
 typedef struct {

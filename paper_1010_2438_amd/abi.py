@@ -74,7 +74,8 @@ class cwc_model_info(ctypes.Structure):
 
 class cwc_tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("block_size", "waves_per_simd", "refill_chunk", "lanes_per_replica")]
+                ("block_size", "waves_per_simd", "refill_chunk", "lanes_per_replica",
+                 "sample_slots")]
 
 
 class cwc_run_desc(ctypes.Structure):

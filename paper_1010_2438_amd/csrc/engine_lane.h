@@ -33,29 +33,27 @@
 // 64-bit sums of x and of x^2 per (instance, sample, cell); x^2 is split in
 // 32-bit halves so no sum wraps for fewer than 2^32 trajectories.
 //
-// Each wavefront keeps a direct-mapped cache of CWC_NSLOT accumulator rows
-// in LDS, tagged by (instance, sample): a lane that records sample k of
-// instance i adds its counts into slot h(i, k) with LDS atomics when the tag
-// matches; otherwise one lane at a time writes the slot's row back to the
-// global sums (device atomics) and re-tags it.  Rows are written back when
-// the wavefront finishes.  Lanes of one instance record the same samples at
-// nearby times, so a row collects many trajectories before it is written
-// back, cutting global atomics by up to the wavefront width.  h maps the
-// consecutive samples of one instance to consecutive slots and scatters
-// instances over the slots, so lanes of different instances (the persistent
-// form mixes them) rarely evict each other.  All sums are exact integers:
-// the result does not depend on the order.
-#define CWC_NSLOT 16
-
-struct cwc_wave_acc {
-    unsigned long long tag[CWC_NSLOT];        // instance * K1 + sample, ~0 = empty
-    unsigned long long s1[CWC_NSLOT][CWC_C];
-    unsigned long long s2[CWC_NSLOT][CWC_C];  // low 32-bit halves of x^2
+// Each wavefront keeps a direct-mapped cache of accumulator rows in LDS
+// (p.nslot rows, a power of two: the sampling-buffer depth), tagged by
+// (instance, sample): a lane that records sample k of instance i adds its
+// counts into slot h(i, k) with LDS atomics when the tag matches; otherwise
+// one lane at a time writes the slot's row back to the global sums (device
+// atomics) and re-tags it.  Rows are written back when the wavefront
+// finishes.  Lanes of one instance record the same samples at nearby
+// times, so a row can collect several trajectories before it is written
+// back.  h maps the consecutive samples of one instance to consecutive
+// slots and scatters instances over the slots.  All sums are exact
+// integers: the result does not depend on the order or on the depth.
+struct cwc_acc {
+    unsigned long long *tag;   // [nslot]  instance * K1 + sample, ~0 = empty
+    unsigned long long *s1;    // [nslot][C]
+    unsigned long long *s2;    // [nslot][C] low 32-bit halves of x^2
+    int mask;                  // nslot - 1
 };
 
-__device__ __forceinline__ int cwc_acc_slot(i64 inst, i32 kn)
+__device__ __forceinline__ int cwc_acc_slot(const cwc_acc &a, i64 inst, i32 kn)
 {
-    return (int)(((u32)kn + (((u32)inst * 0x9E3779B1u) >> 28)) & (CWC_NSLOT - 1));
+    return (int)(((u32)kn + (((u32)inst * 0x9E3779B1u) >> 26)) & (u32)a.mask);
 }
 
 // keeps the compiler from moving LDS accesses across this point; the
@@ -66,23 +64,25 @@ __device__ __forceinline__ void cwc_lds_order()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ void cwc_acc_init(cwc_wave_acc *a)
+__device__ __forceinline__ void cwc_acc_init(const cwc_acc &a)
 {
     const int lane = __lane_id();
-    for (int i = lane; i < CWC_NSLOT; i += 64) a->tag[i] = ~0ull;
-    for (int i = lane; i < CWC_NSLOT * CWC_C; i += 64) {
-        (&a->s1[0][0])[i] = 0ull;
-        (&a->s2[0][0])[i] = 0ull;
+    const int n = a.mask + 1;
+    for (int i = lane; i < n; i += 64) a.tag[i] = ~0ull;
+    for (int i = lane; i < n * CWC_C; i += 64) {
+        a.s1[i] = 0ull;
+        a.s2[i] = 0ull;
     }
     cwc_lds_order();
 }
 
 // write slot `sl` back to the global sums (one lane) and empty it
-__device__ __forceinline__ void cwc_acc_flush_slot(const cwc_kparams &p, cwc_wave_acc *a, int sl)
+__device__ __forceinline__ void cwc_acc_flush_slot(const cwc_kparams &p, const cwc_acc &a, int sl)
 {
-    const unsigned long long key = a->tag[sl];
+    const unsigned long long key = a.tag[sl];
     if (key == ~0ull) return;
     const i64 row = (i64)key * (i64)CWC_C;
+    unsigned long long *r1 = a.s1 + sl * CWC_C, *r2 = a.s2 + sl * CWC_C;
     // eight cells at a time: their loads are issued together
     constexpr int B = CWC_C < 8 ? CWC_C : 8;
 #pragma unroll 1
@@ -91,8 +91,8 @@ __device__ __forceinline__ void cwc_acc_flush_slot(const cwc_kparams &p, cwc_wav
 #pragma unroll
         for (int i = 0; i < B; ++i) {
             const int c = c0 + i < CWC_C ? c0 + i : CWC_C - 1;
-            x[i] = a->s1[sl][c];
-            q[i] = a->s2[sl][c];
+            x[i] = r1[c];
+            q[i] = r2[c];
         }
 #pragma unroll
         for (int i = 0; i < B; ++i) {
@@ -100,31 +100,32 @@ __device__ __forceinline__ void cwc_acc_flush_slot(const cwc_kparams &p, cwc_wav
             if (c < CWC_C) {
                 if (x[i]) atomicAdd(p.s1 + row + c, x[i]);
                 if (q[i]) atomicAdd(p.s2_lo32 + row + c, q[i]);
-                a->s1[sl][c] = 0ull;
-                a->s2[sl][c] = 0ull;
+                r1[c] = 0ull;
+                r2[c] = 0ull;
             }
         }
     }
-    a->tag[sl] = ~0ull;
+    a.tag[sl] = ~0ull;
 }
 
 // lanes of the calling (possibly partial) set record their staged state
-__device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, cwc_wave_acc *a,
+__device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const cwc_acc &a,
                                                  const i32 *col, i64 inst, i32 kn, i32 *tr)
 {
     const unsigned long long key = (unsigned long long)(inst * (i64)p.K1 + kn);
-    const int sl = cwc_acc_slot(inst, kn);
+    const int sl = cwc_acc_slot(a, inst, kn);
+    unsigned long long *r1 = a.s1 + sl * CWC_C, *r2 = a.s2 + sl * CWC_C;
     bool pending = true;
     for (;;) {
         cwc_lds_order();
-        if (pending && a->tag[sl] == key) {
+        if (pending && a.tag[sl] == key) {
 #pragma unroll 4
             for (int c = 0; c < CWC_C; ++c) {
                 const i32 v = col[c * 64];
                 const u64 x = (u64)(u32)v;
                 const u64 q = x * x;
-                atomicAdd(&a->s1[sl][c], x);
-                atomicAdd(&a->s2[sl][c], q & 0xFFFFFFFFull);
+                atomicAdd(r1 + c, x);
+                atomicAdd(r2 + c, q & 0xFFFFFFFFull);
                 if (q >> 32) atomicAdd(p.s2_hi32 + key * (u64)CWC_C + c, q >> 32);
                 if (tr) tr[c] = v;
             }
@@ -137,16 +138,16 @@ __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, cwc_wave_
         const int leader = __ffsll((long long)want) - 1;
         if (__lane_id() == leader) {
             cwc_acc_flush_slot(p, a, sl);
-            a->tag[sl] = key;
+            a.tag[sl] = key;
         }
     }
 }
 
-__device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, cwc_wave_acc *a)
+__device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cwc_acc &a)
 {
     cwc_lds_order();
     if (__lane_id() == 0) {
-        for (int sl = 0; sl < CWC_NSLOT; ++sl) cwc_acc_flush_slot(p, a, sl);
+        for (int sl = 0; sl <= a.mask; ++sl) cwc_acc_flush_slot(p, a, sl);
     }
 }
 
@@ -167,13 +168,22 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, cwc_wave
 
 #define CWC_LANE_LOCALS                                                       \
     const double INF = __longlong_as_double(0x7FF0000000000000ll);            \
-    /* dynamic LDS, per wavefront: staging [cell][lane] i32, then the      \
-       accumulator cache (sized by the host: cwc_lane_lds_bytes) */         \
+    /* dynamic LDS (sized by the host): per wavefront a staging area      \
+       [cell][lane] i32, then per wavefront the accumulator cache: nslot   \
+       tags, then nslot x C sums of x, then nslot x C sums of x^2 (u64) */  \
     extern __shared__ __align__(16) unsigned char cwc_lds[];                  \
     const int wv_ = (int)(threadIdx.x >> 6);                                  \
     i32 *const col = (i32 *)cwc_lds + wv_ * (CWC_C * 64) + (threadIdx.x & 63); \
-    cwc_wave_acc *const acc = (cwc_wave_acc *)(cwc_lds +                      \
-        (blockDim.x >> 6) * (CWC_C * 64 * 4)) + wv_;                          \
+    cwc_acc acc;                                                              \
+    {                                                                         \
+        const int ns_ = p.nslot;                                              \
+        unsigned long long *b_ = (unsigned long long *)(cwc_lds +             \
+            (blockDim.x >> 6) * (CWC_C * 64 * 4)) + wv_ * ns_ * (1 + 2 * CWC_C); \
+        acc.tag = b_;                                                         \
+        acc.s1 = b_ + ns_;                                                    \
+        acc.s2 = b_ + ns_ + ns_ * CWC_C;                                      \
+        acc.mask = ns_ - 1;                                                   \
+    }                                                                         \
     cwc_acc_init(acc);                                                        \
     CWC_DECL_K;                                                               \
     CWC_DECL_STATE;                                                           \

@@ -35,6 +35,8 @@ struct cwc_kparams {
     unsigned long long *cursor;   // persistent form: next unclaimed item
     const int *order;             // persistent form: instance claimed by the
                                   // i-th group of R items (null = identity)
+    int nslot;                    // lane layout: accumulator rows per wavefront
+                                  // (power of two, 1..64)
     long long chunk;              // persistent lane form: 1 = lanes claim single
                                   // items; >= 64 = a wavefront claims `chunk`
                                   // consecutive items into its own window

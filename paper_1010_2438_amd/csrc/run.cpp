@@ -253,6 +253,9 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     if (tun.refill_chunk <= 0) tun.refill_chunk = 64;
     if (tun.refill_chunk > 1 && tun.refill_chunk < 64)
         return set_err(CWC_E_INVALID, "refill_chunk must be 1 or at least 64");
+    if (tun.sample_slots <= 0) tun.sample_slots = kDefaultSampleSlots;
+    if (tun.sample_slots > 64 || (tun.sample_slots & (tun.sample_slots - 1)))
+        return set_err(CWC_E_INVALID, "sample_slots must be a power of two, at most 64");
     int layout = f.layout;
     if (tun.lanes_per_replica == 1) layout = 0;
     else if (tun.lanes_per_replica == 64) layout = 1;
@@ -333,6 +336,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     kp.rates = d_rates;
     kp.init = d_init;
     kp.chunk = tun.refill_chunk;
+    kp.nslot = tun.sample_slots;
     if (d_order) {
         // Longest-first claim order (the paper's predictive scheduling of
         // instances, Sec. 5.2 schema ii): instances are claimed in
@@ -355,8 +359,11 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     r->block = (unsigned)tun.block_size;
     // the lane layout's per-wavefront LDS (staging + accumulator cache)
     // grows with the cell count: narrow the block until it fits
-    while (!wave && r->block > 64 && cwc_lane_lds_bytes(C, (int)(r->block / 64)) > ctx->max_lds)
+    while (!wave && r->block > 64 &&
+           cwc_lane_lds_bytes(C, (int)(r->block / 64), tun.sample_slots) > ctx->max_lds)
         r->block /= 2;
+    if (!wave && cwc_lane_lds_bytes(C, 1, tun.sample_slots) > ctx->max_lds)
+        return set_err(CWC_E_INVALID, "sample_slots too large for this model's cells");
     // lane layout: one trajectory per lane; wavefront layout: one per wave
     const long long per_block = wave ? r->block / 64 : r->block;
     const long long need_blocks = (G + per_block - 1) / per_block;
@@ -373,7 +380,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
         r->grid = (unsigned)need_blocks;
     }
     r->n_threads = (unsigned long long)r->grid * (unsigned long long)per_block;
-    r->lds = wave ? 0u : (unsigned)cwc_lane_lds_bytes(C, (int)(r->block / 64));
+    r->lds = wave ? 0u : (unsigned)cwc_lane_lds_bytes(C, (int)(r->block / 64), tun.sample_slots);
 
     if (hipEventCreate(&r->ev_start) != hipSuccess || hipEventCreate(&r->ev_sim) != hipSuccess ||
         hipEventCreate(&r->ev_end) != hipSuccess) {

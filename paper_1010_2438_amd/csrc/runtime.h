@@ -40,13 +40,15 @@ struct cwc_model {
 
 namespace cwc {
 // Dynamic LDS bytes of a lane-layout launch with `waves` wavefronts per
-// block: per wavefront a [cell][lane] int32 staging area and the
-// accumulator cache of engine_lane.h (16 tags + 16 x C x 2 sums, 64-bit).
-inline size_t cwc_lane_lds_bytes(int n_cells, int waves)
+// block and `nslot` accumulator rows per wavefront: per wavefront a
+// [cell][lane] int32 staging area and the accumulator cache of
+// engine_lane.h (nslot tags + nslot x C x 2 sums, 64-bit).
+inline size_t cwc_lane_lds_bytes(int n_cells, int waves, int nslot)
 {
-    const size_t slots = 16;
-    return (size_t)waves * ((size_t)n_cells * 64 * 4 + slots * 8 + 2 * slots * (size_t)n_cells * 8);
+    return (size_t)waves * ((size_t)n_cells * 64 * 4 + (size_t)nslot * 8 +
+                            2 * (size_t)nslot * (size_t)n_cells * 8);
 }
+constexpr int kDefaultSampleSlots = 16;
 // Compiles and loads the model's device code for `layout` if needed.
 cwc_status ensure_layout(cwc_model *m, int layout);
 // Directory of the compiled-code cache and the tuning table (created).

@@ -249,6 +249,8 @@ bool init_job(cwc_server *s, Job *j, int slot)
     kp.want_traj = 0;
     kp.want_digest = j->d.want_digest ? 1 : 0;
     kp.done_count = s->d_done + slot;
+    kp.nslot = kDefaultSampleSlots;
+    kp.chunk = 1;
     hipStream_t a = s->aux;
     SCHK(hipMemcpyAsync((void *)kp.rates, j->rates.data(), j->rates.size() * 8,
                         hipMemcpyHostToDevice, a));
@@ -305,7 +307,7 @@ bool run_tick(cwc_server *s, std::vector<Job *> &act)
         // LDS would not fit); pad with entries that start past the end
         int wpb = 4;
         while (g.layout == 0 && wpb > 1 &&
-               cwc_lane_lds_bytes(g.m->flat.n_cells, wpb) > s->ctx->max_lds)
+               cwc_lane_lds_bytes(g.m->flat.n_cells, wpb, kDefaultSampleSlots) > s->ctx->max_lds)
             wpb /= 2;
         while (g.wave_job.size() % wpb) {
             g.wave_job.push_back(g.wave_job.back());
@@ -334,7 +336,7 @@ bool run_tick(cwc_server *s, std::vector<Job *> &act)
         long long budget = s->slice;
         void *args[] = {&s->d_jobs, &s->d_wave_job[si], &s->d_wave_first[si], &budget};
         const unsigned lds =
-            g.layout == 0 ? (unsigned)cwc_lane_lds_bytes(g.m->flat.n_cells, wpb) : 0u;
+            g.layout == 0 ? (unsigned)cwc_lane_lds_bytes(g.m->flat.n_cells, wpb, kDefaultSampleSlots) : 0u;
         SCHK(hipModuleLaunchKernel(fn, (unsigned)(n / wpb), 1, 1, 64 * wpb, 1, 1, lds, st, args,
                                    nullptr));
     }

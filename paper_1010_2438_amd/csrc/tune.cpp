@@ -32,7 +32,9 @@ uint64_t hash_str(const std::string &s)
     return h;
 }
 
-std::string table_path() { return cache_dir_path() + "/tuning.txt"; }
+// one line per key: key block waves_per_simd refill_chunk lanes_per_replica
+// sample_slots milliseconds
+std::string table_path() { return cache_dir_path() + "/tuning_v2.txt"; }
 
 std::string tune_key(const cwc_model *m, const cwc_run_desc *d)
 {
@@ -62,7 +64,8 @@ bool tuning_lookup(const cwc_model *m, const cwc_run_desc *d, cwc_tuning *out)
         std::istringstream is(line);
         std::string k;
         cwc_tuning t{};
-        if (!(is >> k >> t.block_size >> t.waves_per_simd >> t.refill_chunk >> t.lanes_per_replica))
+        if (!(is >> k >> t.block_size >> t.waves_per_simd >> t.refill_chunk >> t.lanes_per_replica >>
+              t.sample_slots))
             continue;
         if (k == key) {
             *out = t;                       // the last entry for a key wins
@@ -82,7 +85,7 @@ void tuning_store(const cwc_model *m, const cwc_run_desc *d, const cwc_tuning &t
     std::ofstream f(table_path(), std::ios::app);
     if (!f) return;
     f << tune_key(m, d) << " " << t.block_size << " " << t.waves_per_simd << " " << t.refill_chunk
-      << " " << t.lanes_per_replica << " " << ms << "\n";
+      << " " << t.lanes_per_replica << " " << t.sample_slots << " " << ms << "\n";
 }
 
 // Runs the descriptor once with tuning t; kernel milliseconds or < 0.
@@ -109,18 +112,29 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
 {
     if (!ctx || !m || !d || !out) return set_err(CWC_E_INVALID, "null argument");
     if (!(budget_s > 0)) return set_err(CWC_E_INVALID, "budget_s must be > 0");
+    const bool persistent = d->mode == CWC_MODE_PERSISTENT;
+    const int C = m->flat.n_cells;
+    // stage 1 and 2 candidates: layout x block shape (x resident waves)
     std::vector<cwc_tuning> cands;
-    const int layouts[2] = {0, 1};
-    for (int lay : layouts) {
+    for (int lay : {0, 1}) {
         if (!m->fits[lay]) continue;
         for (int bs : {64, 128, 256}) {
-            if (d->mode == CWC_MODE_PERSISTENT) {
-                for (int wps : {1, 2, 4}) cands.push_back(cwc_tuning{bs, wps, 0, lay ? 64 : 1});
+            if (persistent) {
+                for (int wps : {1, 2, 4}) cands.push_back(cwc_tuning{bs, wps, 0, lay ? 64 : 1, 0});
             } else {
-                cands.push_back(cwc_tuning{bs, 2, 0, lay ? 64 : 1});
+                cands.push_back(cwc_tuning{bs, 2, 0, lay ? 64 : 1, 0});
             }
         }
     }
+    if (cands.empty()) return set_err(CWC_E_UNSUPPORTED, "model fits no layout");
+    // lane layout, stage 3: sampling-buffer depths that fit in LDS
+    std::vector<int> depths;
+    for (int ds : {4, 64})
+        if (cwc_lane_lds_bytes(C, 1, ds) <= ctx->max_lds) depths.push_back(ds);
+    // stage 4 (persistent lane layout): refill chunk
+    const std::vector<int> chunks = {1, 256};
+    const size_t n_trials = cands.size() + depths.size() + (persistent ? chunks.size() : 0);
+
     // probe the default shape on a short horizon to size the trials
     cwc_run_desc probe = *d;
     cwc_status st = CWC_OK;
@@ -129,19 +143,63 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
     double ms = trial(ctx, m, probe, cands[0], &st);
     if (ms < 0) return st;
     const double per_unit = ms / (double)(probe.n_samples - 1);      // per sample interval
-    const double target = 1e3 * budget_s / (double)cands.size();
+    const double target = 1e3 * budget_s / (double)n_trials;
     int k1 = (int)std::floor(target / std::max(per_unit, 1e-6)) + 1;
     k1 = std::max(2, std::min(K1, k1));
     cwc_run_desc td = *d;
     td.n_samples = k1;
+
+    // stage 1: the first shape of each layout; a layout more than 1.5x
+    // slower than the fastest one is not searched further
+    auto layout_of = [](const cwc_tuning &c) { return c.lanes_per_replica == 64 ? 1 : 0; };
+    double lay_ms[2] = {-1.0, -1.0};
+    size_t lay_first[2] = {cands.size(), cands.size()};
+    for (size_t i = 0; i < cands.size(); ++i) {
+        const int lay = layout_of(cands[i]);
+        if (lay_first[lay] != cands.size()) continue;
+        lay_first[lay] = i;
+        lay_ms[lay] = trial(ctx, m, td, cands[i], &st);
+        if (lay_ms[lay] < 0) return st;
+    }
+    double fastest = 1e300;
+    for (int l = 0; l < 2; ++l)
+        if (lay_ms[l] >= 0) fastest = std::min(fastest, lay_ms[l]);
+    // stage 2: every shape of the remaining layouts
     double best = 1e300;
     cwc_tuning bt = cands[0];
-    for (const cwc_tuning &c : cands) {
-        double t = trial(ctx, m, td, c, &st);
-        if (t < 0) return st;
+    auto consider = [&](const cwc_tuning &c, double t) {
         if (t < best) {
             best = t;
             bt = c;
+        }
+    };
+    for (size_t i = 0; i < cands.size(); ++i) {
+        const int lay = layout_of(cands[i]);
+        if (lay_ms[lay] > 1.5 * fastest) continue;
+        double t = i == lay_first[lay] ? lay_ms[lay] : trial(ctx, m, td, cands[i], &st);
+        if (t < 0) return st;
+        consider(cands[i], t);
+    }
+    if (layout_of(bt) == 0) {
+        // stage 3: sampling-buffer depth for the best shape
+        const cwc_tuning shape = bt;
+        for (int ds : depths) {
+            cwc_tuning c = shape;
+            c.sample_slots = ds;
+            double t = trial(ctx, m, td, c, &st);
+            if (t < 0) return st;
+            consider(c, t);
+        }
+        // stage 4: queue refill granularity
+        if (persistent) {
+            const cwc_tuning base = bt;
+            for (int ch : chunks) {
+                cwc_tuning c = base;
+                c.refill_chunk = ch;
+                double t = trial(ctx, m, td, c, &st);
+                if (t < 0) return st;
+                consider(c, t);
+            }
         }
     }
     tuning_store(m, d, bt, best);

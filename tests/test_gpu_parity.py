@@ -141,12 +141,27 @@ def test_persistent_refill_chunks(ctx, chunk):
     compare_stats(g, orc)
 
 
-def test_refill_chunk_validation(ctx):
+@pytest.mark.parametrize("tuning", [{"sample_slots": 1, "refill_chunk": 64},
+                                    {"sample_slots": 64, "refill_chunk": 256, "block_size": 128}])
+def test_sampling_buffer_depth(ctx, tuning):
+    """The accumulator rows kept per wavefront (1: every sample written back
+    at once, up to 64) change nothing in the results."""
+    m, run, orc = refill_case()
+    print("case depth", tuning, flush=True)
+    t = dict({"block_size": 64, "waves_per_simd": 1}, **tuning)
+    g = gpu_run(ctx, model(ctx, m), run, mode="persistent", tuning=t)
+    compare_trajectories(g, orc)
+    compare_stats(g, orc)
+
+
+@pytest.mark.parametrize("bad", [{"refill_chunk": 32}, {"sample_slots": 3},
+                                 {"sample_slots": 128}])
+def test_tuning_validation(ctx, bad):
     from paper_1010_2438_amd import CwcError
     m, run = W.config(0)
     with pytest.raises(CwcError) as e:
         gpu_run(ctx, model(ctx, m), run, mode="persistent",
-                tuning={"block_size": 64, "waves_per_simd": 1, "refill_chunk": 32})
+                tuning=dict({"block_size": 64, "waves_per_simd": 1}, **bad))
     assert e.value.code == -1
 
 
