@@ -400,9 +400,13 @@ std::string codegen_lane(const Flat &f)
     };
     // CWC_APPLY_TRY declares the candidate counts v<c>_ of the event and its
     // overflow flag in the enclosing scope; CWC_COMMIT makes them current.
+    // The digit is taken with a bit-field extract of the mask at position j
+    // (one instruction, no carry through a scalar register).  A rule only
+    // fires with enough reactants, so no count goes below zero and the cap
+    // test over the cells that can grow is one compare of their maximum.
     w.begin("CWC_APPLY_TRY(j, cap, ovf)");
     w.line("const unsigned js_ = (unsigned)(j);");
-    w.line("bool ovf = false;");
+    w.line("unsigned mx_ = 0u;");
     for (int c = 0; c < C; ++c) {
         if (per_cell[c].empty()) continue;
         bool pos = false;
@@ -416,15 +420,25 @@ std::string codegen_lane(const Flat &f)
                 }
                 if (!m) continue;
                 if (sign > 0) pos = true;
-                std::string bit = wide ? "(unsigned)((" + mask_lit(m) + " >> js_) & 1ull)"
-                                       : "((" + mask_lit(m) + " >> js_) & 1u)";
+                std::string bit;
+                if (!wide) {
+                    bit = "__builtin_amdgcn_ubfe(" + mask_lit(m) + ", js_, 1u)";
+                } else {
+                    // 64-bit mask: extract from the half holding bit j
+                    char hi[24], lo[24];
+                    std::snprintf(hi, sizeof hi, "0x%llxu", m >> 32);
+                    std::snprintf(lo, sizeof lo, "0x%llxu", m & 0xffffffffull);
+                    bit = std::string("__builtin_amdgcn_ubfe((js_ & 32u) ? ") + hi + " : " + lo +
+                          ", js_ & 31u, 1u)";
+                }
                 if (b) bit = "(" + bit + " << " + I(b) + ")";
                 e += (sign > 0 ? " + " : " - ") + bit;
             }
         }
         w.line("const unsigned v" + I(c) + "_ = " + e + ";");
-        if (pos) w.line("ovf = ovf || (v" + I(c) + "_ > (cap));");
+        if (pos) w.line("mx_ = mx_ > v" + I(c) + "_ ? mx_ : v" + I(c) + "_;");
     }
+    w.line("const bool ovf = mx_ > (cap);");
     w.end();
     w.begin("CWC_COMMIT()");
     for (int c = 0; c < C; ++c)

@@ -59,6 +59,17 @@ def test_small_models(ctx, name):
     check(ctx, m, run)
 
 
+@pytest.mark.parametrize("which", ["one_cell", "seven_children"])
+def test_lane_layout_wide_trees(ctx, which):
+    """Lane layout at its largest tree (64 leaves: one cell of the
+    multi-compartment model, 24 cells) and a 7-child transport model, both
+    forms, 300 replicas."""
+    m = (W.multi_compartment(3, n_cells_=1) if which == "one_cell"
+         else W.transport(n_children=7))
+    run = W.make_run(seed=5, replicas=300, dt=0.25, n_samples=41)
+    check(ctx, m, run)
+
+
 def test_gene_regulation_ragged(ctx):
     """Configuration 1's model, 333 replicas (not a multiple of the block)."""
     m, run = W.config(1, replicas=333)
