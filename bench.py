@@ -36,10 +36,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None):
+def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None, e2e=False):
     """Warm up, then time exactly `steps` launches bracketed by device
     synchronisation; per-launch simulation time from the library's HIP events
-    on the launch stream."""
+    on the launch stream.  With e2e, also one untimed-for-`value` cycle from
+    host tables to host statistics (submission with table upload, the run,
+    mean/variance/n copied back), wall clock."""
     import torch
     from paper_1010_2438_amd import Run
     r = Run(ctx, model, run, mode=mode, stream=stream, tuning=tuning)
@@ -61,9 +63,20 @@ def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None):
     r.close()
     sim_ms = sum(s[0] for s in sims) / len(sims)
     tot_ms = sum(s[1] for s in sims) / len(sims)
-    return {"events_per_step": events, "ms_per_step": 1e3 * wall / steps,
-            "events_per_s": events * steps / wall, "kernel_ms": sim_ms,
-            "launch_ms": tot_ms, "finite_mean": bool((mean == mean).all())}
+    out = {"events_per_step": events, "ms_per_step": 1e3 * wall / steps,
+           "events_per_s": events * steps / wall, "kernel_ms": sim_ms,
+           "launch_ms": tot_ms, "finite_mean": bool((mean == mean).all())}
+    if e2e:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = Run(ctx, model, run, mode=mode, stream=stream, tuning=tuning)
+        r.wait()
+        mean, var, n = r.stats()
+        wall = time.perf_counter() - t0
+        r.close()
+        out["host_to_host_ms"] = 1e3 * wall
+        out["host_to_host_events_per_s"] = events / wall
+    return out
 
 
 def cpu_baseline(model, run, budget_s=15.0):
@@ -266,7 +279,8 @@ def main():
         t2q = model2.autotune(run2, "plain", budget_s=1.0)
     log("sweep: %s, %.1f algorithmic VALU slots/event; tuned persistent %s plain %s"
         % (model2.info, alg2, t2p, t2q))
-    pers = time_form(ctx, model2, run2, "persistent", args.steps, args.warmup, stream, t2p)
+    pers = time_form(ctx, model2, run2, "persistent", args.steps, args.warmup, stream, t2p,
+                     e2e=True)
     log("sweep persistent", pers)
     plain = None
     if not args.only_headline:
@@ -336,7 +350,9 @@ def main():
                    "trajectories": run2["n_instances"] * run2["replicas"],
                    "t_end": (run2["n_samples"] - 1) * run2["dt"],
                    "sample_points": run2["n_samples"], "form": "persistent",
-                   "events_per_step": pers["events_per_step"], "tuning": t2p},
+                   "events_per_step": pers["events_per_step"], "tuning": t2p,
+                   "host_to_host_events_per_s": pers.get("host_to_host_events_per_s"),
+                   "host_to_host_ms": pers.get("host_to_host_ms")},
         "plain": None if plain is None else {
             "events_per_s": plain["events_per_s"], "ms_per_step": plain["ms_per_step"],
             "tuning": t2q, "persistent_over_plain": pers["events_per_s"] / plain["events_per_s"]},
