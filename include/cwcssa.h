@@ -277,13 +277,16 @@ cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d,
 
 /* Continuous batching (paper Sec. 5.2 schema ii: instances as objects that
  * can be stopped and restarted, time-sliced, scheduled on line).  A server
- * owns a device pool of `hbm_budget` bytes and a scheduler thread that runs
- * ticks: jobs waiting in the queue are admitted (FIFO) when a job slot and
- * pool memory are free; then, for every model with admitted jobs, one
- * launch advances every unfinished trajectory of all those jobs by at most
- * `slice_events` draws, suspending the rest to a device checkpoint.  Jobs
- * therefore join and leave between ticks while others are on the GPU, and
- * their work shares each launch.  A job's trajectories and statistics are
+ * owns a device pool of `hbm_budget` bytes, four device streams and a
+ * scheduler thread: jobs waiting in the queue are admitted (FIFO) when a job
+ * slot and pool memory are free; a stream with no work in flight takes the
+ * ready jobs of one model (oldest first, up to about half the device's
+ * wavefronts) and runs one slice launch that advances every unfinished
+ * trajectory of those jobs by at most `slice_events` draws, suspending the
+ * rest to a device checkpoint; when a slice ends, jobs whose trajectories
+ * have all finished get their statistics finalised, the others become ready
+ * again.  Jobs therefore join and leave while others are on the GPU, and
+ * streams advance independently.  A job's trajectories and statistics are
  * bit-identical to the same run submitted alone (counter-based stream).
  * Job memory stays on the device until cwc_server_release. */
 
@@ -293,7 +296,7 @@ cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d,
 
 typedef struct {
     int32_t state;        /* CWC_JOB_*                                    */
-    int32_t n_ticks;      /* ticks the job took part in                   */
+    int32_t n_ticks;      /* slice launches the job took part in          */
     double t_submit;      /* seconds since server creation                */
     double t_admit;
     double t_done;        /* results ready (statistics finalised)         */
@@ -305,7 +308,7 @@ typedef struct {
     int64_t jobs_submitted, jobs_done, ticks;
     int64_t events;              /* applied events of finished jobs       */
     int64_t pool_bytes, pool_used, pool_peak;
-    double busy_s;               /* wall time spent in ticks              */
+    double busy_s;               /* wall time with a slice in flight      */
 } cwc_server_stats;
 
 /* hbm_budget: device bytes for the pool (from the context's arena or

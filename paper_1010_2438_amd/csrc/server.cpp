@@ -3,18 +3,23 @@
 // The paper's schema ii (Sec. 5.2) makes each simulation instance an object
 // that can be stopped and restarted so that an on-line scheduler can
 // time-slice instances across workers.  Here the scheduler is a host thread
-// and the "workers" are one kernel launch per model per tick:
-//   tick:  admit queued jobs (FIFO) while a job slot and pool memory are
-//          free -> for every (model, layout, rate-table) group of admitted
-//          jobs, one launch advances every unfinished trajectory of those
-//          jobs by at most slice_events draws, suspending the rest to a
-//          device checkpoint -> read the per-job finished counters -> jobs
-//          whose trajectories all finished get their statistics finalised
-//          and leave their slot.
-// Groups are launched on separate streams so different models' slices run
-// concurrently.  A trajectory's events do not depend on how it was sliced
-// or which jobs shared a launch (counter-based random stream), so every job
-// is bit-identical to the same run submitted alone.
+// and the "workers" are four device streams, each running one slice launch
+// at a time:
+//   admit:    queued jobs (FIFO) while a job slot and pool memory are free;
+//   launch:   a stream without work takes the ready jobs of one model group
+//             (model, layout, rate-table use), up to about half a device of
+//             wavefronts, and advances each of their unfinished trajectories
+//             by at most slice_events draws, suspending the rest to a device
+//             checkpoint;
+//   complete: when a stream's slice has finished, its jobs' finished-
+//             trajectory counters are read; jobs whose trajectories have all
+//             finished get their statistics finalised and leave their slot,
+//             the others are ready for another slice.
+// Streams run independently, so a model whose slices are slow does not hold
+// up the others, and the device keeps up to four slices in flight.  A
+// trajectory's events do not depend on how it was sliced or which jobs
+// shared a launch (counter-based random stream), so every job is
+// bit-identical to the same run submitted alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -162,6 +167,9 @@ struct cwc_server {
     int *d_wave_job[kStreams] = {};
     long long *d_wave_first[kStreams] = {};
     size_t wave_cap[kStreams] = {};
+    std::vector<int> h_wave_job[kStreams];         // tables of the slice in flight
+    std::vector<long long> h_wave_first[kStreams];
+    hipEvent_t ev_slice[kStreams] = {};           // end of each stream's slice
 };
 
 namespace {
@@ -268,81 +276,66 @@ bool init_job(cwc_server *s, Job *j, int slot)
     return true;
 }
 
-struct Group {
-    cwc_model *m;
-    int layout;
-    bool shared_k;
-    std::vector<int> wave_job;
-    std::vector<long long> wave_first;
-};
-
-// One tick over the admitted jobs (scheduler thread, mutex not held).
-bool run_tick(cwc_server *s, std::vector<Job *> &act)
+// Launches one slice over `jobs` (all of one model group) on stream `si`
+// (scheduler thread, mutex not held); the stream's table buffers are free
+// because the stream has no work in flight.
+bool launch_slice(cwc_server *s, int si, const std::vector<Job *> &jobs)
 {
-    std::vector<Group> groups;
-    for (Job *j : act) {
-        Group *gp = nullptr;
-        for (auto &g : groups)
-            if (g.m == j->m && g.layout == j->layout && g.shared_k == j->shared_k) gp = &g;
-        if (!gp) {
-            groups.push_back(Group{j->m, j->layout, j->shared_k, {}, {}});
-            gp = &groups.back();
-        }
+    std::vector<int> &wave_job = s->h_wave_job[si];
+    std::vector<long long> &wave_first = s->h_wave_first[si];
+    wave_job.clear();
+    wave_first.clear();
+    const Job *j0 = jobs.front();
+    for (Job *j : jobs) {
         if (j->layout == 0) {
             for (long long f = 0; f < j->G; f += 64) {
-                gp->wave_job.push_back(j->slot);
-                gp->wave_first.push_back(f);
+                wave_job.push_back(j->slot);
+                wave_first.push_back(f);
             }
         } else {
             for (long long f = 0; f < j->G; ++f) {
-                gp->wave_job.push_back(j->slot);
-                gp->wave_first.push_back(f);
+                wave_job.push_back(j->slot);
+                wave_first.push_back(f);
             }
         }
         j->n_ticks += 1;
     }
-    for (size_t gi = 0; gi < groups.size(); ++gi) {
-        Group &g = groups[gi];
-        // up to four wavefronts per block (fewer where the lane layout's
-        // LDS would not fit); pad with entries that start past the end
-        int wpb = 4;
-        while (g.layout == 0 && wpb > 1 &&
-               cwc_lane_lds_bytes(g.m->flat.n_cells, wpb, kDefaultSampleSlots) > s->ctx->max_lds)
-            wpb /= 2;
-        while (g.wave_job.size() % wpb) {
-            g.wave_job.push_back(g.wave_job.back());
-            g.wave_first.push_back(1ll << 40);
-        }
-        const int si = (int)(gi % kStreams);
-        hipStream_t st = s->streams[si];
-        if (gi >= (size_t)kStreams) SCHK(hipStreamSynchronize(st));   // reuse of its buffers
-        const size_t n = g.wave_job.size();
-        if (n > s->wave_cap[si]) {
-            if (s->d_wave_job[si]) {
-                SCHK(hipStreamSynchronize(st));
-                SCHK(hipFree(s->d_wave_job[si]));
-                SCHK(hipFree(s->d_wave_first[si]));
-            }
-            size_t cap = std::max<size_t>(n, 2 * s->wave_cap[si]);
-            SCHK(hipMalloc(&s->d_wave_job[si], cap * sizeof(int)));
-            SCHK(hipMalloc(&s->d_wave_first[si], cap * sizeof(long long)));
-            s->wave_cap[si] = cap;
-        }
-        SCHK(hipMemcpyAsync(s->d_wave_job[si], g.wave_job.data(), n * sizeof(int),
-                            hipMemcpyHostToDevice, st));
-        SCHK(hipMemcpyAsync(s->d_wave_first[si], g.wave_first.data(), n * sizeof(long long),
-                            hipMemcpyHostToDevice, st));
-        hipFunction_t fn = g.m->fn[g.layout][g.shared_k ? 4 : 5];
-        long long budget = s->slice;
-        void *args[] = {&s->d_jobs, &s->d_wave_job[si], &s->d_wave_first[si], &budget};
-        const unsigned lds =
-            g.layout == 0 ? (unsigned)cwc_lane_lds_bytes(g.m->flat.n_cells, wpb, kDefaultSampleSlots) : 0u;
-        SCHK(hipModuleLaunchKernel(fn, (unsigned)(n / wpb), 1, 1, 64 * wpb, 1, 1, lds, st, args,
-                                   nullptr));
+    // up to four wavefronts per block (fewer where the lane layout's LDS
+    // would not fit); pad with entries that start past the end
+    int wpb = 4;
+    while (j0->layout == 0 && wpb > 1 &&
+           cwc_lane_lds_bytes(j0->m->flat.n_cells, wpb, kDefaultSampleSlots) > s->ctx->max_lds)
+        wpb /= 2;
+    while (wave_job.size() % wpb) {
+        wave_job.push_back(wave_job.back());
+        wave_first.push_back(1ll << 40);
     }
-    // (the host vectors of `groups` outlive every copy: all streams are
-    // drained before they go out of scope)
-    for (int i = 0; i < kStreams; ++i) SCHK(hipStreamSynchronize(s->streams[i]));
+    hipStream_t st = s->streams[si];
+    const size_t n = wave_job.size();
+    if (n > s->wave_cap[si]) {
+        if (s->d_wave_job[si]) {
+            SCHK(hipFree(s->d_wave_job[si]));
+            SCHK(hipFree(s->d_wave_first[si]));
+        }
+        size_t cap = std::max<size_t>(n, 2 * s->wave_cap[si]);
+        SCHK(hipMalloc(&s->d_wave_job[si], cap * sizeof(int)));
+        SCHK(hipMalloc(&s->d_wave_first[si], cap * sizeof(long long)));
+        s->wave_cap[si] = cap;
+    }
+    // the host vectors stay untouched until this stream's slice completes
+    SCHK(hipMemcpyAsync(s->d_wave_job[si], wave_job.data(), n * sizeof(int),
+                        hipMemcpyHostToDevice, st));
+    SCHK(hipMemcpyAsync(s->d_wave_first[si], wave_first.data(), n * sizeof(long long),
+                        hipMemcpyHostToDevice, st));
+    hipFunction_t fn = j0->m->fn[j0->layout][j0->shared_k ? 4 : 5];
+    long long budget = s->slice;
+    void *args[] = {&s->d_jobs, &s->d_wave_job[si], &s->d_wave_first[si], &budget};
+    const unsigned lds =
+        j0->layout == 0 ? (unsigned)cwc_lane_lds_bytes(j0->m->flat.n_cells, wpb, kDefaultSampleSlots)
+                        : 0u;
+    SCHK(hipModuleLaunchKernel(fn, (unsigned)(n / wpb), 1, 1, 64 * wpb, 1, 1, lds, st, args,
+                               nullptr));
+    SCHK(hipEventRecord(s->ev_slice[si], st));
     return true;
 }
 
@@ -361,6 +354,10 @@ bool finish_job(cwc_server *s, Job *j)
     return true;
 }
 
+// Wavefronts one slice launch may cover: about half the device at two
+// wavefronts per SIMD, so one model's jobs can occupy several streams.
+long long slice_wave_cap(const cwc_server *s) { return (long long)s->ctx->n_cu * 4; }
+
 void scheduler(cwc_server *s)
 {
     if (hipSetDevice(s->ctx->device) != hipSuccess) {
@@ -370,80 +367,145 @@ void scheduler(cwc_server *s)
     }
     std::vector<unsigned long long> done(s->max_active);
     std::vector<Job *> admitted;
+    std::vector<Job *> inflight[kStreams];       // jobs of each stream's slice
+    std::vector<Job *> ready;                    // admitted, not in a slice
+    bool ok = true;
+    bool stopping = false;
+    double t_last = now_s(s->t0);
     for (;;) {
-        std::vector<Job *> act;
+        bool busy = false;
+        for (int i = 0; i < kStreams; ++i) busy = busy || !inflight[i].empty();
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
-            if (s->stop) return;
-            if (!s->error.empty()) {
-                s->idle_cv.notify_all();
-                s->cv.wait(lk, [&] { return s->stop; });
-                return;
-            }
-            // admission: FIFO, while a slot and pool memory are free
-            while (!s->queue.empty() && !s->free_slots.empty()) {
-                Job *j = s->jobs[s->queue.front()].get();
-                if (!reserve(s, j)) break;
-                j->slot = s->free_slots.back();
-                s->free_slots.pop_back();
-                s->queue.pop_front();
-                admitted.push_back(j);
+            const double t = now_s(s->t0);
+            if (busy) s->stats.busy_s += t - t_last;
+            t_last = t;
+            if (!busy)
+                s->cv.wait(lk, [&] { return s->stop || !s->queue.empty() || !ready.empty(); });
+            t_last = now_s(s->t0);
+            stopping = s->stop;
+            if (stopping && !busy) return;
+            if (stopping) {
+                // drain the slices in flight, start nothing new
+            } else if (!s->error.empty() || !ok) {
+                if (!busy) {
+                    s->idle_cv.notify_all();
+                    s->cv.wait(lk, [&] { return s->stop; });
+                    return;
+                }
+            } else {
+                // admission: FIFO, while a slot and pool memory are free
+                while (!s->queue.empty() && !s->free_slots.empty()) {
+                    Job *j = s->jobs[s->queue.front()].get();
+                    if (!reserve(s, j)) break;
+                    j->slot = s->free_slots.back();
+                    s->free_slots.pop_back();
+                    s->queue.pop_front();
+                    admitted.push_back(j);
+                }
             }
         }
-        bool ok = true;
         for (Job *j : admitted)
             if (ok) ok = init_job(s, j, j->slot);
-        {
+        if (!admitted.empty()) {
             std::lock_guard<std::mutex> lk(s->mu);
             for (Job *j : admitted) {
                 j->state = CWC_JOB_ACTIVE;
                 j->t_admit = now_s(s->t0);
                 s->active.push_back(j);
+                ready.push_back(j);
             }
             admitted.clear();
-            if (!ok) continue;
-            act = s->active;
         }
-        if (act.empty()) {
-            // nothing admissible yet (pool held by finished, unreleased
-            // jobs): sleep until a submit or release
-            std::unique_lock<std::mutex> lk(s->mu);
-            s->cv.wait_for(lk, std::chrono::milliseconds(20));
-            continue;
-        }
-        const double tb = now_s(s->t0);
-        ok = run_tick(s, act);
-        if (ok && hipMemcpy(done.data(), s->d_done, s->max_active * 8, hipMemcpyDeviceToHost) !=
-                      hipSuccess) {
-            std::lock_guard<std::mutex> lk(s->mu);
-            fail_locked(s, "reading job progress failed");
-            ok = false;
-        }
+        // completions
         std::vector<Job *> finished;
-        if (ok)
-            for (Job *j : act)
+        bool progressed = false;
+        for (int i = 0; ok && i < kStreams; ++i) {
+            if (inflight[i].empty()) continue;
+            const hipError_t q = hipEventQuery(s->ev_slice[i]);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess ||
+                hipMemcpyAsync(done.data(), s->d_done, s->max_active * 8, hipMemcpyDeviceToHost,
+                               s->aux) != hipSuccess ||
+                hipStreamSynchronize(s->aux) != hipSuccess) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                fail_locked(s, "a slice launch failed");
+                ok = false;
+                break;
+            }
+            progressed = true;
+            for (Job *j : inflight[i]) {
                 if ((long long)done[j->slot] == j->G) {
                     if (!finish_job(s, j)) {
                         ok = false;
                         break;
                     }
                     finished.push_back(j);
+                } else {
+                    ready.push_back(j);
                 }
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stats.ticks += 1;
-        s->stats.busy_s += now_s(s->t0) - tb;
-        for (Job *j : finished) {
-            j->state = CWC_JOB_DONE;
-            j->t_done = now_s(s->t0);
-            s->free_slots.push_back(j->slot);
-            s->active.erase(std::find(s->active.begin(), s->active.end(), j));
-            s->unreported.push_back(j->id);
-            s->stats.jobs_done += 1;
-            s->stats.events += j->events;
+            }
+            inflight[i].clear();
         }
-        if (s->queue.empty() && s->active.empty()) s->idle_cv.notify_all();
-        if (!ok) s->idle_cv.notify_all();
+        if (!finished.empty()) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (Job *j : finished) {
+                j->state = CWC_JOB_DONE;
+                j->t_done = now_s(s->t0);
+                s->free_slots.push_back(j->slot);
+                s->active.erase(std::find(s->active.begin(), s->active.end(), j));
+                s->unreported.push_back(j->id);
+                s->stats.jobs_done += 1;
+                s->stats.events += j->events;
+            }
+        }
+        // launches: an idle stream takes the oldest ready job's group
+        for (int i = 0; ok && !stopping && i < kStreams && !ready.empty(); ++i) {
+            if (!inflight[i].empty()) continue;
+            const Job *lead = ready.front();
+            std::vector<Job *> take_jobs, rest;
+            long long waves = 0;
+            for (Job *j : ready) {
+                const bool same = j->m == lead->m && j->layout == lead->layout &&
+                                  j->shared_k == lead->shared_k;
+                const long long w = j->layout == 0 ? (j->G + 63) / 64 : j->G;
+                if (same && (take_jobs.empty() || waves + w <= slice_wave_cap(s))) {
+                    take_jobs.push_back(j);
+                    waves += w;
+                } else {
+                    rest.push_back(j);
+                }
+            }
+            ready.swap(rest);
+            if (!launch_slice(s, i, take_jobs)) {
+                ok = false;
+                break;
+            }
+            inflight[i] = take_jobs;
+            progressed = true;
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stats.ticks += 1;
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (!ok) fail_locked(s, "scheduler stopped after a device error");
+            bool any = false;
+            for (int i = 0; i < kStreams; ++i) any = any || !inflight[i].empty();
+            if (s->queue.empty() && s->active.empty() && !any) s->idle_cv.notify_all();
+            if (!ok) s->idle_cv.notify_all();
+        }
+        if (!progressed) {
+            // slices in flight and none finished: poll again shortly; nothing
+            // in flight and nothing admissible (the pool is held by finished,
+            // unreleased jobs): sleep until a submission or release
+            bool any = false;
+            for (int i = 0; i < kStreams; ++i) any = any || !inflight[i].empty();
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (any)
+                s->cv.wait_for(lk, std::chrono::microseconds(200));
+            else
+                s->cv.wait_for(lk, std::chrono::milliseconds(20));
+        }
     }
 }
 
@@ -496,7 +558,8 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
               hipMalloc(&s->d_done, 8 * max_active) == hipSuccess &&
               hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < kStreams; ++i)
-        ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess;
+        ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&s->ev_slice[i], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         ctx->release(s->pool_mem);
         return set_err(CWC_E_DEVICE, "server device setup failed");
@@ -677,6 +740,7 @@ void cwc_server_destroy(cwc_server *s)
         }
         if (s->d_wave_job[i]) (void)hipFree(s->d_wave_job[i]);
         if (s->d_wave_first[i]) (void)hipFree(s->d_wave_first[i]);
+        if (s->ev_slice[i]) (void)hipEventDestroy(s->ev_slice[i]);
     }
     if (s->aux) (void)hipStreamDestroy(s->aux);
     if (s->d_jobs) (void)hipFree(s->d_jobs);
