@@ -206,12 +206,12 @@ def fnv1a64(text):
     return "%016x" % h
 
 
-def measured_traffic(source):
+def measured_traffic(source, kernel):
     """HBM bytes per launch of the headline kernel from its committed counter
-    summary (profiles/), only if the counters were taken on this exact
-    kernel (same generated source); else None."""
-    path = os.path.join(ROOT, "profiles",
-                        "cwc_lane_persistent_table_gene_regulation_sweep_i4096_r64.md")
+    summary (profiles/<kernel>_gene_regulation_sweep_i4096_r64.md), only if
+    the counters were taken on this exact kernel (same generated source);
+    else None."""
+    path = os.path.join(ROOT, "profiles", "%s_gene_regulation_sweep_i4096_r64.md" % kernel)
     try:
         text = open(path).read()
     except OSError:
@@ -220,6 +220,14 @@ def measured_traffic(source):
     if fig.get("source_fnv1a64") != fnv1a64(source) or "traffic_bytes_per_launch" not in fig:
         return None
     return int(fig["traffic_bytes_per_launch"])
+
+
+def kernel_name(tuning, mode):
+    """The simulation kernel a run with this tuning dispatches (the lane
+    layout's module also holds the pair kernels)."""
+    lpr = (tuning or {}).get("lanes_per_replica", 1)
+    fam = {2: "cwc_pair", 64: "cwc_wave"}.get(lpr, "cwc_lane")
+    return "%s_%s_table" % (fam, mode)
 
 
 def main():
@@ -233,7 +241,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=150)
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the headline kernel (for profiler runs)")
-    ap.add_argument("--tuning", default="", metavar="BLOCK,WAVES_PER_SIMD[,REFILL_CHUNK[,SLOTS]]",
+    ap.add_argument("--tuning", default="",
+                    metavar="BLOCK,WAVES_PER_SIMD[,REFILL_CHUNK[,SLOTS[,LANES_PER_REPLICA]]]",
                     help="pin the headline launch shape instead of autotuning it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="copy BYTES device-to-device 5 times and exit (counter calibration)")
@@ -271,7 +280,8 @@ def main():
     if args.tuning:
         v = [int(x) for x in args.tuning.split(",")]
         b, w, ch, ns = v[0], v[1], (v[2] if len(v) > 2 else 0), (v[3] if len(v) > 3 else 0)
-        t2p = {"block_size": b, "waves_per_simd": w, "refill_chunk": ch, "lanes_per_replica": 1,
+        lpr = v[4] if len(v) > 4 else 1
+        t2p = {"block_size": b, "waves_per_simd": w, "refill_chunk": ch, "lanes_per_replica": lpr,
                "sample_slots": ns}
         t2q = dict(t2p)
     else:
@@ -331,8 +341,8 @@ def main():
     achieved = pers["events_per_step"] * alg2 / (pers["kernel_ms"] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_VALU_SLOTS,
-                "traffic": measured_traffic(model2.source()),
-                "kernel": "cwc_lane_persistent_table",
+                "traffic": measured_traffic(model2.source(), kernel_name(t2p, "persistent")),
+                "kernel": kernel_name(t2p, "persistent"),
                 "work_unit": "%.1f VALU issue slots per applied event" % alg2}
     cpu = None
     if not args.no_cpu:

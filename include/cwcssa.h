@@ -192,7 +192,10 @@ typedef struct {
                                   consecutive items at once and its idle lanes
                                   take them first; 0 = auto (64); 2..63 are
                                   rejected with CWC_E_INVALID                 */
-    int32_t lanes_per_replica; /* 1 (lane layout) or 64 (wave layout); 0 = auto */
+    int32_t lanes_per_replica; /* 1 (lane layout), 2 (pair: two lanes per
+                                  trajectory, each holding half of the
+                                  propensity tree; models with >= 2 leaves)
+                                  or 64 (wave layout); 0 = auto            */
     int32_t sample_slots;      /* lane layout: sampling-buffer depth, i.e. the
                                   accumulator rows each wavefront keeps in
                                   LDS before writing moments back; a power of

@@ -440,3 +440,220 @@ cwc_lane_slice_shared(const cwc_kparams *jobs, const int *wave_job, const long l
 extern "C" __global__ void __launch_bounds__(256)
 cwc_lane_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
                      long long budget) { cwc_lane_slice<false>(jobs, wave_job, wave_first, budget); }
+
+#ifdef CWC_PAIR
+// ------------------------------------------------------------ pair layout
+// Two lanes per trajectory (lane bit h): lane h holds half h of the
+// propensity tree (leaves [h*B, (h+1)*B)), both hold the counts.  Per event:
+// each lane builds its half; the root is its half plus the partner's (one
+// DPP swap; the sum is the same in both lanes); both take the root decision,
+// then each descends its own half and the lane holding the chosen half
+// supplies the leaf index; both apply the change.  The draws are shared:
+// on even iterations of the wavefront lane 1 computes the draw of the next
+// event and lane 0 the one after, so Philox and ssa_log run every other
+// iteration; the event of an even iteration uses lane 0's draw, of an odd
+// one lane 1's.  Every pair of a wavefront follows this parity, so the draw
+// code is wavefront-uniform.  Results are those of the lane layout bit for
+// bit: the same tree, the same descent, the same draws per event.
+
+// partner lane's value (lane ^ 1: DPP quad permutation 1,0,3,2)
+__device__ __forceinline__ int cwc_pair_swap_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double cwc_pair_swap(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = cwc_pair_swap_i((int)b);
+    const int hi = cwc_pair_swap_i((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <bool PERSIST, bool SHARED_K>
+__device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
+{
+    CWC_LANE_LOCALS;
+    CWC_PAIR_DECL;
+    const int h_ = (int)(__lane_id() & 1u);
+    if (SHARED_K) { CWC_PAIR_LOAD_K(p.rates, h_); }
+    u32 it = 0;                     // wavefront iteration (parity: whose draw)
+
+    // begin the trajectory of item `item` at the current iteration: the lane
+    // whose draw the next event uses takes draw 0; at an odd iteration lane 0
+    // also needs draw 1 (the even iteration after computes draws 2 and 3)
+#define CWC_PBEGIN(item)                                                      \
+    do {                                                                      \
+        i64 lg0_ = (item);                                                    \
+        if (PERSIST && p.order) {                                             \
+            const u32 grp_ = (u32)(item) / (u32)p.R;                          \
+            const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
+            lg0_ = (i64)p.order[grp_] * p.R + rep_;                           \
+        }                                                                     \
+        lg = lg0_;                                                            \
+        inst = (i64)((u32)lg / (u32)p.R);                                     \
+        g = p.g_base + lg;                                                    \
+        if (!SHARED_K) {                                                      \
+            const double *kr_ = p.rates + (i64)p.rate_stride * inst;          \
+            CWC_PAIR_LOAD_K(kr_, h_);                                         \
+        }                                                                     \
+        { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
+          CWC_LOAD_COUNTS(ini_); }                                            \
+        t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
+        dig = 0xcbf29ce484222325ull;                                          \
+        { const u64 d0_ = (it & 1u) ? (u64)(1 - h_) : 0ull;                   \
+          CWC_DRAW(d0_, E, U); }                                              \
+    } while (0)
+
+    // sample kn of the current state (lane 0 of the pair records it)
+#define CWC_PEMIT()                                                           \
+    do {                                                                      \
+        if (h_ == 0) {                                                        \
+            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+            CWC_STAGE(col, 64);                                               \
+            cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
+        }                                                                     \
+        kn += 1;                                                              \
+        t_next = (kn < p.K1) ? (double)kn * p.dt : INF;                       \
+    } while (0)
+
+#define CWC_PSTEP(st, EVEN)                                                   \
+    do {                                                                      \
+        CWC_PAIR_TREE(h_);                                                    \
+        const double s_ = CWC_PAIR_HALF;                                      \
+        const double o_ = cwc_pair_swap(s_);                                  \
+        const double a0_ = s_ + o_;                                           \
+        const double Eo_ = cwc_pair_swap(E), Uo_ = cwc_pair_swap(U);          \
+        const bool mine_ = h_ == ((EVEN) ? 0 : 1);                            \
+        const double Ec_ = mine_ ? E : Eo_;                                   \
+        const double Uc_ = mine_ ? U : Uo_;                                   \
+        const double tn_ = t + Ec_ / a0_;                                     \
+        double x_ = Uc_ * a0_;                                                \
+        const double L0_ = h_ ? o_ : s_;                                      \
+        const double R0_ = h_ ? s_ : o_;                                      \
+        const bool b0_ = (x_ >= L0_) && (R0_ != 0.0);                         \
+        x_ = b0_ ? x_ - L0_ : x_;                                             \
+        int jl_ = 0;                                                          \
+        CWC_PAIR_DESCEND(x_, jl_);                                            \
+        const int jo_ = cwc_pair_swap_i(jl_);                                 \
+        const i32 j_ = (b0_ ? CWC_PB : 0) + ((h_ == (b0_ ? 1 : 0)) ? jl_ : jo_); \
+        CWC_APPLY_TRY(j_, p.cap, ovf_);                                       \
+        double E1_ = E, U1_ = U;                                              \
+        if (EVEN) {                                                           \
+            const u64 d1_ = e + 2ull - (u64)h_;                               \
+            CWC_DRAW(d1_, E1_, U1_);                                          \
+        }                                                                     \
+        const bool slow_ = (a0_ == 0.0) | (t_next < tn_) | ovf_ |             \
+                           (e + 1 == (u64)p.max_events);                      \
+        if (!slow_) {                                                         \
+            CWC_COMMIT();                                                     \
+            t = tn_; e = e + 1; E = E1_; U = U1_;                             \
+            if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
+        } else if (a0_ == 0.0) {                                              \
+            while (kn < p.K1) CWC_PEMIT();                                    \
+            (st) = CWC_ST_ABSORBED;                                           \
+        } else {                                                              \
+            while (t_next < tn_) CWC_PEMIT();                                 \
+            if (kn >= p.K1) {                                                 \
+                (st) = CWC_ST_OK;                                             \
+            } else if (ovf_) {                                                \
+                (st) = CWC_ST_OVERFLOW;                                       \
+            } else {                                                          \
+                CWC_COMMIT();                                                 \
+                t = tn_; e = e + 1; E = E1_; U = U1_;                         \
+                if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
+                if (e == (u64)p.max_events) (st) = CWC_ST_EVENT_CAP;          \
+            }                                                                 \
+        }                                                                     \
+    } while (0)
+
+    const i64 tid = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const i64 pid = tid >> 1;
+    bool active = pid < p.G;
+    bool live = active;
+    i64 w_next = 0, w_end = 0;      // chunked claims: the wavefront's window
+    if (active) CWC_PBEGIN(pid);
+
+    // persistent form: pairs whose trajectory ended take the next items
+#define CWC_PREFILL                                                           \
+    if (PERSIST) {                                                            \
+        const u64 want = __ballot(live && !active);                           \
+        if (want) {                                                           \
+            const u64 evens = want & 0x5555555555555555ull;                   \
+            const int cnt = __popcll(evens);                                  \
+            const int lane = __lane_id();                                     \
+            const int leader = __ffsll((long long)want) - 1;                  \
+            const int rank = __popcll(evens & ((1ull << (lane & ~1)) - 1ull)); \
+            i64 item;                                                         \
+            if (p.chunk <= 1) {                                               \
+                u64 base = 0;                                                 \
+                if (lane == leader) base = atomicAdd(p.cursor, (u64)cnt);     \
+                base = __shfl(base, leader);                                  \
+                item = (i64)base + rank;                                      \
+            } else {                                                          \
+                const i64 avail = w_end - w_next;                             \
+                if (avail >= cnt) {                                           \
+                    item = w_next + rank;                                     \
+                    w_next += cnt;                                            \
+                } else {                                                      \
+                    u64 base = 0;                                             \
+                    if (lane == leader) base = atomicAdd(p.cursor, (u64)p.chunk); \
+                    base = __shfl(base, leader);                              \
+                    const i64 nb = (i64)base;                                 \
+                    item = rank < avail ? w_next + rank : nb + (rank - avail); \
+                    w_end = nb + p.chunk < p.G ? nb + p.chunk : p.G;          \
+                    w_next = nb + (cnt - avail);                              \
+                    if (w_next > w_end) w_next = w_end;                       \
+                }                                                             \
+            }                                                                 \
+            if (live && !active) {                                            \
+                if (item < p.G) {                                             \
+                    CWC_PBEGIN(item);                                         \
+                    active = true;                                            \
+                } else {                                                      \
+                    live = false;                                             \
+                }                                                             \
+            }                                                                 \
+        }                                                                     \
+        if (!__any(live)) break;                                              \
+    } else {                                                                  \
+        if (!__any(active)) break;                                            \
+    }
+
+    for (;;) {
+        CWC_PREFILL
+        if (active) {
+            int st = CWC_ST_RUNNING;
+            CWC_PSTEP(st, true);
+            if (st != CWC_ST_RUNNING) {
+                if (h_ == 0) CWC_FINISH(st);
+                active = false;
+            }
+        }
+        it += 1u;
+        CWC_PREFILL
+        if (active) {
+            int st = CWC_ST_RUNNING;
+            CWC_PSTEP(st, false);
+            if (st != CWC_ST_RUNNING) {
+                if (h_ == 0) CWC_FINISH(st);
+                active = false;
+            }
+        }
+        it += 1u;
+    }
+    cwc_acc_flush_all(p, acc);
+#undef CWC_PREFILL
+#undef CWC_PSTEP
+#undef CWC_PEMIT
+#undef CWC_PBEGIN
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+cwc_pair_plain_shared(cwc_kparams p) { cwc_pair_main<false, true>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_pair_plain_table(cwc_kparams p) { cwc_pair_main<false, false>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_pair_persistent_shared(cwc_kparams p) { cwc_pair_main<true, true>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_pair_persistent_table(cwc_kparams p) { cwc_pair_main<true, false>(p); }
+#endif  // CWC_PAIR

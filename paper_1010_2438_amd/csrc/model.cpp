@@ -449,6 +449,122 @@ std::string codegen_lane(const Flat &f)
     w.begin("CWC_STAGE(ptr, stride)");
     for (int c = 0; c < C; ++c) w.line("(ptr)[" + I(c) + " * (stride)] = n" + I(c) + ";");
     w.end();
+
+    // --- pair layout: two lanes per trajectory.  Lane h (0 or 1) of a pair
+    // holds leaves [h*B, (h+1)*B) of the same canonical tree (B = P/2): the
+    // root is its half plus the partner's, the root decision is taken by
+    // both lanes, the rest of the descent by the lane holding the chosen
+    // half.  Leaf position i of a lane is the left slot i or the right slot
+    // B + i: its factors are selected by h, and it is formed with the same
+    // operations as the lane layout's leaf (k * h with h = product of the
+    // binomial factors), so the tree has the same bits; an empty side has
+    // rate 0 and gives +0, which leaves every sum unchanged.
+    if (P >= 2) {
+        const int B = P / 2;
+        int DB = 0;
+        while ((1 << DB) < B) ++DB;
+        o << "#define CWC_PAIR 1\n#define CWC_PB " << B << "\n";
+        std::vector<char> hz(2 * B, 1);
+        for (int i = 0; i < B; ++i) hz[B + i] = (f.leaf_slot[i] < 0) && (f.leaf_slot[B + i] < 0);
+        for (int i = B - 1; i >= 1; --i) hz[i] = hz[2 * i] && hz[2 * i + 1];
+        auto hv = [&](int i) -> std::string { return hz[i] ? std::string("0.0") : "q" + I(i); };
+        w.begin("CWC_PAIR_DECL");
+        for (int i = 0; i < B; ++i)
+            if (!hz[B + i]) w.line("double K" + I(i) + " = 0.0;");
+        for (int i = 1; i < 2 * B; ++i)
+            if (!hz[i]) w.line("double q" + I(i) + " = 0.0;");
+        w.end();
+        // per-lane rates of the lane's leaf positions from a rate row
+        w.begin("CWC_PAIR_LOAD_K(ptr, h)");
+        for (int i = 0; i < B; ++i) {
+            if (hz[B + i]) continue;
+            const int sl = f.leaf_slot[i], sr = f.leaf_slot[B + i];
+            const std::string Ls = sl < 0 ? "0.0" : "(ptr)[" + I(f.slots[sl].rule) + "]";
+            const std::string Rs = sr < 0 ? "0.0" : "(ptr)[" + I(f.slots[sr].rule) + "]";
+            w.line("K" + I(i) + " = (h) ? " + Rs + " : " + Ls + ";");
+        }
+        w.end();
+        // binomial factors of a slot: (F1, F2) with h = F1 * F2
+        auto factors = [&](int si) -> std::pair<std::string, std::string> {
+            if (si < 0) return {"1.0", "1.0"};
+            const Slot &sl = f.slots[si];
+            if (sl.n_react == 1 && sl.react_mult[0] == 1) return {"c" + I(sl.react_cell[0]) + "_", "1.0"};
+            if (sl.n_react == 1 && sl.react_mult[0] == 2) {
+                const int c = sl.react_cell[0];
+                return {"(c" + I(c) + "_ * m" + I(c) + "_)", "0.5"};
+            }
+            if (sl.n_react == 2) return {"c" + I(sl.react_cell[0]) + "_", "c" + I(sl.react_cell[1]) + "_"};
+            return {"1.0", "1.0"};
+        };
+        w.begin("CWC_PAIR_TREE(h)");
+        w.line("{");
+        for (int c = 0; c < C; ++c) {
+            if (need_c[c]) w.line("const double c" + I(c) + "_ = (double)n" + I(c) + ";");
+            if (need_d[c])
+                w.line("const double m" + I(c) + "_ = (double)(n" + I(c) + " > 0 ? n" + I(c) + " - 1 : 0);");
+        }
+        for (int i = 0; i < B; ++i) {
+            if (hz[B + i]) continue;
+            auto L = factors(f.leaf_slot[i]), R = factors(f.leaf_slot[B + i]);
+            const std::string F1 = L.first == R.first ? L.first : "((h) ? " + R.first + " : " + L.first + ")";
+            const std::string F2 = L.second == R.second ? L.second : "((h) ? " + R.second + " : " + L.second + ")";
+            std::string H;
+            if (F2 == "1.0") H = F1;
+            else H = "(" + F1 + " * " + F2 + ")";
+            w.line("q" + I(B + i) + " = " + (H == "1.0" ? "K" + I(i) : "K" + I(i) + " * " + H) + ";");
+        }
+        for (int i = B - 1; i >= 1; --i) {
+            if (hz[i]) continue;
+            if (!hz[2 * i] && !hz[2 * i + 1]) w.line("q" + I(i) + " = q" + I(2 * i) + " + q" + I(2 * i + 1) + ";");
+            else if (!hz[2 * i]) w.line("q" + I(i) + " = q" + I(2 * i) + ";");
+            else w.line("q" + I(i) + " = q" + I(2 * i + 1) + ";");
+        }
+        w.line("}");
+        w.end();
+        o << "#define CWC_PAIR_HALF " << hv(1) << "\n";
+        // descent inside the lane's half (same narrowing as CWC_DESCEND)
+        w.begin("CWC_PAIR_DESCEND(x, j)");
+        w.line("{");
+        w.line("int jj_ = 0;");
+        std::vector<std::string> hbits;
+        int htmp = 0;
+        for (int d = 0; d < DB; ++d) {
+            std::vector<std::string> vals;
+            for (int m = 0; m < (2 << d); ++m) vals.push_back(hv((2 << d) + m));
+            for (int q = 0; q < d; ++q) {
+                const size_t half = vals.size() / 2;
+                std::vector<std::string> nv(half);
+                for (size_t m = 0; m < half; ++m) {
+                    const std::string &A = vals[m + half], &Bv = vals[m];
+                    if (hbits[q].empty() || A == Bv) {
+                        nv[m] = Bv;
+                    } else {
+                        const std::string t = "u" + I(htmp++) + "_";
+                        w.line("const double " + t + " = " + hbits[q] + " ? " + A + " : " + Bv + ";");
+                        nv[m] = t;
+                    }
+                }
+                vals = nv;
+            }
+            const std::string Lv = vals[0], Rv = vals[1];
+            if (Rv == "0.0") {
+                w.line("jj_ = jj_ << 1;");
+                hbits.push_back("");
+                continue;
+            }
+            const std::string b = "e" + I(d) + "_";
+            if (Lv == "0.0")
+                w.line("const bool " + b + " = (" + Rv + " != 0.0);");
+            else
+                w.line("const bool " + b + " = ((x) >= " + Lv + ") && (" + Rv + " != 0.0);");
+            if (Lv != "0.0") w.line("(x) = " + b + " ? (x) - " + Lv + " : (x);");
+            w.line("jj_ = (jj_ << 1) | (" + b + " ? 1 : 0);");
+            hbits.push_back(b);
+        }
+        w.line("(j) = jj_;");
+        w.line("}");
+        w.end();
+    }
     return o.str();
 }
 

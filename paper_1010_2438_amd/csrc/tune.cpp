@@ -115,14 +115,21 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
     const bool persistent = d->mode == CWC_MODE_PERSISTENT;
     const int C = m->flat.n_cells;
     // stage 1 and 2 candidates: layout x block shape (x resident waves)
+    // lanes per trajectory: 1 and (two or more leaves) 2 in the lane
+    // layout's module, 64 in the wavefront layout
+    std::vector<int> lprs;
+    if (m->fits[0]) {
+        lprs.push_back(1);
+        if (m->flat.n_leaves >= 2) lprs.push_back(2);
+    }
+    if (m->fits[1]) lprs.push_back(64);
     std::vector<cwc_tuning> cands;
-    for (int lay : {0, 1}) {
-        if (!m->fits[lay]) continue;
+    for (int lpr : lprs) {
         for (int bs : {64, 128, 256}) {
             if (persistent) {
-                for (int wps : {1, 2, 4}) cands.push_back(cwc_tuning{bs, wps, 0, lay ? 64 : 1, 0});
+                for (int wps : {1, 2, 4}) cands.push_back(cwc_tuning{bs, wps, 0, lpr, 0});
             } else {
-                cands.push_back(cwc_tuning{bs, 2, 0, lay ? 64 : 1, 0});
+                cands.push_back(cwc_tuning{bs, 2, 0, lpr, 0});
             }
         }
     }
@@ -149,11 +156,14 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
     cwc_run_desc td = *d;
     td.n_samples = k1;
 
-    // stage 1: the first shape of each layout; a layout more than 1.5x
-    // slower than the fastest one is not searched further
-    auto layout_of = [](const cwc_tuning &c) { return c.lanes_per_replica == 64 ? 1 : 0; };
-    double lay_ms[2] = {-1.0, -1.0};
-    size_t lay_first[2] = {cands.size(), cands.size()};
+    // stage 1: the first shape of each layout (lanes per trajectory); a
+    // layout more than 1.5x slower than the fastest one is not searched
+    // further
+    auto layout_of = [](const cwc_tuning &c) {
+        return c.lanes_per_replica == 64 ? 2 : (c.lanes_per_replica == 2 ? 1 : 0);
+    };
+    double lay_ms[3] = {-1.0, -1.0, -1.0};
+    size_t lay_first[3] = {cands.size(), cands.size(), cands.size()};
     for (size_t i = 0; i < cands.size(); ++i) {
         const int lay = layout_of(cands[i]);
         if (lay_first[lay] != cands.size()) continue;
@@ -162,7 +172,7 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
         if (lay_ms[lay] < 0) return st;
     }
     double fastest = 1e300;
-    for (int l = 0; l < 2; ++l)
+    for (int l = 0; l < 3; ++l)
         if (lay_ms[l] >= 0) fastest = std::min(fastest, lay_ms[l]);
     // stage 2: every shape of the remaining layouts
     double best = 1e300;
@@ -180,7 +190,7 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
         if (t < 0) return st;
         consider(cands[i], t);
     }
-    if (layout_of(bt) == 0) {
+    if (layout_of(bt) != 2) {
         // stage 3: sampling-buffer depth for the best shape
         const cwc_tuning shape = bt;
         for (int ds : depths) {

@@ -226,6 +226,55 @@ def test_config1_full_size_sampled(ctx):
     assert np.allclose(g["mean"][0], mean, rtol=1e-12, atol=0)
 
 
+# ---------------------------------------------------------------- pair layout
+
+PAIR = {"lanes_per_replica": 2, "block_size": 64, "waves_per_simd": 1}
+
+
+@pytest.mark.parametrize("name", ["birth_death", "isomerisation", "transport",
+                                  "receptor_binding", "lotka_volterra"])
+def test_pair_layout_small_models(ctx, name):
+    """Two lanes per trajectory: bit-identical to the oracle in both forms."""
+    m = getattr(W, name)()
+    run = W.make_run(seed=7, replicas=300, dt=0.25, n_samples=41)
+    check(ctx, m, run, tuning=PAIR)
+
+
+def test_pair_layout_needs_two_leaves(ctx):
+    from paper_1010_2438_amd import CwcError
+    with pytest.raises(CwcError) as e:
+        gpu_run(ctx, model(ctx, W.dimerisation()), W.make_run(replicas=8, n_samples=3),
+                tuning=PAIR)
+    assert e.value.code == -2
+
+
+def test_pair_layout_gene_regulation_and_wide_tree(ctx):
+    m, run = W.config(1, replicas=333)
+    check(ctx, m, dict(run, n_samples=41), tuning=PAIR)
+    check(ctx, W.multi_compartment(3, n_cells_=1),
+          W.make_run(seed=5, replicas=300, dt=0.25, n_samples=41), tuning=PAIR)
+
+
+def test_pair_layout_statuses(ctx):
+    m, run = W.config(0, replicas=70)
+    check(ctx, m, dict(run, max_events=20000), tuning=PAIR)
+    check(ctx, m, dict(run, count_cap=1010), tuning=PAIR)
+    # absorbing: two species that only decay
+    decay2 = W._single("decay2", ["A", "B"], [W._local(0, {0: 1}, {}, 2.0),
+                                              W._local(0, {1: 1}, {}, 1.0)], [5, 3])
+    check(ctx, decay2, W.make_run(replicas=65, dt=0.5, n_samples=30), tuning=PAIR)
+
+
+@pytest.mark.parametrize("chunk", [1, 64])
+def test_pair_layout_refill(ctx, chunk):
+    """Pairs claiming queue items (more trajectories than resident pairs)."""
+    m, run, orc = refill_case()
+    g = gpu_run(ctx, model(ctx, m), run, mode="persistent",
+                tuning=dict(PAIR, refill_chunk=chunk))
+    compare_trajectories(g, orc)
+    compare_stats(g, orc)
+
+
 # ---------------------------------------------------------------- wave layout
 
 def test_config3_multicompartment(ctx):
