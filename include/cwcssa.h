@@ -228,7 +228,8 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m,
                           cwc_run **out);
 /* Re-enqueues the same run (same inputs, same buffers; results are
  * overwritten with identical values).  In persistent mode the launch
- * sequence is replayed from a captured HIP graph. */
+ * sequence is replayed from a captured HIP graph.  On another stream the
+ * relaunch first waits for the previous launch to end. */
 cwc_status cwc_run_relaunch(cwc_run *r, void *hip_stream);
 cwc_status cwc_run_query(cwc_run *r, int *done);
 cwc_status cwc_run_wait(cwc_run *r);

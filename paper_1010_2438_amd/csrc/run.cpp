@@ -98,6 +98,9 @@ cwc_status capture_graph(cwc_run *r)
 cwc_status launch(cwc_run *r, hipStream_t s)
 {
     HIPCHK(hipSetDevice(r->ctx->device));
+    // a relaunch on another stream must not overlap the previous launch,
+    // which uses the same buffers
+    if (r->launched) HIPCHK(hipStreamWaitEvent(s, r->ev_end, 0));
     if (r->mode == CWC_MODE_PERSISTENT) {
         HIPCHK(hipEventRecord(r->ev_start, s));
         HIPCHK(hipGraphLaunch(r->graph, s));
