@@ -469,54 +469,11 @@ __device__ __forceinline__ double cwc_pair_swap(double v)
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-template <bool PERSIST, bool SHARED_K>
-__device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
-{
-    CWC_LANE_LOCALS;
-    CWC_PAIR_DECL;
-    const int h_ = (int)(__lane_id() & 1u);
-    if (SHARED_K) { CWC_PAIR_LOAD_K(p.rates, h_); }
-    u32 it = 0;                     // wavefront iteration (parity: whose draw)
-
-    // begin the trajectory of item `item` at the current iteration: the lane
-    // whose draw the next event uses takes draw 0; at an odd iteration lane 0
-    // also needs draw 1 (the even iteration after computes draws 2 and 3)
-#define CWC_PBEGIN(item)                                                      \
-    do {                                                                      \
-        i64 lg0_ = (item);                                                    \
-        if (PERSIST && p.order) {                                             \
-            const u32 grp_ = (u32)(item) / (u32)p.R;                          \
-            const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
-            lg0_ = (i64)p.order[grp_] * p.R + rep_;                           \
-        }                                                                     \
-        lg = lg0_;                                                            \
-        inst = (i64)((u32)lg / (u32)p.R);                                     \
-        g = p.g_base + lg;                                                    \
-        if (!SHARED_K) {                                                      \
-            const double *kr_ = p.rates + (i64)p.rate_stride * inst;          \
-            CWC_PAIR_LOAD_K(kr_, h_);                                         \
-        }                                                                     \
-        { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
-          CWC_LOAD_COUNTS(ini_); }                                            \
-        t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
-        dig = 0xcbf29ce484222325ull;                                          \
-        { const u64 d0_ = (it & 1u) ? (u64)(1 - h_) : 0ull;                   \
-          CWC_DRAW(d0_, E, U); }                                              \
-    } while (0)
-
-    // sample kn of the current state (lane 0 of the pair records it)
-#define CWC_PEMIT()                                                           \
-    do {                                                                      \
-        if (h_ == 0) {                                                        \
-            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
-            CWC_STAGE(col, 64);                                               \
-            cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
-        }                                                                     \
-        kn += 1;                                                              \
-        t_next = (kn < p.K1) ? (double)kn * p.dt : INF;                       \
-    } while (0)
-
-#define CWC_PSTEP(st, EVEN)                                                   \
+// One step of a pair (the locals of the pair kernels, CWC_PEMIT and h_ in
+// scope): the event of this iteration (its draw: lane 0's at an even
+// iteration, lane 1's at an odd one) and, at an even iteration, each lane's
+// next draw (lane 1: e+1, lane 0: e+2).
+#define CWC_PAIR_STEP_BODY(st, EVEN)                                                   \
     do {                                                                      \
         CWC_PAIR_TREE(h_);                                                    \
         const double s_ = CWC_PAIR_HALF;                                      \
@@ -564,6 +521,53 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
                 if (e == (u64)p.max_events) (st) = CWC_ST_EVENT_CAP;          \
             }                                                                 \
         }                                                                     \
+    } while (0)
+
+template <bool PERSIST, bool SHARED_K>
+__device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
+{
+    CWC_LANE_LOCALS;
+    CWC_PAIR_DECL;
+    const int h_ = (int)(__lane_id() & 1u);
+    if (SHARED_K) { CWC_PAIR_LOAD_K(p.rates, h_); }
+    u32 it = 0;                     // wavefront iteration (parity: whose draw)
+
+    // begin the trajectory of item `item` at the current iteration: the lane
+    // whose draw the next event uses takes draw 0; at an odd iteration lane 0
+    // also needs draw 1 (the even iteration after computes draws 2 and 3)
+#define CWC_PBEGIN(item)                                                      \
+    do {                                                                      \
+        i64 lg0_ = (item);                                                    \
+        if (PERSIST && p.order) {                                             \
+            const u32 grp_ = (u32)(item) / (u32)p.R;                          \
+            const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
+            lg0_ = (i64)p.order[grp_] * p.R + rep_;                           \
+        }                                                                     \
+        lg = lg0_;                                                            \
+        inst = (i64)((u32)lg / (u32)p.R);                                     \
+        g = p.g_base + lg;                                                    \
+        if (!SHARED_K) {                                                      \
+            const double *kr_ = p.rates + (i64)p.rate_stride * inst;          \
+            CWC_PAIR_LOAD_K(kr_, h_);                                         \
+        }                                                                     \
+        { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
+          CWC_LOAD_COUNTS(ini_); }                                            \
+        t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
+        dig = 0xcbf29ce484222325ull;                                          \
+        { const u64 d0_ = (it & 1u) ? (u64)(1 - h_) : 0ull;                   \
+          CWC_DRAW(d0_, E, U); }                                              \
+    } while (0)
+
+    // sample kn of the current state (lane 0 of the pair records it)
+#define CWC_PEMIT()                                                           \
+    do {                                                                      \
+        if (h_ == 0) {                                                        \
+            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+            CWC_STAGE(col, 64);                                               \
+            cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
+        }                                                                     \
+        kn += 1;                                                              \
+        t_next = (kn < p.K1) ? (double)kn * p.dt : INF;                       \
     } while (0)
 
     const i64 tid = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -623,7 +627,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
         CWC_PREFILL
         if (active) {
             int st = CWC_ST_RUNNING;
-            CWC_PSTEP(st, true);
+            CWC_PAIR_STEP_BODY(st, true);
             if (st != CWC_ST_RUNNING) {
                 if (h_ == 0) CWC_FINISH(st);
                 active = false;
@@ -633,7 +637,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
         CWC_PREFILL
         if (active) {
             int st = CWC_ST_RUNNING;
-            CWC_PSTEP(st, false);
+            CWC_PAIR_STEP_BODY(st, false);
             if (st != CWC_ST_RUNNING) {
                 if (h_ == 0) CWC_FINISH(st);
                 active = false;
@@ -643,9 +647,101 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
     }
     cwc_acc_flush_all(p, acc);
 #undef CWC_PREFILL
-#undef CWC_PSTEP
 #undef CWC_PEMIT
 #undef CWC_PBEGIN
+}
+
+// Time-sliced pair form (serving): wavefront w works on job wave_job[w],
+// trajectories wave_first[w] + lane / 2; each pair resumes from its
+// checkpoint (or starts), runs at most `budget` draws, then finishes or is
+// suspended.  The slice starts at an even iteration, so lane 0 takes the
+// draw of the current event and lane 1 receives the next one from the
+// first even iteration's pair of draws.
+template <bool SHARED_K>
+__device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const int *wave_job,
+                                               const long long *wave_first, long long budget)
+{
+    const int w = (int)((blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6);
+    const cwc_kparams &p = jobs[wave_job[w]];
+    CWC_LANE_LOCALS;
+    CWC_PAIR_DECL;
+    const int h_ = (int)(__lane_id() & 1u);
+    if (SHARED_K) { CWC_PAIR_LOAD_K(p.rates, h_); }
+    const i64 my = wave_first[w] + (i64)((threadIdx.x & 63) >> 1);
+    bool active = my < p.G && p.ck_state[my] != 2;
+    if (active) {
+        lg = my;
+        inst = (i64)((u32)lg / (u32)p.R);
+        g = p.g_base + lg;
+        if (!SHARED_K) {
+            const double *kr_ = p.rates + (i64)p.rate_stride * inst;
+            CWC_PAIR_LOAD_K(kr_, h_);
+        }
+        if (p.ck_state[my] == 0) {
+            { const i32 *ini_ = p.init + (i64)p.init_stride * inst; CWC_LOAD_COUNTS(ini_); }
+            t = 0.0; t_next = 0.0; e = 0; kn = 0;
+            dig = 0xcbf29ce484222325ull;
+        } else {
+            { const i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_LOAD_COUNTS(ck_); }
+            t = p.ck_t[lg];
+            e = p.ck_e[lg];
+            dig = p.ck_dig[lg];
+            kn = p.ck_kn[lg];
+            t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
+        }
+        CWC_DRAW(e, E, U);
+    }
+    long long n = 0;
+#define CWC_PEMIT()                                                           \
+    do {                                                                      \
+        if (h_ == 0) {                                                        \
+            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+            CWC_STAGE(col, 64);                                               \
+            cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
+        }                                                                     \
+        kn += 1;                                                              \
+        t_next = (kn < p.K1) ? (double)kn * p.dt : INF;                       \
+    } while (0)
+    // after a step: finish, or suspend once the slice's draws are used
+#define CWC_PSLICE_AFTER(st)                                                  \
+    do {                                                                      \
+        if ((st) != CWC_ST_RUNNING) {                                         \
+            if (h_ == 0) {                                                    \
+                CWC_FINISH(st);                                               \
+                p.ck_state[lg] = 2;                                           \
+                atomicAdd(p.done_count, 1ull);                                \
+            }                                                                 \
+            active = false;                                                   \
+        } else if (n == budget) {                                             \
+            if (h_ == 0) {                                                    \
+                { i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(ck_); } \
+                p.ck_t[lg] = t;                                               \
+                p.ck_e[lg] = e;                                               \
+                p.ck_dig[lg] = dig;                                           \
+                p.ck_kn[lg] = kn;                                             \
+                p.ck_state[lg] = 1;                                           \
+            }                                                                 \
+            active = false;                                                   \
+        }                                                                     \
+    } while (0)
+    while (__any(active)) {
+        if (active) {
+            int st = CWC_ST_RUNNING;
+            ++n;
+            CWC_PAIR_STEP_BODY(st, true);
+            CWC_PSLICE_AFTER(st);
+        }
+        if (!__any(active)) break;
+        if (active) {
+            int st = CWC_ST_RUNNING;
+            ++n;
+            CWC_PAIR_STEP_BODY(st, false);
+            CWC_PSLICE_AFTER(st);
+        }
+    }
+#undef CWC_PSLICE_AFTER
+#undef CWC_PEMIT
+    cwc_acc_flush_all(p, acc);
 }
 
 extern "C" __global__ void __launch_bounds__(256)
@@ -656,4 +752,10 @@ extern "C" __global__ void __launch_bounds__(256)
 cwc_pair_persistent_shared(cwc_kparams p) { cwc_pair_main<true, true>(p); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_pair_persistent_table(cwc_kparams p) { cwc_pair_main<true, false>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_pair_slice_shared(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
+                      long long budget) { cwc_pair_slice<true>(jobs, wave_job, wave_first, budget); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_pair_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
+                     long long budget) { cwc_pair_slice<false>(jobs, wave_job, wave_first, budget); }
 #endif  // CWC_PAIR

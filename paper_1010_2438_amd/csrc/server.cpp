@@ -42,6 +42,8 @@ using namespace cwc;
 namespace {
 
 constexpr int kStreams = 4;
+// launches of at most this many trajectories use two lanes per trajectory
+constexpr long long kPairSliceMax = 32768;
 
 // First-fit sub-allocator over the server's device pool.
 struct Pool {
@@ -286,9 +288,15 @@ bool launch_slice(cwc_server *s, int si, const std::vector<Job *> &jobs)
     wave_job.clear();
     wave_first.clear();
     const Job *j0 = jobs.front();
+    // a lane-layout launch that leaves most lanes idle runs two lanes per
+    // trajectory (shorter per-trajectory latency), when the model has them
+    long long traj = 0;
+    for (Job *j : jobs) traj += j->G;
+    const bool pair = j0->layout == 0 && j0->m->pair_fn[4] && traj <= kPairSliceMax;
+    const long long per_wave = pair ? 32 : 64;
     for (Job *j : jobs) {
         if (j->layout == 0) {
-            for (long long f = 0; f < j->G; f += 64) {
+            for (long long f = 0; f < j->G; f += per_wave) {
                 wave_job.push_back(j->slot);
                 wave_first.push_back(f);
             }
@@ -327,7 +335,8 @@ bool launch_slice(cwc_server *s, int si, const std::vector<Job *> &jobs)
                         hipMemcpyHostToDevice, st));
     SCHK(hipMemcpyAsync(s->d_wave_first[si], wave_first.data(), n * sizeof(long long),
                         hipMemcpyHostToDevice, st));
-    hipFunction_t fn = j0->m->fn[j0->layout][j0->shared_k ? 4 : 5];
+    hipFunction_t fn = pair ? j0->m->pair_fn[j0->shared_k ? 4 : 5]
+                            : j0->m->fn[j0->layout][j0->shared_k ? 4 : 5];
     long long budget = s->slice;
     void *args[] = {&s->d_jobs, &s->d_wave_job[si], &s->d_wave_first[si], &budget};
     const unsigned lds =
