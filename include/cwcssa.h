@@ -233,6 +233,11 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m,
 cwc_status cwc_run_relaunch(cwc_run *r, void *hip_stream);
 cwc_status cwc_run_query(cwc_run *r, int *done);
 cwc_status cwc_run_wait(cwc_run *r);
+/* Waits at most `timeout_s` seconds (a host-side watchdog): CWC_OK once
+ * the launch has ended, CWC_E_NOTREADY if it is still running (it keeps
+ * running; wait again or destroy the run after it ends), CWC_E_DEVICE if
+ * it failed. */
+cwc_status cwc_run_wait_for(cwc_run *r, double timeout_s);
 /* Device time of the last launch of the simulation kernel (HIP events on
  * the run's stream), and of the whole launch sequence. */
 cwc_status cwc_run_elapsed(cwc_run *r, float *sim_ms, float *total_ms);

@@ -27,7 +27,7 @@ SYMBOLS = [
     "cwc_abi_version", "cwc_last_error", "cwc_ctx_create", "cwc_ctx_destroy",
     "cwc_model_create", "cwc_model_get_info", "cwc_model_source",
     "cwc_model_destroy", "cwc_model_describe", "cwc_codegen", "cwc_run_submit", "cwc_run_relaunch",
-    "cwc_run_query", "cwc_run_wait", "cwc_run_elapsed", "cwc_run_fetch_stats",
+    "cwc_run_query", "cwc_run_wait", "cwc_run_wait_for", "cwc_run_elapsed", "cwc_run_fetch_stats",
     "cwc_run_fetch_moments", "cwc_run_fetch_trajectories",
     "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_server_create",
     "cwc_server_submit", "cwc_server_poll", "cwc_server_job_info",
@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH):
         "cwc_run_relaunch": [P, P],
         "cwc_run_query": [P, ctypes.POINTER(ctypes.c_int)],
         "cwc_run_wait": [P],
+        "cwc_run_wait_for": [P, ctypes.c_double],
         "cwc_run_elapsed": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
         "cwc_run_fetch_stats": [P, P, P, P, ctypes.c_int],
         "cwc_run_fetch_moments": [P, P, P, P, P, ctypes.c_int],
@@ -358,6 +359,15 @@ class Run:
 
     def wait(self):
         check(load().cwc_run_wait(self.h))
+
+    def wait_for(self, timeout_s: float) -> bool:
+        """cwc_run_wait_for: True once the launch has ended, False if it is
+        still running after timeout_s seconds."""
+        code = load().cwc_run_wait_for(self.h, float(timeout_s))
+        if code == -5:
+            return False
+        check(code)
+        return True
         return self
 
     def elapsed_ms(self):

@@ -2,6 +2,8 @@
 // simulation kernel -> contributor counts -> mean/variance), HIP-graph
 // capture of the persistent form, completion and result fetches.
 #include <hip/hip_runtime.h>
+#include <thread>
+#include <chrono>
 
 #include <algorithm>
 #include <cmath>
@@ -436,6 +438,24 @@ cwc_status cwc_run_wait(cwc_run *r)
     if (!r->launched) return set_err(CWC_E_NOTREADY, "run not launched");
     HIPCHK(hipEventSynchronize(r->ev_end));
     return ready(r);
+}
+
+cwc_status cwc_run_wait_for(cwc_run *r, double timeout_s)
+{
+    if (!r) return set_err(CWC_E_INVALID, "null run");
+    if (!r->launched) return set_err(CWC_E_NOTREADY, "run not launched");
+    if (!(timeout_s >= 0)) return set_err(CWC_E_INVALID, "timeout_s must be >= 0");
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipEventQuery(r->ev_end);
+        if (e == hipSuccess) return ready(r);
+        if (e != hipErrorNotReady)
+            return set_err(CWC_E_DEVICE, "run failed: %s", hipGetErrorString(e));
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (el >= timeout_s)
+            return set_err(CWC_E_NOTREADY, "run still in flight after %.3f s", timeout_s);
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
 }
 
 cwc_status cwc_run_elapsed(cwc_run *r, float *sim_ms, float *total_ms)

@@ -106,3 +106,16 @@ def test_concurrent_runs_on_two_streams(ctx):
         compare_trajectories(g, orc)
         compare_stats(g, orc)
         r.close()
+
+
+def test_wait_with_timeout(ctx):
+    """The host-side watchdog: a launch still running after the timeout
+    reports "not ready" (and keeps running); a later wait sees it end."""
+    from paper_1010_2438_amd import Model, Run
+    m, run = W.config(2)
+    run = dict(run, n_instances=512, rate_table=run["rate_table"][:512])
+    r = Run(ctx, Model(ctx, m), run, mode="persistent")
+    assert r.wait_for(0.0) is False          # hundreds of milliseconds of work
+    assert r.wait_for(120.0) is True
+    assert int(r.counters()["events"].sum()) > 0
+    r.close()
