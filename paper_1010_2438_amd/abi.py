@@ -359,6 +359,7 @@ class Run:
 
     def wait(self):
         check(load().cwc_run_wait(self.h))
+        return self
 
     def wait_for(self, timeout_s: float) -> bool:
         """cwc_run_wait_for: True once the launch has ended, False if it is
@@ -368,7 +369,6 @@ class Run:
             return False
         check(code)
         return True
-        return self
 
     def elapsed_ms(self):
         a, b = ctypes.c_float(), ctypes.c_float()

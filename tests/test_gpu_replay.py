@@ -117,5 +117,6 @@ def test_wait_with_timeout(ctx):
     r = Run(ctx, Model(ctx, m), run, mode="persistent")
     assert r.wait_for(0.0) is False          # hundreds of milliseconds of work
     assert r.wait_for(120.0) is True
+    assert r.wait() is r                     # chains, as the smoke check uses it
     assert int(r.counters()["events"].sum()) > 0
     r.close()
