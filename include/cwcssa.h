@@ -351,6 +351,18 @@ void cwc_server_destroy(cwc_server *s);
 
 /* --------------------------------------------------------------- stats */
 
+/* Confidence bands of the on-line statistics (paper Sec. 5.2 schema iii:
+ * the reduction reports mean, variance and a confidence interval per
+ * sample time).  Host function, no device: for each row r (an (instance,
+ * sample) pair with n[r] trajectories) and cell c,
+ *   half_width[r][c] = t_{(1+level)/2, n[r]-1} * sqrt(var[r][c] / n[r]),
+ * the half-width of the two-sided Student-t interval around the mean at
+ * the given level (0.9 for the paper's 90 % band); NaN where n[r] < 2.
+ * var/half_width: [rows][n_cells] host arrays; n: [rows].  The t quantile
+ * is accurate to about 1e-12 relative.  Errors: CWC_E_INVALID. */
+cwc_status cwc_stats_confidence(const double *var, const int64_t *n, int64_t rows,
+                                int32_t n_cells, double level, double *half_width);
+
 /* Finalises exact moments into mean/var on the device (the same routine the
  * runs use).  All pointers are device pointers; rows = I*(K+1).
  * n[row] trajectories; s1/s2_hi32/s2_lo32 [row][C]. */

@@ -34,6 +34,7 @@ SYMBOLS = [
     "cwc_server_fetch_stats", "cwc_server_fetch_counters", "cwc_server_release",
     "cwc_server_wait_idle", "cwc_server_get_stats", "cwc_server_destroy",
     "cwc_autotune",
+    "cwc_stats_confidence",
     "cwc_stats_finalize",
 ]
 
@@ -143,6 +144,7 @@ def load(path: str = LIB_PATH):
         "cwc_run_fetch_trajectories": [P, P, ctypes.c_int],
         "cwc_run_fetch_counters": [P, P, P, P, P, P, P, ctypes.c_int],
         "cwc_stats_finalize": [P, P, P, P, P, I64, I32, P, P, P],
+        "cwc_stats_confidence": [P, P, I64, I32, ctypes.c_double, P],
         "cwc_server_create": [P, S, I32, I64, ctypes.POINTER(P)],
         "cwc_autotune": [P, P, ctypes.POINTER(cwc_run_desc), ctypes.c_double,
                          ctypes.POINTER(cwc_tuning)],
@@ -207,6 +209,21 @@ class _ModelDesc:
         self.desc = cwc_model_desc(ns, len(types), len(comps), self.has_wrap,
                                    self.comp_type, self.comp_parent, self.init,
                                    len(rules), self.rules)
+
+
+def confidence(var, n, level: float = 0.9):
+    """cwc_stats_confidence: half-widths of the two-sided Student-t interval
+    (level 0.9: the paper's 90 % band) for variances var [..., cells] and
+    counts n [...]; NaN where n < 2."""
+    var = np.ascontiguousarray(var, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    cells = var.shape[-1]
+    rows = n.size
+    assert var.size == rows * cells
+    out = np.empty_like(var)
+    check(load().cwc_stats_confidence(var.ctypes.data, n.ctypes.data, rows, cells,
+                                      float(level), out.ctypes.data))
+    return out
 
 
 def cwc_codegen(model: Dict) -> str:

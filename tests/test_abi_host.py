@@ -132,3 +132,25 @@ def test_algorithmic_work_accounting(P):
     assert (g["n_cells"], g["n_slots"], g["n_leaves"], g["p_local"]) == (20, 20, 32, 16)
     c3 = P.cwc_model_describe(W.multi_compartment())
     assert (c3["n_cells"], c3["n_slots"], c3["n_leaves"], c3["layout"]) == (396, 836, 2048, 1)
+
+
+def test_confidence_bands(P):
+    """cwc_stats_confidence against scipy's Student-t distribution (an
+    independent implementation): the returned quantile puts exactly the
+    requested tail beyond it (scipy's sf, 1e-12 relative) and agrees with
+    scipy's ppf to that routine's own accuracy; 50/90/99/99.9999 % bands,
+    n from 2 to 10^6; NaN below two trajectories."""
+    from scipy import stats
+    rng = np.random.default_rng(3)
+    n = np.array([0, 1, 2, 3, 5, 10, 21, 40, 41, 64, 1000, 16384, 1000000], np.int64)
+    var = rng.uniform(0.5, 50.0, size=(len(n), 4))
+    for level in (0.5, 0.9, 0.99, 0.999999):
+        w = P.confidence(var, n, level)
+        assert np.isnan(w[:2]).all()
+        t = w[2:] / np.sqrt(var[2:] / n[2:, None])
+        q = 0.5 - level / 2
+        assert np.allclose(stats.t.sf(t, (n[2:] - 1)[:, None]), q, rtol=1e-12, atol=0)
+        ref = stats.t.ppf(0.5 + level / 2, n[2:] - 1)
+        assert np.allclose(t, ref[:, None], rtol=5e-10, atol=0)   # scipy ppf: ~1e-10
+    with pytest.raises(P.CwcError):
+        P.confidence(var, n, 1.5)
