@@ -39,14 +39,17 @@ cwc_status alloc_buf(cwc_run *r, T **p, size_t count)
 void free_run(cwc_run *r)
 {
     if (!r) return;
-    (void)hipSetDevice(r->ctx->device);
+    cwc_ctx *ctx = r->ctx;
+    (void)hipSetDevice(ctx->device);
     if (r->launched && r->ev_end) (void)hipEventSynchronize(r->ev_end);
     if (r->graph) (void)hipGraphExecDestroy(r->graph);
-    for (void *p : r->bufs) r->ctx->release(p);
+    for (void *p : r->bufs) ctx->release(p);
     if (r->ev_start) (void)hipEventDestroy(r->ev_start);
     if (r->ev_sim) (void)hipEventDestroy(r->ev_sim);
     if (r->ev_end) (void)hipEventDestroy(r->ev_end);
     delete r;
+    (void)hipGetLastError();   // errors of the teardown are not the next call's
+    ctx_drop(ctx);
 }
 
 // Zero the accumulators and reset the queue cursor.
@@ -277,6 +280,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
 
     auto r = new cwc_run();
     r->ctx = ctx;
+    ctx_retain(ctx);                    // dropped by free_run
     r->m = m;
     r->I = I;
     r->R = R;
@@ -287,7 +291,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     r->tun = tun;
     cwc_status st = CWC_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) {
-        delete r;
+        free_run(r);
         return set_err(CWC_E_DEVICE, "hipSetDevice failed");
     }
     double *d_rates = nullptr;

@@ -3,6 +3,7 @@
 #define CWC_RUNTIME_H
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -24,9 +25,19 @@ struct cwc_ctx {
     std::map<void *, size_t> sizes;           // live allocations
     std::mutex mu;
     hipStream_t capture_stream = nullptr;
+    // models, runs and servers hold the context: cwc_ctx_destroy marks it
+    // closed and it is freed when the last of them is destroyed
+    std::atomic<int> refs{0};
+    bool closed = false;                // guarded by mu
     void *alloc(size_t bytes, cwc_status *st);
     void release(void *p);
 };
+
+namespace cwc {
+void ctx_retain(cwc_ctx *ctx);
+void ctx_drop(cwc_ctx *ctx);            // frees a closed context at the last drop
+void ctx_drop_final(cwc_ctx *ctx);
+}  // namespace cwc
 
 struct cwc_model {
     cwc_ctx *ctx = nullptr;

@@ -576,6 +576,7 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
     for (int i = max_active - 1; i >= 0; --i) s->free_slots.push_back(i);
     s->stats.pool_bytes = (int64_t)s->pool.bytes;
     s->t0 = std::chrono::steady_clock::now();
+    ctx_retain(ctx);                    // dropped by cwc_server_destroy
     cwc_server *raw = s.release();
     raw->th = std::thread(scheduler, raw);
     *out = raw;
@@ -754,8 +755,11 @@ void cwc_server_destroy(cwc_server *s)
     if (s->aux) (void)hipStreamDestroy(s->aux);
     if (s->d_jobs) (void)hipFree(s->d_jobs);
     if (s->d_done) (void)hipFree(s->d_done);
-    s->ctx->release(s->pool_mem);
+    cwc_ctx *ctx = s->ctx;
+    ctx->release(s->pool_mem);
     delete s;
+    (void)hipGetLastError();   // errors of the teardown are not the next call's
+    ctx_drop(ctx);
 }
 
 }  // extern "C"

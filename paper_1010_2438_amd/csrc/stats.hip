@@ -115,6 +115,7 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, long lon
                            hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
+    (void)hipGetLastError();    // report this launch's error, not an earlier one
     hipLaunchKernelGGL(cwc_k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
     return hipGetLastError();
 }
@@ -122,6 +123,7 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, long lon
 hipError_t launch_hist_to_n(const unsigned long long *hist, long long *n, long long n_inst,
                             int K1, hipStream_t s)
 {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(cwc_k_hist_to_n, dim3(blocks_for(n_inst, 64)), dim3(64), 0, s, hist, n,
                        n_inst, K1);
     return hipGetLastError();
@@ -133,6 +135,7 @@ hipError_t launch_finalize(const long long *n, const unsigned long long *s1,
                            double *mean, double *var, hipStream_t s)
 {
     if (rows <= 0) return hipSuccess;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(cwc_k_finalize, dim3(blocks_for(rows * C, 256)), dim3(256), 0, s, n, s1,
                        s2_hi32, s2_lo32, rows, C, mean, var);
     return hipGetLastError();

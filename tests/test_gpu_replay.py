@@ -120,3 +120,26 @@ def test_wait_with_timeout(ctx):
     assert r.wait() is r                     # chains, as the smoke check uses it
     assert int(r.counters()["events"].sum()) > 0
     r.close()
+
+
+def test_context_closed_before_its_model_and_run(ctx):
+    """A context closed while a model and a run still use it stays alive
+    until they are destroyed; the run's results stay readable, and no error
+    is left behind for the next caller."""
+    from paper_1010_2438_amd import Context, Model, Run
+    m, run = W.config(0, replicas=64)
+    run = dict(run, n_samples=11)
+    c = Context(0)
+    mo = Model(c, m)
+    r = Run(c, mo, run, mode="persistent", want_digest=True)
+    c.close()
+    r.wait()
+    got = r.counters()
+    r.close()
+    mo.close()
+    orc = oracle.simulate(m, run, threads=4)
+    assert np.array_equal(got["digest"], orc["digest"])
+    # the next user of the device sees a clean state
+    r2 = Run(ctx, Model(ctx, m), run, mode="plain", want_digest=True).wait()
+    assert np.array_equal(r2.counters()["digest"], orc["digest"])
+    r2.close()
