@@ -276,7 +276,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     }
     if (pair && !m->pair_fn[0])
         return set_err(CWC_E_UNSUPPORTED, "two lanes per trajectory need at least two leaves");
-    tun.lanes_per_replica = layout == 1 ? 64 : 1;
+    tun.lanes_per_replica = layout == 1 ? 64 : (pair ? 2 : 1);   // as launched
 
     auto r = new cwc_run();
     r->ctx = ctx;

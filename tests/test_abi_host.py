@@ -154,3 +154,12 @@ def test_confidence_bands(P):
         assert np.allclose(t, ref[:, None], rtol=5e-10, atol=0)   # scipy ppf: ~1e-10
     with pytest.raises(P.CwcError):
         P.confidence(var, n, 1.5)
+
+
+def test_bench_refuses_several_gpus():
+    """This simulator runs on one GPU: the benchmark says so and exits 2
+    before touching a device."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr
