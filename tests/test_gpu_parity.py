@@ -240,6 +240,19 @@ def test_pair_layout_small_models(ctx, name):
     check(ctx, m, run, tuning=PAIR)
 
 
+def test_pair_layout_tables(ctx):
+    """Two lanes per trajectory with per-instance rate rows and initial
+    states."""
+    m, _ = W.config(1)
+    tab, _ = W.sweep_rate_table(m, 4096, 2)
+    check(ctx, m, W.make_run(seed=0, n_instances=24, replicas=5, dt=0.5, n_samples=21,
+                             rate_table=tab[:24]), tuning=PAIR)
+    lv = W.lotka_volterra(x0=100, y0=100, k=(1.0, 0.01, 1.0))
+    init = np.array([[100, 100], [50, 20], [0, 30], [7, 0]], np.int32)
+    check(ctx, lv, W.make_run(seed=11, n_instances=4, replicas=17, dt=0.1, n_samples=31,
+                              init_table=init), tuning=PAIR)
+
+
 def test_pair_layout_needs_two_leaves(ctx):
     from paper_1010_2438_amd import CwcError
     with pytest.raises(CwcError) as e:
