@@ -429,10 +429,17 @@ void scheduler(cwc_server *s)
         // completions
         std::vector<Job *> finished;
         bool progressed = false;
-        for (int i = 0; ok && i < kStreams; ++i) {
+        for (int i = 0; i < kStreams; ++i) {
             if (inflight[i].empty()) continue;
             const hipError_t q = hipEventQuery(s->ev_slice[i]);
             if (q == hipErrorNotReady) continue;
+            if (!ok) {
+                // after a failure the slices in flight are only drained, so
+                // the scheduler can stop
+                inflight[i].clear();
+                progressed = true;
+                continue;
+            }
             if (q != hipSuccess ||
                 hipMemcpyAsync(done.data(), s->d_done, s->max_active * 8, hipMemcpyDeviceToHost,
                                s->aux) != hipSuccess ||
