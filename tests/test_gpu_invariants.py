@@ -90,3 +90,30 @@ def test_status_edges(ctx, tuning):
     near = W.lotka_volterra(x0=2 ** 31 - 3, y0=0)                      # prey only, near INT32_MAX
     o = check(ctx, near, W.make_run(seed=5, replicas=65, dt=1e-9, n_samples=6), tuning)
     assert (o["status"] == 2).all() and (o["final_counts"][:, 0] <= 2 ** 31 - 1).all()
+
+
+@pytest.mark.parametrize("bad", [
+    {"replicas": 0}, {"n_instances": 0}, {"dt": 0.0}, {"dt": float("inf")},
+    {"n_samples": 0}, {"count_cap": 0}, {"max_events": -1}, {"count_cap": 999},
+])
+def test_run_validation(ctx, bad):
+    """Malformed run descriptors are refused with CWC_E_INVALID before any
+    device work (count_cap 999 is below the model's initial 1000)."""
+    from paper_1010_2438_amd import CwcError
+    m, run = W.config(0)
+    with pytest.raises(CwcError) as e:
+        gpu_run(ctx, model(ctx, m), dict(run, **bad), mode="plain")
+    assert e.value.code == -1
+
+
+def test_rate_and_init_table_validation(ctx):
+    from paper_1010_2438_amd import CwcError
+    m, run = W.config(0)
+    tab = np.array([[10.0, 0.01, 10.0], [10.0, 0.0, 10.0]])
+    with pytest.raises(CwcError) as e:
+        gpu_run(ctx, model(ctx, m), dict(run, n_instances=2, replicas=4, rate_table=tab))
+    assert e.value.code == -1
+    init = np.array([[10, 10], [-1, 3]], np.int32)
+    with pytest.raises(CwcError) as e:
+        gpu_run(ctx, model(ctx, m), dict(run, n_instances=2, replicas=4, init_table=init))
+    assert e.value.code == -1
