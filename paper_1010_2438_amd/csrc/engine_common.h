@@ -9,6 +9,13 @@ typedef unsigned long long u64;
 typedef int i32;
 typedef long long i64;
 
+// Keeps an updated count in a register as an opaque value: the in-place
+// update n += d of an event is undone on its rare slow path by n -= d, and
+// without this the compiler would fold n + d - d back to n and keep both
+// the old and the new count alive through every event (an extra copy of
+// every count per event).  Emits no instruction.
+#define CWC_KEEP(v) __asm__("" : "+v"(v))
+
 #define CWC_ST_OK 0
 #define CWC_ST_ABSORBED 1
 #define CWC_ST_OVERFLOW 2

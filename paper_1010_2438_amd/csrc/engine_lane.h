@@ -11,7 +11,9 @@
 //   CWC_TREE                           leaves k * prod C(n, m), node sums
 //   CWC_ROOT                           the root value (total propensity a0)
 //   CWC_DESCEND(x, j)                  selection descent -> leaf index j
-//   CWC_APPLY(j, cap, ovf)             net change of leaf j unless overflow
+//   CWC_APPLY(j, cap, ovf)             net change of leaf j, in place, and
+//                                      whether a count exceeds the cap
+//   CWC_UNDO() / CWC_REDO()            take that change back / apply it again
 //   CWC_STAGE(ptr, stride)             counts -> ptr[c * stride]
 //
 // One event (paper Sec. 2.3, Match / Resolve / Update):
@@ -192,6 +194,7 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
     i64 g = 0, lg = 0, inst = 0;    /* global / local id, instance */         \
     i32 kn = 0;                     /* next sample index */                   \
     double E = 0.0, U = 0.0;        /* draw e: -ln(u_tau), u_sel */           \
+    CWC_DT_SETUP;                   /* per-leaf change table -> LDS */        \
     (void)INF;
 
 // draw e of trajectory g
@@ -245,28 +248,29 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
         double x_ = U * a0_;            /* Resolve: which slot */             \
         i32 j_;                                                               \
         CWC_DESCEND(x_, j_);                                                  \
-        CWC_APPLY_TRY(j_, p.cap, ovf_); /* Update, as a candidate */          \
+        CWC_APPLY(j_, p.cap, ovf_);     /* Update, undone on the slow path */ \
         const u64 e1_ = e + 1;                                                \
         double E1_, U1_;                                                      \
         CWC_DRAW(e1_, E1_, U1_);        /* next draw, independent */          \
         const bool slow_ = (a0_ == 0.0) | (t_next < tn_) | ovf_ |             \
                            (e1_ == (u64)p.max_events);                        \
         if (!slow_) {                                                         \
-            CWC_COMMIT();                                                     \
             t = tn_; e = e1_; E = E1_; U = U1_;                               \
             if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
         } else if (a0_ == 0.0) {                                              \
             /* absorbing state: remaining samples hold the current counts */  \
+            CWC_UNDO();                                                       \
             while (kn < p.K1) CWC_EMIT();                                     \
             (st) = CWC_ST_ABSORBED;                                           \
         } else {                                                              \
+            CWC_UNDO();                                                       \
             while (t_next < tn_) CWC_EMIT();                                  \
             if (kn >= p.K1) {                                                 \
                 (st) = CWC_ST_OK;       /* this draw lies past the horizon */ \
             } else if (ovf_) {                                                \
                 (st) = CWC_ST_OVERFLOW;                                       \
             } else {                                                          \
-                CWC_COMMIT();                                                 \
+                CWC_REDO();                                                   \
                 t = tn_; e = e1_; E = E1_; U = U1_;                           \
                 if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
                 if (e == (u64)p.max_events) (st) = CWC_ST_EVENT_CAP;          \
@@ -493,7 +497,7 @@ __device__ __forceinline__ double cwc_pair_swap(double v)
         CWC_PAIR_DESCEND(x_, jl_);                                            \
         const int jo_ = cwc_pair_swap_i(jl_);                                 \
         const i32 j_ = (b0_ ? CWC_PB : 0) + ((h_ == (b0_ ? 1 : 0)) ? jl_ : jo_); \
-        CWC_APPLY_TRY(j_, p.cap, ovf_);                                       \
+        CWC_APPLY(j_, p.cap, ovf_);                                           \
         double E1_ = E, U1_ = U;                                              \
         if (EVEN) {                                                           \
             const u64 d1_ = e + 2ull - (u64)h_;                               \
@@ -502,20 +506,21 @@ __device__ __forceinline__ double cwc_pair_swap(double v)
         const bool slow_ = (a0_ == 0.0) | (t_next < tn_) | ovf_ |             \
                            (e + 1 == (u64)p.max_events);                      \
         if (!slow_) {                                                         \
-            CWC_COMMIT();                                                     \
             t = tn_; e = e + 1; E = E1_; U = U1_;                             \
             if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
         } else if (a0_ == 0.0) {                                              \
+            CWC_UNDO();                                                       \
             while (kn < p.K1) CWC_PEMIT();                                    \
             (st) = CWC_ST_ABSORBED;                                           \
         } else {                                                              \
+            CWC_UNDO();                                                       \
             while (t_next < tn_) CWC_PEMIT();                                 \
             if (kn >= p.K1) {                                                 \
                 (st) = CWC_ST_OK;                                             \
             } else if (ovf_) {                                                \
                 (st) = CWC_ST_OVERFLOW;                                       \
             } else {                                                          \
-                CWC_COMMIT();                                                 \
+                CWC_REDO();                                                   \
                 t = tn_; e = e + 1; E = E1_; U = U1_;                         \
                 if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
                 if (e == (u64)p.max_events) (st) = CWC_ST_EVENT_CAP;          \

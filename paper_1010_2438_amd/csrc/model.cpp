@@ -384,65 +384,157 @@ std::string codegen_lane(const Flat &f)
     w.line("}");
     w.end();
 
-    // --- net change of the chosen leaf, branch-free: for every cell and
-    // every binary digit b of the |change| values it receives, a P-bit mask
-    // of the leaves whose change has that digit (one mask for increases,
-    // one for decreases), so d = sum_b ((M+_b >> j) & 1) << b - (...).
-    // Nothing is written if any count would exceed the cap.
+    // --- net change of the chosen leaf.  Each cell's change over the
+    // leaves is a small integer field; the fields of the cells are packed
+    // into at most two 32-bit words per leaf (first fit, a field never
+    // straddles a word), and the table of these words, one entry per leaf,
+    // is copied to LDS when the block starts: an event reads its leaf's
+    // entry once and extracts each cell's change with one bit-field
+    // extract (signed when the cell can decrease).  Cells whose fields do
+    // not fit take the change from per-digit leaf masks instead:
+    // d = sum_b ((M+_b >> j) & 1) << b - (...).  Nothing is written if any
+    // count would exceed the cap.
     std::vector<std::vector<std::pair<int, int>>> per_cell(C);   // (leaf, delta)
     for (auto &s : f.slots)
         for (auto &dv : s.delta) per_cell[dv.first].push_back({s.leaf, dv.second});
+    struct Field { int word = -1, off = 0, width = 0; bool sgn = false; };
+    std::vector<Field> field(C);
+    int used[2] = {0, 0};
+    int n_words = 0;
+    for (int c = 0; c < C; ++c) {
+        if (per_cell[c].empty()) continue;
+        int lo = 0, hi = 0;
+        for (auto &ld : per_cell[c]) { lo = std::min(lo, ld.second); hi = std::max(hi, ld.second); }
+        Field fd;
+        fd.sgn = lo < 0;
+        fd.width = 1;
+        if (fd.sgn) {
+            while (!(-(1ll << (fd.width - 1)) <= lo && hi <= (1ll << (fd.width - 1)) - 1)) ++fd.width;
+        } else {
+            while (hi > (1ll << fd.width) - 1) ++fd.width;
+        }
+        for (int wd = 0; wd < 2; ++wd)
+            if (used[wd] + fd.width <= 32) {
+                fd.word = wd;
+                fd.off = used[wd];
+                used[wd] += fd.width;
+                n_words = std::max(n_words, wd + 1);
+                break;
+            }
+        field[c] = fd;
+    }
+    o << "#define CWC_DT_W " << n_words << "\n";
+    if (n_words > 0) {
+        // table entry l: word 0 in the low half, word 1 in the high half
+        o << "__constant__ unsigned long long cwc_dtab_g[" << P << "] = {";
+        for (int l = 0; l < P; ++l) {
+            unsigned long long v = 0;
+            for (int c = 0; c < C; ++c) {
+                if (field[c].word < 0) continue;
+                long long d = 0;
+                for (auto &ld : per_cell[c])
+                    if (ld.first == l) d += ld.second;
+                const unsigned long long bits =
+                    (unsigned long long)d & ((1ull << field[c].width) - 1ull);
+                v |= bits << (32 * field[c].word + field[c].off);
+            }
+            char b[32];
+            std::snprintf(b, sizeof b, "%s0x%llxull", l ? ", " : "", v);
+            o << b;
+        }
+        o << "};\n";
+        // the block's copy in LDS (every thread of the block passes here
+        // before any event)
+        w.begin("CWC_DT_SETUP");
+        if (n_words == 1) {
+            w.line("__shared__ unsigned int cwc_dtab[" + I(P) + "];");
+            w.line("for (int i_ = (int)threadIdx.x; i_ < " + I(P) +
+                   "; i_ += (int)blockDim.x) cwc_dtab[i_] = (unsigned int)cwc_dtab_g[i_];");
+        } else {
+            w.line("__shared__ unsigned long long cwc_dtab[" + I(P) + "];");
+            w.line("for (int i_ = (int)threadIdx.x; i_ < " + I(P) +
+                   "; i_ += (int)blockDim.x) cwc_dtab[i_] = cwc_dtab_g[i_];");
+        }
+        w.line("__syncthreads();");
+        w.end();
+    } else {
+        o << "#define CWC_DT_SETUP\n";
+    }
     const bool wide = P > 32;
     auto mask_lit = [&](unsigned long long m) {
         char b[40];
         std::snprintf(b, sizeof b, wide ? "0x%llxull" : "0x%llxu", m);
         return std::string(b);
     };
-    // CWC_APPLY_TRY declares the candidate counts v<c>_ of the event and its
-    // overflow flag in the enclosing scope; CWC_COMMIT makes them current.
-    // The digit is taken with a bit-field extract of the mask at position j
-    // (one instruction, no carry through a scalar register).  A rule only
+    // CWC_APPLY adds the change d<c>_ of leaf j to the counts in place and
+    // declares the changes and the overflow flag in the enclosing scope;
+    // CWC_UNDO takes the change back (the slow path of an event that is
+    // not, or not yet, applied) and CWC_REDO applies it again.  Counts are
+    // added modulo 2^32, so an undo restores them exactly.  A rule only
     // fires with enough reactants, so no count goes below zero and the cap
     // test over the cells that can grow is one compare of their maximum.
-    w.begin("CWC_APPLY_TRY(j, cap, ovf)");
+    w.begin("CWC_APPLY(j, cap, ovf)");
     w.line("const unsigned js_ = (unsigned)(j);");
+    if (n_words == 1) {
+        w.line("const unsigned dw0_ = cwc_dtab[js_];");
+    } else if (n_words == 2) {
+        w.line("const unsigned long long dq_ = cwc_dtab[js_];");
+        w.line("const unsigned dw0_ = (unsigned)dq_, dw1_ = (unsigned)(dq_ >> 32);");
+    }
     w.line("unsigned mx_ = 0u;");
     for (int c = 0; c < C; ++c) {
         if (per_cell[c].empty()) continue;
         bool pos = false;
-        std::string e = "(unsigned)n" + I(c);
-        for (int sign = 1; sign >= -1; sign -= 2) {
-            for (int b = 0; b < 21; ++b) {
-                unsigned long long m = 0;
-                for (auto &ld : per_cell[c]) {
-                    int v = ld.second * sign;
-                    if (v > 0 && ((v >> b) & 1)) m |= 1ull << ld.first;
+        for (auto &ld : per_cell[c]) pos = pos || ld.second > 0;
+        std::string e;
+        const Field &fd = field[c];
+        if (fd.word >= 0) {
+            const std::string wv = "dw" + I(fd.word) + "_";
+            if (fd.sgn)
+                e = "(unsigned)__builtin_amdgcn_sbfe((int)" + wv + ", " + I(fd.off) + "u, " +
+                    I(fd.width) + "u)";
+            else
+                e = "__builtin_amdgcn_ubfe(" + wv + ", " + I(fd.off) + "u, " + I(fd.width) + "u)";
+        } else {
+            e = "0u";
+            for (int sign = 1; sign >= -1; sign -= 2) {
+                for (int b = 0; b < 21; ++b) {
+                    unsigned long long m = 0;
+                    for (auto &ld : per_cell[c]) {
+                        int v = ld.second * sign;
+                        if (v > 0 && ((v >> b) & 1)) m |= 1ull << ld.first;
+                    }
+                    if (!m) continue;
+                    std::string bit;
+                    if (!wide) {
+                        bit = "__builtin_amdgcn_ubfe(" + mask_lit(m) + ", js_, 1u)";
+                    } else {
+                        // 64-bit mask: extract from the half holding bit j
+                        char hi[24], lo[24];
+                        std::snprintf(hi, sizeof hi, "0x%llxu", m >> 32);
+                        std::snprintf(lo, sizeof lo, "0x%llxu", m & 0xffffffffull);
+                        bit = std::string("__builtin_amdgcn_ubfe((js_ & 32u) ? ") + hi + " : " + lo +
+                              ", js_ & 31u, 1u)";
+                    }
+                    if (b) bit = "(" + bit + " << " + I(b) + ")";
+                    e += (sign > 0 ? " + " : " - ") + bit;
                 }
-                if (!m) continue;
-                if (sign > 0) pos = true;
-                std::string bit;
-                if (!wide) {
-                    bit = "__builtin_amdgcn_ubfe(" + mask_lit(m) + ", js_, 1u)";
-                } else {
-                    // 64-bit mask: extract from the half holding bit j
-                    char hi[24], lo[24];
-                    std::snprintf(hi, sizeof hi, "0x%llxu", m >> 32);
-                    std::snprintf(lo, sizeof lo, "0x%llxu", m & 0xffffffffull);
-                    bit = std::string("__builtin_amdgcn_ubfe((js_ & 32u) ? ") + hi + " : " + lo +
-                          ", js_ & 31u, 1u)";
-                }
-                if (b) bit = "(" + bit + " << " + I(b) + ")";
-                e += (sign > 0 ? " + " : " - ") + bit;
             }
         }
-        w.line("const unsigned v" + I(c) + "_ = " + e + ";");
-        if (pos) w.line("mx_ = mx_ > v" + I(c) + "_ ? mx_ : v" + I(c) + "_;");
+        w.line("const unsigned d" + I(c) + "_ = " + e + ";");
+        w.line("n" + I(c) + " = (int)((unsigned)n" + I(c) + " + d" + I(c) + "_);");
+        w.line("CWC_KEEP(n" + I(c) + ");");
+        if (pos) w.line("mx_ = mx_ > (unsigned)n" + I(c) + " ? mx_ : (unsigned)n" + I(c) + ";");
     }
     w.line("const bool ovf = mx_ > (cap);");
     w.end();
-    w.begin("CWC_COMMIT()");
+    w.begin("CWC_UNDO()");
     for (int c = 0; c < C; ++c)
-        if (!per_cell[c].empty()) w.line("n" + I(c) + " = (int)v" + I(c) + "_;");
+        if (!per_cell[c].empty()) w.line("n" + I(c) + " = (int)((unsigned)n" + I(c) + " - d" + I(c) + "_);");
+    w.end();
+    w.begin("CWC_REDO()");
+    for (int c = 0; c < C; ++c)
+        if (!per_cell[c].empty()) w.line("n" + I(c) + " = (int)((unsigned)n" + I(c) + " + d" + I(c) + "_);");
     w.end();
 
     // --- stage the counts for the on-line reduction (see CWC_EMIT)
@@ -484,17 +576,42 @@ std::string codegen_lane(const Flat &f)
             w.line("K" + I(i) + " = (h) ? " + Rs + " : " + Ls + ";");
         }
         w.end();
-        // binomial factors of a slot: (F1, F2) with h = F1 * F2
-        auto factors = [&](int si) -> std::pair<std::string, std::string> {
-            if (si < 0) return {"1.0", "1.0"};
+        // binomial factors of a slot: (F1, F2) with h = F1 * F2.  Kinds:
+        // 'n' a count, 'd' n (n-1) of a count, '1' one, 'h' one half.
+        struct Fac {
+            char kind;
+            int cell;
+            bool operator==(const Fac &o) const { return kind == o.kind && cell == o.cell; }
+        };
+        auto factors = [&](int si) -> std::pair<Fac, Fac> {
+            const Fac one{'1', -1};
+            if (si < 0) return {one, one};
             const Slot &sl = f.slots[si];
-            if (sl.n_react == 1 && sl.react_mult[0] == 1) return {"c" + I(sl.react_cell[0]) + "_", "1.0"};
-            if (sl.n_react == 1 && sl.react_mult[0] == 2) {
-                const int c = sl.react_cell[0];
-                return {"(c" + I(c) + "_ * m" + I(c) + "_)", "0.5"};
+            if (sl.n_react == 1 && sl.react_mult[0] == 1) return {Fac{'n', sl.react_cell[0]}, one};
+            if (sl.n_react == 1 && sl.react_mult[0] == 2)
+                return {Fac{'d', sl.react_cell[0]}, Fac{'h', -1}};
+            if (sl.n_react == 2) return {Fac{'n', sl.react_cell[0]}, Fac{'n', sl.react_cell[1]}};
+            return {one, one};
+        };
+        auto fexpr = [&](const Fac &a) -> std::string {
+            switch (a.kind) {
+            case 'n': return "c" + I(a.cell) + "_";
+            case 'd': return "(c" + I(a.cell) + "_ * m" + I(a.cell) + "_)";
+            case 'h': return "0.5";
+            default: return "1.0";
             }
-            if (sl.n_react == 2) return {"c" + I(sl.react_cell[0]) + "_", "c" + I(sl.react_cell[1]) + "_"};
-            return {"1.0", "1.0"};
+        };
+        // the lane's factor: h selects the right or the left slot's.  Two
+        // integer-valued factors (a count or one) are selected as integers
+        // and converted once (the conversion is exact either way).
+        auto fsel = [&](const Fac &l, const Fac &r) -> std::string {
+            if (l == r) return fexpr(l);
+            const bool li = l.kind == 'n' || l.kind == '1', ri = r.kind == 'n' || r.kind == '1';
+            if (li && ri) {
+                auto iexpr = [&](const Fac &a) { return a.kind == 'n' ? "n" + I(a.cell) : std::string("1"); };
+                return "(double)((h) ? " + iexpr(r) + " : " + iexpr(l) + ")";
+            }
+            return "((h) ? " + fexpr(r) + " : " + fexpr(l) + ")";
         };
         w.begin("CWC_PAIR_TREE(h)");
         w.line("{");
@@ -505,9 +622,14 @@ std::string codegen_lane(const Flat &f)
         }
         for (int i = 0; i < B; ++i) {
             if (hz[B + i]) continue;
-            auto L = factors(f.leaf_slot[i]), R = factors(f.leaf_slot[B + i]);
-            const std::string F1 = L.first == R.first ? L.first : "((h) ? " + R.first + " : " + L.first + ")";
-            const std::string F2 = L.second == R.second ? L.second : "((h) ? " + R.second + " : " + L.second + ")";
+            const int sl = f.leaf_slot[i], sr = f.leaf_slot[B + i];
+            auto L = factors(sl), R = factors(sr);
+            // an empty side has rate +0: any finite factor gives +0 there,
+            // so the other side's factors are used unselected
+            if (sl < 0) L = R;
+            if (sr < 0) R = L;
+            const std::string F1 = fsel(L.first, R.first);
+            const std::string F2 = fsel(L.second, R.second);
             std::string H;
             if (F2 == "1.0") H = F1;
             else H = "(" + F1 + " * " + F2 + ")";

@@ -16,7 +16,7 @@
 struct cwc_ctx {
     int device = 0;
     int n_cu = 0;
-    size_t max_lds = 65536;             // LDS bytes one block may allocate
+    size_t max_lds = 65536;             // dynamic LDS bytes a lane-layout block may allocate
     std::string arch;
     void *arena = nullptr;
     size_t arena_bytes = 0;
@@ -62,6 +62,8 @@ inline size_t cwc_lane_lds_bytes(int n_cells, int waves, int nslot)
                             2 * (size_t)nslot * (size_t)n_cells * 8);
 }
 constexpr int kDefaultSampleSlots = 16;
+// static LDS of a lane-layout kernel: the per-leaf change table
+constexpr size_t kLaneStaticLds = 64 * 8;
 // Compiles and loads the model's device code for `layout` if needed.
 cwc_status ensure_layout(cwc_model *m, int layout);
 // Directory of the compiled-code cache and the tuning table (created).

@@ -228,6 +228,31 @@ def test_config1_full_size_sampled(ctx):
 
 # ---------------------------------------------------------------- pair layout
 
+def bursts():
+    """Six species made in bursts of 600 to 5000 molecules and lost one at a
+    time.  The per-leaf change fields (11 to 14 bits) fill both table words
+    and two cells take their change from per-digit leaf masks instead."""
+    sizes = [600, 900, 1500, 3000, 5000, 700]
+    rules = []
+    for i, b in enumerate(sizes):
+        rules.append(W._local(0, {}, {i: b}, 1.0))
+        rules.append(W._local(0, {i: 1}, {}, 1.0))
+    return W._single("bursts", [f"X{i}" for i in range(6)], rules, [0] * 6)
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_large_changes(ctx, lanes):
+    """Large net changes per event, both lane layouts and forms; with a cap
+    below the largest burst the trajectories end in overflow with the state
+    before the burst."""
+    m = bursts()
+    tuning = PAIR if lanes == 2 else None
+    run = W.make_run(seed=13, replicas=300, dt=0.1, n_samples=21)
+    check(ctx, m, run, tuning=tuning)
+    orc = check(ctx, m, dict(run, count_cap=4000), tuning=tuning)
+    assert (orc["status"] == 2).sum() > 100
+
+
 PAIR = {"lanes_per_replica": 2, "block_size": 64, "waves_per_simd": 1}
 
 
