@@ -30,9 +30,43 @@ __device__ __forceinline__ double cwc_rl(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-__device__ __forceinline__ double cwc_xor_shfl(double v, int mask)
+// Butterfly partner of level l (1..6) for a value that is uniform within
+// each block of 2^(l-1) lanes: any lane of the sibling block will do, since
+// the sum of the two blocks is the same in either order (IEEE addition
+// commutes).  Levels 1-4 stay inside a row of 16 lanes (DPP: quad
+// permutations, half-row and row mirrors); levels 5 and 6 use the row swaps
+// of gfx950 (permlane16/permlane32 swap), which hand back both halves, so
+// the level's sum is formed from the pair directly.
+template <int CTRL>
+__device__ __forceinline__ double cwc_dpp(double v)
 {
-    return __shfl_xor(v, mask, 64);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double cwc_bfly_sum(double v, int level)
+{
+    switch (level) {
+    case 1: return v + cwc_dpp<0xB1>(v);     // quad_perm [1,0,3,2]: lane ^ 1
+    case 2: return v + cwc_dpp<0x4E>(v);     // quad_perm [2,3,0,1]: lane ^ 2
+    case 3: return v + cwc_dpp<0x141>(v);    // row_half_mirror: 7 - lane in 8
+    case 4: return v + cwc_dpp<0x140>(v);    // row_mirror: 15 - lane in 16
+    default: {
+        const long long b = __double_as_longlong(v);
+        const int lo = (int)b, hi = (int)(b >> 32);
+        // the first result holds the even row (lower half) of each pair,
+        // the second the odd row (upper half), in every lane
+        const auto rl = level == 5 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                                   : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto rh = level == 5 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                                   : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        const double a = __longlong_as_double(((long long)rh[0] << 32) | (long long)(unsigned)rl[0]);
+        const double c = __longlong_as_double(((long long)rh[1] << 32) | (long long)(unsigned)rl[1]);
+        return a + c;
+    }
+    }
 }
 
 #define CWC_NCELL_LANE (CWC_HAS_WRAP ? 2 * CWC_NS : CWC_NS)
@@ -139,12 +173,12 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
             // ---- Match: leaves, subtree, butterfly over compartment blocks
             CWC_LEAVES(kind);
             const double v0 = a1;
-            const double v1 = CWC_LP >= 1 ? v0 + cwc_xor_shfl(v0, 1) : v0;
-            const double v2 = CWC_LP >= 2 ? v1 + cwc_xor_shfl(v1, 2) : v1;
-            const double v3 = CWC_LP >= 3 ? v2 + cwc_xor_shfl(v2, 4) : v2;
-            const double v4 = CWC_LP >= 4 ? v3 + cwc_xor_shfl(v3, 8) : v3;
-            const double v5 = CWC_LP >= 5 ? v4 + cwc_xor_shfl(v4, 16) : v4;
-            const double v6 = CWC_LP >= 6 ? v5 + cwc_xor_shfl(v5, 32) : v5;
+            const double v1 = CWC_LP >= 1 ? cwc_bfly_sum(v0, 1) : v0;
+            const double v2 = CWC_LP >= 2 ? cwc_bfly_sum(v1, 2) : v1;
+            const double v3 = CWC_LP >= 3 ? cwc_bfly_sum(v2, 3) : v2;
+            const double v4 = CWC_LP >= 4 ? cwc_bfly_sum(v3, 4) : v3;
+            const double v5 = CWC_LP >= 5 ? cwc_bfly_sum(v4, 5) : v4;
+            const double v6 = CWC_LP >= 6 ? cwc_bfly_sum(v5, 6) : v5;
             const double a0 = cwc_rl(v6, 0);
             // ---- draws, 64 at a time
             if (!have_batch || e - e0 >= 64ull) {
