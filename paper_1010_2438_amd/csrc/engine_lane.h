@@ -460,53 +460,68 @@ cwc_lane_slice_table(const cwc_kparams *jobs, const int *wave_job, const long lo
 // code is wavefront-uniform.  Results are those of the lane layout bit for
 // bit: the same tree, the same descent, the same draws per event.
 
-// partner lane's value (lane ^ 1: DPP quad permutation 1,0,3,2)
-__device__ __forceinline__ int cwc_pair_swap_i(int v)
+// Values of the pair's lanes (DPP quad permutations; both lanes of a pair
+// are always active together, so every source lane is live): the value of
+// lane 0 of the pair ([0,0,2,2]) and of lane 1 ([1,1,3,3]), in both lanes.
+template <int CTRL>
+__device__ __forceinline__ int cwc_pair_dpp_i(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
-__device__ __forceinline__ double cwc_pair_swap(double v)
+template <int CTRL>
+__device__ __forceinline__ double cwc_pair_dpp(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = cwc_pair_swap_i((int)b);
-    const int hi = cwc_pair_swap_i((int)(b >> 32));
+    const int lo = cwc_pair_dpp_i<CTRL>((int)b);
+    const int hi = cwc_pair_dpp_i<CTRL>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
+#define CWC_PAIR_LO 0xA0
+#define CWC_PAIR_HI 0xF5
+
+// Both lanes take the pair's two fresh draws: lane 1's (the next event,
+// an odd iteration) into Eo/Uo, lane 0's (the one after, an even
+// iteration) into E/U.
+#define CWC_PAIR_SPREAD(EN, UN)                                               \
+    do {                                                                      \
+        Eo = cwc_pair_dpp<CWC_PAIR_HI>(EN);                                   \
+        Uo = cwc_pair_dpp<CWC_PAIR_HI>(UN);                                   \
+        E = cwc_pair_dpp<CWC_PAIR_LO>(EN);                                    \
+        U = cwc_pair_dpp<CWC_PAIR_LO>(UN);                                    \
+    } while (0)
 
 // One step of a pair (the locals of the pair kernels, CWC_PEMIT and h_ in
-// scope): the event of this iteration (its draw: lane 0's at an even
-// iteration, lane 1's at an odd one) and, at an even iteration, each lane's
-// next draw (lane 1: e+1, lane 0: e+2).
+// scope): the event of this iteration -- its draw is E/U at an even
+// iteration, Eo/Uo at an odd one, the same in both lanes -- and, at an
+// even iteration, the next two draws (lane 1: e+1, lane 0: e+2).  The root
+// is lane 0's half plus lane 1's, in that order in both lanes.
 #define CWC_PAIR_STEP_BODY(st, EVEN)                                                   \
     do {                                                                      \
         CWC_PAIR_TREE(h_);                                                    \
         const double s_ = CWC_PAIR_HALF;                                      \
-        const double o_ = cwc_pair_swap(s_);                                  \
-        const double a0_ = s_ + o_;                                           \
-        const double Eo_ = cwc_pair_swap(E), Uo_ = cwc_pair_swap(U);          \
-        const bool mine_ = h_ == ((EVEN) ? 0 : 1);                            \
-        const double Ec_ = mine_ ? E : Eo_;                                   \
-        const double Uc_ = mine_ ? U : Uo_;                                   \
-        const double tn_ = t + Ec_ / a0_;                                     \
-        double x_ = Uc_ * a0_;                                                \
-        const double L0_ = h_ ? o_ : s_;                                      \
-        const double R0_ = h_ ? s_ : o_;                                      \
+        const double L0_ = cwc_pair_dpp<CWC_PAIR_LO>(s_);                     \
+        const double R0_ = cwc_pair_dpp<CWC_PAIR_HI>(s_);                     \
+        const double a0_ = L0_ + R0_;                                         \
+        const double tn_ = t + ((EVEN) ? E : Eo) / a0_;                       \
+        double x_ = ((EVEN) ? U : Uo) * a0_;                                  \
         const bool b0_ = (x_ >= L0_) && (R0_ != 0.0);                         \
         x_ = b0_ ? x_ - L0_ : x_;                                             \
         int jl_ = 0;                                                          \
         CWC_PAIR_DESCEND(x_, jl_);                                            \
-        const int jo_ = cwc_pair_swap_i(jl_);                                 \
-        const i32 j_ = (b0_ ? CWC_PB : 0) + ((h_ == (b0_ ? 1 : 0)) ? jl_ : jo_); \
+        const int j0_ = cwc_pair_dpp_i<CWC_PAIR_LO>(jl_);                     \
+        const int j1_ = cwc_pair_dpp_i<CWC_PAIR_HI>(jl_);                     \
+        const i32 j_ = b0_ ? CWC_PB + j1_ : j0_;                              \
         CWC_APPLY(j_, p.cap, ovf_);                                           \
-        double E1_ = E, U1_ = U;                                              \
+        double En_ = 0.0, Un_ = 0.0;                                          \
         if (EVEN) {                                                           \
             const u64 d1_ = e + 2ull - (u64)h_;                               \
-            CWC_DRAW(d1_, E1_, U1_);                                          \
+            CWC_DRAW(d1_, En_, Un_);                                          \
         }                                                                     \
         const bool slow_ = (a0_ == 0.0) | (t_next < tn_) | ovf_ |             \
                            (e + 1 == (u64)p.max_events);                      \
         if (!slow_) {                                                         \
-            t = tn_; e = e + 1; E = E1_; U = U1_;                             \
+            t = tn_; e = e + 1;                                               \
+            if (EVEN) CWC_PAIR_SPREAD(En_, Un_);                              \
             if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
         } else if (a0_ == 0.0) {                                              \
             CWC_UNDO();                                                       \
@@ -521,7 +536,8 @@ __device__ __forceinline__ double cwc_pair_swap(double v)
                 (st) = CWC_ST_OVERFLOW;                                       \
             } else {                                                          \
                 CWC_REDO();                                                   \
-                t = tn_; e = e + 1; E = E1_; U = U1_;                         \
+                t = tn_; e = e + 1;                                           \
+                if (EVEN) CWC_PAIR_SPREAD(En_, Un_);                          \
                 if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
                 if (e == (u64)p.max_events) (st) = CWC_ST_EVENT_CAP;          \
             }                                                                 \
@@ -536,10 +552,12 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
     const int h_ = (int)(__lane_id() & 1u);
     if (SHARED_K) { CWC_PAIR_LOAD_K(p.rates, h_); }
     u32 it = 0;                     // wavefront iteration (parity: whose draw)
+    double Eo = 0.0, Uo = 0.0;      // draw of the next odd-iteration event
 
-    // begin the trajectory of item `item` at the current iteration: the lane
-    // whose draw the next event uses takes draw 0; at an odd iteration lane 0
-    // also needs draw 1 (the even iteration after computes draws 2 and 3)
+    // begin the trajectory of item `item` at the current iteration: at an
+    // even one both lanes take draw 0 (E/U); at an odd one draw 0 goes to
+    // Eo/Uo and draw 1, for the even iteration after, to E/U (that
+    // iteration then draws 2 and 3)
 #define CWC_PBEGIN(item)                                                      \
     do {                                                                      \
         i64 lg0_ = (item);                                                    \
@@ -559,8 +577,15 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
           CWC_LOAD_COUNTS(ini_); }                                            \
         t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
         dig = 0xcbf29ce484222325ull;                                          \
-        { const u64 d0_ = (it & 1u) ? (u64)(1 - h_) : 0ull;                   \
-          CWC_DRAW(d0_, E, U); }                                              \
+        if (it & 1u) {                                                        \
+            /* odd iteration: lane 1 draws 0 (this event), lane 0 draws 1 */  \
+            double Et_, Ut_;                                                  \
+            const u64 d0_ = (u64)(1 - h_);                                    \
+            CWC_DRAW(d0_, Et_, Ut_);                                          \
+            CWC_PAIR_SPREAD(Et_, Ut_);                                        \
+        } else {                                                              \
+            CWC_DRAW(0ull, E, U);                                             \
+        }                                                                     \
     } while (0)
 
     // sample kn of the current state (lane 0 of the pair records it)
@@ -672,6 +697,7 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
     CWC_PAIR_DECL;
     const int h_ = (int)(__lane_id() & 1u);
     if (SHARED_K) { CWC_PAIR_LOAD_K(p.rates, h_); }
+    double Eo = 0.0, Uo = 0.0;      // draw of the next odd-iteration event
     const i64 my = wave_first[w] + (i64)((threadIdx.x & 63) >> 1);
     bool active = my < p.G && p.ck_state[my] != 2;
     if (active) {
