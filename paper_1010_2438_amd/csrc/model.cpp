@@ -258,6 +258,58 @@ struct MacroWriter {
 };
 }  // namespace
 
+// Narrows the level-(d+1) node values `vals` (heap order, d = bits.size())
+// to the pair (L, R) under the current node, given the decisions taken so
+// far (bits[q] of depth q; "" = constant false), with two-way selects that
+// never use a lane-varying index.  The decisions are applied most
+// significant first (each select can start as soon as its decision is
+// known) unless applying them least significant first needs fewer selects
+// (padding subtrees then pair up with padding and cost nothing).  Emits the
+// selects as `const double <pfx><n>_ = bit ? A : B;` lines when `w` is
+// given; returns (L, R) and the number of selects.
+struct Narrowed {
+    std::string L, R;
+    int selects;
+};
+static Narrowed narrow_pair(std::vector<std::string> vals, const std::vector<std::string> &bits,
+                            const std::string &pfx, int &tmp, MacroWriter *w)
+{
+    auto run = [&](bool lsb, MacroWriter *out, int &t) {
+        std::vector<std::string> v = vals;
+        int n = 0;
+        const int d = (int)bits.size();
+        for (int k = 0; k < d; ++k) {
+            const int q = lsb ? d - 1 - k : k;
+            const size_t half = v.size() / 2;
+            std::vector<std::string> nv(half);
+            for (size_t r = 0; r < half; ++r) {
+                size_t i0, i1;
+                if (lsb) {   // decision q sits at bit 1 of the index
+                    i0 = ((r >> 1) << 2) | (r & 1);
+                    i1 = i0 | 2;
+                } else {     // decision q is the most significant bit
+                    i0 = r;
+                    i1 = r + half;
+                }
+                const std::string &A = v[i1], &B = v[i0];
+                if (bits[q].empty() || A == B) {
+                    nv[r] = B;
+                } else {
+                    ++n;
+                    const std::string tv = pfx + std::to_string(t++) + "_";
+                    if (out) out->line("const double " + tv + " = " + bits[q] + " ? " + A + " : " + B + ";");
+                    nv[r] = tv;
+                }
+            }
+            v = nv;
+        }
+        return Narrowed{v[0], v[1], n};
+    };
+    int scratch = 0;
+    const bool lsb = run(true, nullptr, scratch).selects < run(false, nullptr, scratch).selects;
+    return run(lsb, w, tmp);
+}
+
 std::string codegen_lane(const Flat &f)
 {
     std::ostringstream o;
@@ -338,10 +390,9 @@ std::string codegen_lane(const Flat &f)
     w.end();
 
     // --- selection descent.  At depth d the pair (L, R) under the current
-    // node is picked from the level-(d+1) nodes by halving them with the
-    // decisions already taken (most significant first), so no value is
-    // ever picked with a lane-varying index and the temporaries of one
-    // level die before the next level starts.
+    // node is picked from the level-(d+1) nodes with the decisions already
+    // taken (narrow_pair), so no value is ever picked with a lane-varying
+    // index and the temporaries of one level die before the next starts.
     w.begin("CWC_DESCEND(x, j)");
     w.line("{");
     w.line("int jj_ = 0;");
@@ -350,22 +401,8 @@ std::string codegen_lane(const Flat &f)
     for (int d = 0; d < D; ++d) {
         std::vector<std::string> vals;
         for (int m = 0; m < (2 << d); ++m) vals.push_back(val((2 << d) + m));
-        for (int q = 0; q < d; ++q) {
-            const size_t half = vals.size() / 2;
-            std::vector<std::string> nv(half);
-            for (size_t m = 0; m < half; ++m) {
-                const std::string &A = vals[m + half], &B = vals[m];
-                if (bits[q].empty() || A == B) {
-                    nv[m] = B;
-                } else {
-                    const std::string t = "t" + I(tmp++) + "_";
-                    w.line("const double " + t + " = " + bits[q] + " ? " + A + " : " + B + ";");
-                    nv[m] = t;
-                }
-            }
-            vals = nv;
-        }
-        const std::string L = vals[0], R = vals[1];
+        const Narrowed nw = narrow_pair(vals, bits, "t", tmp, &w);
+        const std::string L = nw.L, R = nw.R;
         if (R == "0.0") {
             w.line("jj_ = jj_ << 1;");
             bits.push_back("");
@@ -653,22 +690,8 @@ std::string codegen_lane(const Flat &f)
         for (int d = 0; d < DB; ++d) {
             std::vector<std::string> vals;
             for (int m = 0; m < (2 << d); ++m) vals.push_back(hv((2 << d) + m));
-            for (int q = 0; q < d; ++q) {
-                const size_t half = vals.size() / 2;
-                std::vector<std::string> nv(half);
-                for (size_t m = 0; m < half; ++m) {
-                    const std::string &A = vals[m + half], &Bv = vals[m];
-                    if (hbits[q].empty() || A == Bv) {
-                        nv[m] = Bv;
-                    } else {
-                        const std::string t = "u" + I(htmp++) + "_";
-                        w.line("const double " + t + " = " + hbits[q] + " ? " + A + " : " + Bv + ";");
-                        nv[m] = t;
-                    }
-                }
-                vals = nv;
-            }
-            const std::string Lv = vals[0], Rv = vals[1];
+            const Narrowed nw = narrow_pair(vals, hbits, "u", htmp, &w);
+            const std::string Lv = nw.L, Rv = nw.R;
             if (Rv == "0.0") {
                 w.line("jj_ = jj_ << 1;");
                 hbits.push_back("");
