@@ -224,9 +224,9 @@ def measured_traffic(source, kernel):
 
 def kernel_name(tuning, mode):
     """The simulation kernel a run with this tuning dispatches (the lane
-    layout's module also holds the pair kernels)."""
+    layout's module also holds the pair and quad kernels)."""
     lpr = (tuning or {}).get("lanes_per_replica", 1)
-    fam = {2: "cwc_pair", 64: "cwc_wave"}.get(lpr, "cwc_lane")
+    fam = {2: "cwc_pair", 4: "cwc_quad", 64: "cwc_wave"}.get(lpr, "cwc_lane")
     return "%s_%s_table" % (fam, mode)
 
 

@@ -194,8 +194,13 @@ typedef struct {
                                   rejected with CWC_E_INVALID                 */
     int32_t lanes_per_replica; /* 1 (lane layout), 2 (pair: two lanes per
                                   trajectory, each holding half of the
-                                  propensity tree; models with >= 2 leaves)
-                                  or 64 (wave layout); 0 = auto            */
+                                  propensity tree; models with >= 2 leaves),
+                                  4 (quad: four lanes, a quarter each; models
+                                  with >= 4 leaves; run forms only, serving
+                                  uses 1 or 2) or 64 (wave layout); 0 = auto.
+                                  Other values, or a group of more lanes
+                                  than the model has leaves:
+                                  CWC_E_UNSUPPORTED                         */
     int32_t sample_slots;      /* lane layout: sampling-buffer depth, i.e. the
                                   accumulator rows each wavefront keeps in
                                   LDS before writing moments back; a power of

@@ -790,3 +790,238 @@ extern "C" __global__ void __launch_bounds__(256)
 cwc_pair_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
                      long long budget) { cwc_pair_slice<false>(jobs, wave_job, wave_first, budget); }
 #endif  // CWC_PAIR
+
+#ifdef CWC_QUAD
+// ------------------------------------------------------------ quad layout
+// Four lanes per trajectory (lane bits h = lane & 3): lane h holds quarter h
+// of the propensity tree (leaves [h*B, (h+1)*B)), all four hold the counts.
+// Per event: each lane builds its quarter; every lane reads the four
+// quarter sums (DPP broadcasts of lanes 0..3 of the quad) and forms the two
+// halves and the root in the canonical order; all take the two top
+// decisions, each descends its own quarter and the leaf index is read from
+// the lane holding the chosen quarter; all apply the change.  Draws: at
+// iterations of phase 0 (it % 4 == 0) lane k draws e + 1 + ((k + 3) % 4)
+// and the four draws are spread at once, so the events of phases 1, 2, 3
+// and the next phase 0 find theirs in E1..E3 and E0.  Every quad of a
+// wavefront follows the wavefront's phase.  Results are those of the lane
+// layout bit for bit.  Like a pair, a quad's lanes are always active
+// together.  (Lanes of a quad whose quarter holds no slot compute zeros.)
+#define CWC_QL0 0x00
+#define CWC_QL1 0x55
+#define CWC_QL2 0xAA
+#define CWC_QL3 0xFF
+
+#define CWC_QUAD_SPREAD(EN, UN)                                               \
+    do {                                                                      \
+        E0 = cwc_pair_dpp<CWC_QL0>(EN); U0 = cwc_pair_dpp<CWC_QL0>(UN);       \
+        E1 = cwc_pair_dpp<CWC_QL1>(EN); U1 = cwc_pair_dpp<CWC_QL1>(UN);       \
+        E2 = cwc_pair_dpp<CWC_QL2>(EN); U2 = cwc_pair_dpp<CWC_QL2>(UN);       \
+        E3 = cwc_pair_dpp<CWC_QL3>(EN); U3 = cwc_pair_dpp<CWC_QL3>(UN);       \
+    } while (0)
+
+// One step of a quad at phase PH (0..3, a constant): the event of this
+// iteration with draw E<PH>/U<PH>; at phase 0 also the next four draws.
+#define CWC_QUAD_STEP_BODY(st, PH)                                            \
+    do {                                                                      \
+        CWC_QUAD_TREE(h_);                                                    \
+        const double s_ = CWC_QUAD_PART;                                      \
+        const double p0_ = cwc_pair_dpp<CWC_QL0>(s_);                         \
+        const double p1_ = cwc_pair_dpp<CWC_QL1>(s_);                         \
+        const double p2_ = cwc_pair_dpp<CWC_QL2>(s_);                         \
+        const double p3_ = cwc_pair_dpp<CWC_QL3>(s_);                         \
+        const double n1_ = p0_ + p1_;                                         \
+        const double n2_ = p2_ + p3_;                                         \
+        const double a0_ = n1_ + n2_;                                         \
+        const double Ec_ = (PH) == 0 ? E0 : (PH) == 1 ? E1 : (PH) == 2 ? E2 : E3; \
+        const double Uc_ = (PH) == 0 ? U0 : (PH) == 1 ? U1 : (PH) == 2 ? U2 : U3; \
+        const double tn_ = t + Ec_ / a0_;                                     \
+        double x_ = Uc_ * a0_;                                                \
+        const bool b0_ = (x_ >= n1_) && (n2_ != 0.0);                         \
+        x_ = b0_ ? x_ - n1_ : x_;                                             \
+        const double L1_ = b0_ ? p2_ : p0_;                                   \
+        const double R1_ = b0_ ? p3_ : p1_;                                   \
+        const bool b1_ = (x_ >= L1_) && (R1_ != 0.0);                         \
+        x_ = b1_ ? x_ - L1_ : x_;                                             \
+        int jl_ = 0;                                                          \
+        CWC_QUAD_DESCEND(x_, jl_);                                            \
+        const int j0_ = cwc_pair_dpp_i<CWC_QL0>(jl_);                         \
+        const int j1_ = cwc_pair_dpp_i<CWC_QL1>(jl_);                         \
+        const int j2_ = cwc_pair_dpp_i<CWC_QL2>(jl_);                         \
+        const int j3_ = cwc_pair_dpp_i<CWC_QL3>(jl_);                         \
+        const i32 jq_ = b0_ ? (b1_ ? j3_ : j2_) : (b1_ ? j1_ : j0_);          \
+        const i32 j_ = ((b0_ ? 2 : 0) + (b1_ ? 1 : 0)) * CWC_QB + jq_;         \
+        CWC_APPLY(j_, p.cap, ovf_);                                           \
+        double En_ = 0.0, Un_ = 0.0;                                          \
+        if ((PH) == 0) {                                                      \
+            const u64 d1_ = e + 1ull + (u64)((h_ + 3) & 3);                   \
+            CWC_DRAW(d1_, En_, Un_);                                          \
+        }                                                                     \
+        const bool slow_ = (a0_ == 0.0) | (t_next < tn_) | ovf_ |             \
+                           (e + 1 == (u64)p.max_events);                      \
+        if (!slow_) {                                                         \
+            t = tn_; e = e + 1;                                               \
+            if ((PH) == 0) CWC_QUAD_SPREAD(En_, Un_);                         \
+            if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
+        } else if (a0_ == 0.0) {                                              \
+            CWC_UNDO();                                                       \
+            while (kn < p.K1) CWC_QEMIT();                                    \
+            (st) = CWC_ST_ABSORBED;                                           \
+        } else {                                                              \
+            CWC_UNDO();                                                       \
+            while (t_next < tn_) CWC_QEMIT();                                 \
+            if (kn >= p.K1) {                                                 \
+                (st) = CWC_ST_OK;                                             \
+            } else if (ovf_) {                                                \
+                (st) = CWC_ST_OVERFLOW;                                       \
+            } else {                                                          \
+                CWC_REDO();                                                   \
+                t = tn_; e = e + 1;                                           \
+                if ((PH) == 0) CWC_QUAD_SPREAD(En_, Un_);                     \
+                if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
+                if (e == (u64)p.max_events) (st) = CWC_ST_EVENT_CAP;          \
+            }                                                                 \
+        }                                                                     \
+    } while (0)
+
+template <bool PERSIST, bool SHARED_K>
+__device__ __forceinline__ void cwc_quad_main(const cwc_kparams &p)
+{
+    CWC_LANE_LOCALS;
+    CWC_QUAD_DECL;
+    const int h_ = (int)(__lane_id() & 3u);
+    if (SHARED_K) { CWC_QUAD_LOAD_K(p.rates, h_); }
+    u32 it = 0;                     // wavefront iteration (phase it % 4)
+    double E0 = 0.0, U0 = 0.0, E1 = 0.0, U1 = 0.0;   // draw of the next event
+    double E2 = 0.0, U2 = 0.0, E3 = 0.0, U3 = 0.0;   // of each phase
+    (void)E; (void)U;
+
+    // begin the trajectory of item `item` at phase r = it % 4: the events
+    // of phases r..3 and of the next phase 0 take draws 0..4-r, drawn by the
+    // lanes of those phases (lane k >= r: draw k - r; lane 0: draw 4 - r)
+#define CWC_QBEGIN(item)                                                      \
+    do {                                                                      \
+        i64 lg0_ = (item);                                                    \
+        if (PERSIST && p.order) {                                             \
+            const u32 grp_ = (u32)(item) / (u32)p.R;                          \
+            const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
+            lg0_ = (i64)p.order[grp_] * p.R + rep_;                           \
+        }                                                                     \
+        lg = lg0_;                                                            \
+        inst = (i64)((u32)lg / (u32)p.R);                                     \
+        g = p.g_base + lg;                                                    \
+        if (!SHARED_K) {                                                      \
+            const double *kr_ = p.rates + (i64)p.rate_stride * inst;          \
+            CWC_QUAD_LOAD_K(kr_, h_);                                         \
+        }                                                                     \
+        { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
+          CWC_LOAD_COUNTS(ini_); }                                            \
+        t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
+        dig = 0xcbf29ce484222325ull;                                          \
+        {                                                                     \
+            const int r_ = (int)(it & 3u);                                    \
+            const int d_ = h_ >= r_ ? h_ - r_ : (h_ == 0 ? 4 - r_ : 0);       \
+            double Et_, Ut_;                                                  \
+            CWC_DRAW((u64)d_, Et_, Ut_);                                      \
+            CWC_QUAD_SPREAD(Et_, Ut_);                                        \
+        }                                                                     \
+    } while (0)
+
+    // sample kn of the current state (lane 0 of the quad records it)
+#define CWC_QEMIT()                                                           \
+    do {                                                                      \
+        if (h_ == 0) {                                                        \
+            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+            CWC_STAGE(col, 64);                                               \
+            cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
+        }                                                                     \
+        kn += 1;                                                              \
+        t_next = (kn < p.K1) ? (double)kn * p.dt : INF;                       \
+    } while (0)
+
+    const i64 tid = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const i64 qid = tid >> 2;
+    bool active = qid < p.G;
+    bool live = active;
+    i64 w_next = 0, w_end = 0;      // chunked claims: the wavefront's window
+    if (active) CWC_QBEGIN(qid);
+
+    // persistent form: quads whose trajectory ended take the next items
+#define CWC_QPREFILL                                                          \
+    if (PERSIST) {                                                            \
+        const u64 want = __ballot(live && !active);                           \
+        if (want) {                                                           \
+            const u64 firsts = want & 0x1111111111111111ull;                  \
+            const int cnt = __popcll(firsts);                                 \
+            const int lane = __lane_id();                                     \
+            const int leader = __ffsll((long long)want) - 1;                  \
+            const int rank = __popcll(firsts & ((1ull << (lane & ~3)) - 1ull)); \
+            i64 item;                                                         \
+            if (p.chunk <= 1) {                                               \
+                u64 base = 0;                                                 \
+                if (lane == leader) base = atomicAdd(p.cursor, (u64)cnt);     \
+                base = __shfl(base, leader);                                  \
+                item = (i64)base + rank;                                      \
+            } else {                                                          \
+                const i64 avail = w_end - w_next;                             \
+                if (avail >= cnt) {                                           \
+                    item = w_next + rank;                                     \
+                    w_next += cnt;                                            \
+                } else {                                                      \
+                    u64 base = 0;                                             \
+                    if (lane == leader) base = atomicAdd(p.cursor, (u64)p.chunk); \
+                    base = __shfl(base, leader);                              \
+                    const i64 nb = (i64)base;                                 \
+                    item = rank < avail ? w_next + rank : nb + (rank - avail); \
+                    w_end = nb + p.chunk < p.G ? nb + p.chunk : p.G;          \
+                    w_next = nb + (cnt - avail);                              \
+                    if (w_next > w_end) w_next = w_end;                       \
+                }                                                             \
+            }                                                                 \
+            if (live && !active) {                                            \
+                if (item < p.G) {                                             \
+                    CWC_QBEGIN(item);                                         \
+                    active = true;                                            \
+                } else {                                                      \
+                    live = false;                                             \
+                }                                                             \
+            }                                                                 \
+        }                                                                     \
+        if (!__any(live)) break;                                              \
+    } else {                                                                  \
+        if (!__any(active)) break;                                            \
+    }
+
+#define CWC_QSTEP(PH)                                                         \
+    CWC_QPREFILL                                                              \
+    if (active) {                                                             \
+        int st = CWC_ST_RUNNING;                                              \
+        CWC_QUAD_STEP_BODY(st, PH);                                           \
+        if (st != CWC_ST_RUNNING) {                                           \
+            if (h_ == 0) CWC_FINISH(st);                                      \
+            active = false;                                                   \
+        }                                                                     \
+    }                                                                         \
+    it += 1u;
+
+    for (;;) {
+        CWC_QSTEP(0)
+        CWC_QSTEP(1)
+        CWC_QSTEP(2)
+        CWC_QSTEP(3)
+    }
+    cwc_acc_flush_all(p, acc);
+#undef CWC_QSTEP
+#undef CWC_QPREFILL
+#undef CWC_QEMIT
+#undef CWC_QBEGIN
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+cwc_quad_plain_shared(cwc_kparams p) { cwc_quad_main<false, true>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_quad_plain_table(cwc_kparams p) { cwc_quad_main<false, false>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_quad_persistent_shared(cwc_kparams p) { cwc_quad_main<true, true>(p); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_quad_persistent_table(cwc_kparams p) { cwc_quad_main<true, false>(p); }
+#endif  // CWC_QUAD

@@ -579,6 +579,33 @@ std::string codegen_lane(const Flat &f)
     for (int c = 0; c < C; ++c) w.line("(ptr)[" + I(c) + " * (stride)] = n" + I(c) + ";");
     w.end();
 
+    // --- lane groups (pair and quad layouts below): the binomial factors of
+    // a slot, (F1, F2) with h = F1 * F2.  Kinds: 'n' a count, 'd' n (n-1)
+    // of a count, '1' one, 'h' one half.
+    struct Fac {
+        char kind;
+        int cell;
+        bool operator==(const Fac &o) const { return kind == o.kind && cell == o.cell; }
+    };
+    auto factors = [&](int si) -> std::pair<Fac, Fac> {
+        const Fac one{'1', -1};
+        if (si < 0) return {one, one};
+        const Slot &sl = f.slots[si];
+        if (sl.n_react == 1 && sl.react_mult[0] == 1) return {Fac{'n', sl.react_cell[0]}, one};
+        if (sl.n_react == 1 && sl.react_mult[0] == 2)
+            return {Fac{'d', sl.react_cell[0]}, Fac{'h', -1}};
+        if (sl.n_react == 2) return {Fac{'n', sl.react_cell[0]}, Fac{'n', sl.react_cell[1]}};
+        return {one, one};
+    };
+    auto fexpr = [&](const Fac &a) -> std::string {
+        switch (a.kind) {
+        case 'n': return "c" + I(a.cell) + "_";
+        case 'd': return "(c" + I(a.cell) + "_ * m" + I(a.cell) + "_)";
+        case 'h': return "0.5";
+        default: return "1.0";
+        }
+    };
+
     // --- pair layout: two lanes per trajectory.  Lane h (0 or 1) of a pair
     // holds leaves [h*B, (h+1)*B) of the same canonical tree (B = P/2): the
     // root is its half plus the partner's, the root decision is taken by
@@ -613,31 +640,6 @@ std::string codegen_lane(const Flat &f)
             w.line("K" + I(i) + " = (h) ? " + Rs + " : " + Ls + ";");
         }
         w.end();
-        // binomial factors of a slot: (F1, F2) with h = F1 * F2.  Kinds:
-        // 'n' a count, 'd' n (n-1) of a count, '1' one, 'h' one half.
-        struct Fac {
-            char kind;
-            int cell;
-            bool operator==(const Fac &o) const { return kind == o.kind && cell == o.cell; }
-        };
-        auto factors = [&](int si) -> std::pair<Fac, Fac> {
-            const Fac one{'1', -1};
-            if (si < 0) return {one, one};
-            const Slot &sl = f.slots[si];
-            if (sl.n_react == 1 && sl.react_mult[0] == 1) return {Fac{'n', sl.react_cell[0]}, one};
-            if (sl.n_react == 1 && sl.react_mult[0] == 2)
-                return {Fac{'d', sl.react_cell[0]}, Fac{'h', -1}};
-            if (sl.n_react == 2) return {Fac{'n', sl.react_cell[0]}, Fac{'n', sl.react_cell[1]}};
-            return {one, one};
-        };
-        auto fexpr = [&](const Fac &a) -> std::string {
-            switch (a.kind) {
-            case 'n': return "c" + I(a.cell) + "_";
-            case 'd': return "(c" + I(a.cell) + "_ * m" + I(a.cell) + "_)";
-            case 'h': return "0.5";
-            default: return "1.0";
-            }
-        };
         // the lane's factor: h selects the right or the left slot's.  Two
         // integer-valued factors (a count or one) are selected as integers
         // and converted once (the conversion is exact either way).
@@ -705,6 +707,138 @@ std::string codegen_lane(const Flat &f)
             if (Lv != "0.0") w.line("(x) = " + b + " ? (x) - " + Lv + " : (x);");
             w.line("jj_ = (jj_ << 1) | (" + b + " ? 1 : 0);");
             hbits.push_back(b);
+        }
+        w.line("(j) = jj_;");
+        w.line("}");
+        w.end();
+    }
+
+    // --- quad layout: four lanes per trajectory.  Lane h (0..3) of a quad
+    // holds quarter h, leaves [h*B, (h+1)*B) of the canonical tree
+    // (B = P/4); the two top levels (halves = quarter 0 + quarter 1 and
+    // quarter 2 + quarter 3, root = left half + right half) are formed from
+    // the four quarter sums in every lane.  Leaf position i of a lane is
+    // slot h*B + i: factors are selected by the two bits of h (an empty
+    // slot takes the factors of a present slot of the quad, preferring its
+    // neighbour, since its rate is +0), integer-valued ones as integers.
+    if (P >= 4) {
+        const int B = P / 4;
+        int DB = 0;
+        while ((1 << DB) < B) ++DB;
+        o << "#define CWC_QUAD 1\n#define CWC_QB " << B << "\n";
+        std::vector<char> qz(2 * B, 1);
+        for (int i = 0; i < B; ++i) {
+            bool z = true;
+            for (int k = 0; k < 4; ++k) z = z && f.leaf_slot[k * B + i] < 0;
+            qz[B + i] = z;
+        }
+        for (int i = B - 1; i >= 1; --i) qz[i] = qz[2 * i] && qz[2 * i + 1];
+        auto qv = [&](int i) -> std::string { return qz[i] ? std::string("0.0") : "r" + I(i); };
+        w.begin("CWC_QUAD_DECL");
+        for (int i = 0; i < B; ++i)
+            if (!qz[B + i]) w.line("double KQ" + I(i) + " = 0.0;");
+        for (int i = 1; i < 2 * B; ++i)
+            if (!qz[i]) w.line("double r" + I(i) + " = 0.0;");
+        w.end();
+        // four-way select by the bits of h, folding equal operands
+        auto sel4 = [&](const std::string v[4]) -> std::string {
+            auto sel2 = [&](const std::string &bit, const std::string &a, const std::string &b) {
+                return a == b ? a : "((" + bit + ") ? " + b + " : " + a + ")";
+            };
+            const std::string lo = sel2("(h) & 1", v[0], v[1]);
+            const std::string hi = sel2("(h) & 1", v[2], v[3]);
+            return sel2("(h) & 2", lo, hi);
+        };
+        w.begin("CWC_QUAD_LOAD_K(ptr, h)");
+        for (int i = 0; i < B; ++i) {
+            if (qz[B + i]) continue;
+            std::string v[4];
+            for (int k = 0; k < 4; ++k) {
+                const int sl = f.leaf_slot[k * B + i];
+                v[k] = sl < 0 ? "0.0" : "(ptr)[" + I(f.slots[sl].rule) + "]";
+            }
+            w.line("KQ" + I(i) + " = " + sel4(v) + ";");
+        }
+        w.end();
+        w.begin("CWC_QUAD_TREE(h)");
+        w.line("{");
+        for (int c = 0; c < C; ++c) {
+            if (need_c[c]) w.line("const double c" + I(c) + "_ = (double)n" + I(c) + ";");
+            if (need_d[c])
+                w.line("const double m" + I(c) + "_ = (double)(n" + I(c) + " > 0 ? n" + I(c) + " - 1 : 0);");
+        }
+        for (int i = 0; i < B; ++i) {
+            if (qz[B + i]) continue;
+            std::pair<Fac, Fac> fk[4];
+            int sl[4];
+            for (int k = 0; k < 4; ++k) {
+                sl[k] = f.leaf_slot[k * B + i];
+                fk[k] = factors(sl[k]);
+            }
+            for (int k = 0; k < 4; ++k) {
+                if (sl[k] >= 0) continue;
+                for (int alt : {k ^ 1, k ^ 2, k ^ 3})
+                    if (sl[alt] >= 0) {
+                        fk[k] = fk[alt];
+                        break;
+                    }
+            }
+            auto fsel4 = [&](bool second) -> std::string {
+                Fac g[4];
+                for (int k = 0; k < 4; ++k) g[k] = second ? fk[k].second : fk[k].first;
+                bool all_int = true, all_eq = true;
+                for (int k = 0; k < 4; ++k) {
+                    all_int = all_int && (g[k].kind == 'n' || g[k].kind == '1');
+                    all_eq = all_eq && g[k] == g[0];
+                }
+                if (all_eq) return fexpr(g[0]);
+                std::string v[4];
+                if (all_int) {
+                    for (int k = 0; k < 4; ++k) v[k] = g[k].kind == 'n' ? "n" + I(g[k].cell) : std::string("1");
+                    return "(double)" + sel4(v);
+                }
+                for (int k = 0; k < 4; ++k) v[k] = fexpr(g[k]);
+                return sel4(v);
+            };
+            const std::string F1 = fsel4(false), F2 = fsel4(true);
+            std::string H;
+            if (F2 == "1.0") H = F1;
+            else H = "(" + F1 + " * " + F2 + ")";
+            w.line("r" + I(B + i) + " = " + (H == "1.0" ? "KQ" + I(i) : "KQ" + I(i) + " * " + H) + ";");
+        }
+        for (int i = B - 1; i >= 1; --i) {
+            if (qz[i]) continue;
+            if (!qz[2 * i] && !qz[2 * i + 1]) w.line("r" + I(i) + " = r" + I(2 * i) + " + r" + I(2 * i + 1) + ";");
+            else if (!qz[2 * i]) w.line("r" + I(i) + " = r" + I(2 * i) + ";");
+            else w.line("r" + I(i) + " = r" + I(2 * i + 1) + ";");
+        }
+        w.line("}");
+        w.end();
+        o << "#define CWC_QUAD_PART " << qv(1) << "\n";
+        // descent inside the lane's quarter (same narrowing as CWC_DESCEND)
+        w.begin("CWC_QUAD_DESCEND(x, j)");
+        w.line("{");
+        w.line("int jj_ = 0;");
+        std::vector<std::string> qbits;
+        int qtmp = 0;
+        for (int d = 0; d < DB; ++d) {
+            std::vector<std::string> vals;
+            for (int m = 0; m < (2 << d); ++m) vals.push_back(qv((2 << d) + m));
+            const Narrowed nw = narrow_pair(vals, qbits, "w", qtmp, &w);
+            const std::string Lv = nw.L, Rv = nw.R;
+            if (Rv == "0.0") {
+                w.line("jj_ = jj_ << 1;");
+                qbits.push_back("");
+                continue;
+            }
+            const std::string b = "g" + I(d) + "_";
+            if (Lv == "0.0")
+                w.line("const bool " + b + " = (" + Rv + " != 0.0);");
+            else
+                w.line("const bool " + b + " = ((x) >= " + Lv + ") && (" + Rv + " != 0.0);");
+            if (Lv != "0.0") w.line("(x) = " + b + " ? (x) - " + Lv + " : (x);");
+            w.line("jj_ = (jj_ << 1) | (" + b + " ? 1 : 0);");
+            qbits.push_back(b);
         }
         w.line("(j) = jj_;");
         w.line("}");

@@ -266,17 +266,21 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
         return set_err(CWC_E_INVALID, "sample_slots must be a power of two, at most 64");
     int layout = f.layout;
     const bool pair = tun.lanes_per_replica == 2;
-    if (tun.lanes_per_replica == 1 || pair) layout = 0;
+    const bool quad = tun.lanes_per_replica == 4;
+    if (tun.lanes_per_replica == 1 || pair || quad) layout = 0;
     else if (tun.lanes_per_replica == 64) layout = 1;
     else if (tun.lanes_per_replica != 0)
-        return set_err(CWC_E_UNSUPPORTED, "lanes_per_replica must be 0 (auto), 1, 2 or 64");
+        return set_err(CWC_E_UNSUPPORTED, "lanes_per_replica must be 0 (auto), 1, 2, 4 or 64");
     {
         cwc_status lst = ensure_layout(const_cast<cwc_model *>(m), layout);
         if (lst != CWC_OK) return lst;
     }
     if (pair && !m->pair_fn[0])
         return set_err(CWC_E_UNSUPPORTED, "two lanes per trajectory need at least two leaves");
-    tun.lanes_per_replica = layout == 1 ? 64 : (pair ? 2 : 1);   // as launched
+    if (quad && !m->quad_fn[0])
+        return set_err(CWC_E_UNSUPPORTED, "four lanes per trajectory need at least four leaves");
+    const int group = quad ? 4 : (pair ? 2 : 1);   // lanes per trajectory (lane module)
+    tun.lanes_per_replica = layout == 1 ? 64 : group;   // as launched
 
     auto r = new cwc_run();
     r->ctx = ctx;
@@ -376,9 +380,10 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
         r->block /= 2;
     if (!wave && cwc_lane_lds_bytes(C, 1, tun.sample_slots) > ctx->max_lds)
         return set_err(CWC_E_INVALID, "sample_slots too large for this model's cells");
-    // lane layout: one trajectory per lane (two in the pair form);
+    // lane layout: one trajectory per lane (two or four lanes per trajectory
+    // in the pair and quad forms);
     // wavefront layout: one per wave
-    const long long per_block = wave ? r->block / 64 : (pair ? r->block / 2 : r->block);
+    const long long per_block = wave ? r->block / 64 : r->block / group;
     const long long need_blocks = (G + per_block - 1) / per_block;
     if (d->mode == CWC_MODE_PERSISTENT) {
         long long resident = (long long)ctx->n_cu * 4 * tun.waves_per_simd * 64 / r->block;
@@ -387,10 +392,11 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
         // to refill: the queue would stay empty, so the kernel without the
         // refill bookkeeping runs the same computation
         const bool covers = (long long)r->grid * per_block >= G;
-        r->fn = pair ? m->pair_fn[covers ? (shared ? 0 : 1) : (shared ? 2 : 3)]
-                     : m->fn[layout][covers ? (shared ? 0 : 1) : (shared ? 2 : 3)];
+        const int k = covers ? (shared ? 0 : 1) : (shared ? 2 : 3);
+        r->fn = quad ? m->quad_fn[k] : (pair ? m->pair_fn[k] : m->fn[layout][k]);
     } else {
-        r->fn = pair ? m->pair_fn[shared ? 0 : 1] : m->fn[layout][shared ? 0 : 1];
+        const int k = shared ? 0 : 1;
+        r->fn = quad ? m->quad_fn[k] : (pair ? m->pair_fn[k] : m->fn[layout][k]);
         r->grid = (unsigned)need_blocks;
     }
     r->n_threads = (unsigned long long)r->grid * (unsigned long long)per_block;

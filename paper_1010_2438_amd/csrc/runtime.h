@@ -46,6 +46,8 @@ struct cwc_model {
     std::string source[2];              // per layout, generated on demand
     hipModule_t module[2] = {nullptr, nullptr};
     hipFunction_t fn[2][6] = {};        // [layout][plain/persistent/slice x shared/table]
+    hipFunction_t quad_fn[4] = {};      // lane module's quad kernels (plain/persistent x
+                                        // shared/table); null with fewer than four leaves
     hipFunction_t pair_fn[6] = {};      // lane module's pair kernels (plain/persistent/
                                         // slice x shared/table); null with one leaf
     std::mutex mu;

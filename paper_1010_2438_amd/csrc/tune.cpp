@@ -115,12 +115,13 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
     const bool persistent = d->mode == CWC_MODE_PERSISTENT;
     const int C = m->flat.n_cells;
     // stage 1 and 2 candidates: layout x block shape (x resident waves)
-    // lanes per trajectory: 1 and (two or more leaves) 2 in the lane
-    // layout's module, 64 in the wavefront layout
+    // lanes per trajectory: 1, 2 (two or more leaves) and 4 (four or more)
+    // in the lane layout's module, 64 in the wavefront layout
     std::vector<int> lprs;
     if (m->fits[0]) {
         lprs.push_back(1);
         if (m->flat.n_leaves >= 2) lprs.push_back(2);
+        if (m->flat.n_leaves >= 4) lprs.push_back(4);
     }
     if (m->fits[1]) lprs.push_back(64);
     std::vector<cwc_tuning> cands;
@@ -160,10 +161,15 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
     // layout more than 1.5x slower than the fastest one is not searched
     // further
     auto layout_of = [](const cwc_tuning &c) {
-        return c.lanes_per_replica == 64 ? 2 : (c.lanes_per_replica == 2 ? 1 : 0);
+        switch (c.lanes_per_replica) {
+        case 64: return 3;
+        case 4: return 2;
+        case 2: return 1;
+        default: return 0;
+        }
     };
-    double lay_ms[3] = {-1.0, -1.0, -1.0};
-    size_t lay_first[3] = {cands.size(), cands.size(), cands.size()};
+    double lay_ms[4] = {-1.0, -1.0, -1.0, -1.0};
+    size_t lay_first[4] = {cands.size(), cands.size(), cands.size(), cands.size()};
     for (size_t i = 0; i < cands.size(); ++i) {
         const int lay = layout_of(cands[i]);
         if (lay_first[lay] != cands.size()) continue;
@@ -172,7 +178,7 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
         if (lay_ms[lay] < 0) return st;
     }
     double fastest = 1e300;
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < 4; ++l)
         if (lay_ms[l] >= 0) fastest = std::min(fastest, lay_ms[l]);
     // stage 2: every shape of the remaining layouts
     double best = 1e300;
@@ -190,7 +196,15 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
         if (t < 0) return st;
         consider(cands[i], t);
     }
-    if (layout_of(bt) != 2) {
+    if (layout_of(bt) != 3) {
+        // stages 3 and 4 move away from the defaults (16 accumulator rows,
+        // chunks of 64) only for a gain above the trials' noise (1 %)
+        auto consider_clear = [&](const cwc_tuning &c, double t) {
+            if (t < 0.99 * best) {
+                best = t;
+                bt = c;
+            }
+        };
         // stage 3: sampling-buffer depth for the best shape
         const cwc_tuning shape = bt;
         for (int ds : depths) {
@@ -198,7 +212,7 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
             c.sample_slots = ds;
             double t = trial(ctx, m, td, c, &st);
             if (t < 0) return st;
-            consider(c, t);
+            consider_clear(c, t);
         }
         // stage 4: queue refill granularity
         if (persistent) {
@@ -208,7 +222,7 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
                 c.refill_chunk = ch;
                 double t = trial(ctx, m, td, c, &st);
                 if (t < 0) return st;
-                consider(c, t);
+                consider_clear(c, t);
             }
         }
     }

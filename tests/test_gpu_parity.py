@@ -313,6 +313,81 @@ def test_pair_layout_refill(ctx, chunk):
     compare_stats(g, orc)
 
 
+
+QUAD = {"lanes_per_replica": 4, "block_size": 64, "waves_per_simd": 1}
+
+
+@pytest.mark.parametrize("name", ["transport", "receptor_binding", "lotka_volterra",
+                                  "transport7"])
+def test_quad_layout_small_models(ctx, name):
+    """Four lanes per trajectory: bit-identical to the oracle in both forms."""
+    m = W.transport(n_children=7) if name == "transport7" else getattr(W, name)()
+    run = W.make_run(seed=17, replicas=300, dt=0.25, n_samples=41)
+    check(ctx, m, run, tuning=QUAD)
+
+
+def test_quad_layout_gene_regulation_tables_and_wide_tree(ctx):
+    """Four lanes per trajectory on configuration 1's model (ragged 333
+    replicas), with per-instance rate rows, and on a 64-leaf tree."""
+    m, run = W.config(1, replicas=333)
+    check(ctx, m, dict(run, n_samples=41), tuning=QUAD)
+    tab, _ = W.sweep_rate_table(m, 4096, 2)
+    check(ctx, m, W.make_run(seed=0, n_instances=24, replicas=5, dt=0.5, n_samples=21,
+                             rate_table=tab[:24]), tuning=QUAD)
+    check(ctx, W.multi_compartment(3, n_cells_=1),
+          W.make_run(seed=5, replicas=300, dt=0.25, n_samples=41), tuning=QUAD)
+
+
+def test_quad_layout_statuses_and_large_changes(ctx):
+    m, run = W.config(0, replicas=70)
+    check(ctx, m, dict(run, max_events=20000), tuning=QUAD)
+    check(ctx, m, dict(run, count_cap=1010), tuning=QUAD)
+    lv = W.lotka_volterra(x0=100, y0=100, k=(1.0, 0.01, 1.0))
+    init = np.array([[100, 100], [50, 20], [0, 30], [7, 0]], np.int32)
+    check(ctx, lv, W.make_run(seed=11, n_instances=4, replicas=17, dt=0.1, n_samples=31,
+                              init_table=init), tuning=QUAD)
+    bm = bursts()
+    brun = W.make_run(seed=13, replicas=300, dt=0.1, n_samples=21)
+    check(ctx, bm, brun, tuning=QUAD)
+    check(ctx, bm, dict(brun, count_cap=4000), tuning=QUAD)
+
+
+_refill4_oracle = {}
+
+
+def refill_case4():
+    """refill_case's sweep on a four-leaf model (A <-> B, A -> 0, 0 -> A)."""
+    m = W._single("iso4", ["A", "B"], [W._local(0, {0: 1}, {1: 1}, 1.0),
+                                       W._local(0, {1: 1}, {0: 1}, 3.0),
+                                       W._local(0, {0: 1}, {}, 0.2),
+                                       W._local(0, {}, {0: 1}, 2.0)], [12, 0])
+    tab, _ = W.sweep_rate_table(m, 2800, 5)
+    run = W.make_run(seed=23, n_instances=2800, replicas=37, dt=0.2, n_samples=11,
+                     rate_table=tab)
+    if "o" not in _refill4_oracle:
+        _refill4_oracle["o"] = oracle.simulate(m, run, want_samples=True, threads=8)
+    return m, run, _refill4_oracle["o"]
+
+
+@pytest.mark.parametrize("chunk", [1, 64])
+def test_quad_layout_refill(ctx, chunk):
+    """Quads claiming queue items (103,600 trajectories, more than the
+    resident quads)."""
+    m, run, orc = refill_case4()
+    g = gpu_run(ctx, model(ctx, m), run, mode="persistent",
+                tuning=dict(QUAD, refill_chunk=chunk))
+    compare_trajectories(g, orc)
+    compare_stats(g, orc)
+
+
+def test_quad_layout_needs_four_leaves(ctx):
+    from paper_1010_2438_amd import CwcError
+    decay2 = W._single("decay2", ["A", "B"], [W._local(0, {0: 1}, {}, 2.0),
+                                              W._local(0, {1: 1}, {}, 1.0)], [5, 3])
+    with pytest.raises(CwcError) as e:
+        gpu_run(ctx, model(ctx, decay2), W.make_run(replicas=8, n_samples=3), tuning=QUAD)
+    assert e.value.code == -2
+
 # ---------------------------------------------------------------- wave layout
 
 def test_config3_multicompartment(ctx):
