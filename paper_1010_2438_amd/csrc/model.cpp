@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <set>
 #include <functional>
 #include <sstream>
 
@@ -988,10 +989,18 @@ std::string codegen_wave(const Flat &f)
     w.end();
 
     // leaves: per position, the formula of the lane's kind (0 if none)
+    // Leaves: a lane evaluates the formulas of its kind only.  The first
+    // count factor of each formula is multiplied by the lane's kind mask
+    // (1.0 for the formula's kind, else 0.0): k * (x * 1) is k * x and
+    // k * (x * 0) is +0 (every factor is finite and non-negative), so no
+    // per-leaf select by kind is needed; a leaf position that several kinds
+    // use sums their formulas, of which at most one is non-zero.
     w.begin("CWC_LEAVES(kind)");
     w.line("{");
     std::vector<char> used_c(NS, 0), used_d(NS, 0), used_p(NS, 0), used_pd(NS, 0), used_w(NS, 0),
         used_wd(NS, 0);
+    std::set<std::pair<int, std::string>> masked;   // (kind, factor variable)
+    std::vector<char> kind_used(kinds.size(), 0);
     // representative compartment of each kind, to resolve regions
     std::vector<int> rep(kinds.size(), -1);
     for (int q = 0; q < f.n_comp; ++q)
@@ -999,6 +1008,7 @@ std::string codegen_wave(const Flat &f)
     std::vector<std::vector<std::string>> form(PL, std::vector<std::string>(kinds.size(), "0.0"));
     for (size_t kd = 0; kd < kinds.size(); ++kd) {
         const int q = rep[kd];
+        const std::string mk = "mk" + I((int)kd) + "_";
         for (int l = 0; l < PL; ++l) {
             int si = f.leaf_slot[q * PL + l];
             if (si < 0) continue;
@@ -1013,14 +1023,23 @@ std::string codegen_wave(const Flat &f)
                 else (dec ? used_wd : used_w)[spi] = 1;
                 return (dec ? "m" : "x") + v + "_";
             };
+            // the first factor, masked by the kind
+            auto cvm = [&](int cell) {
+                const std::string v = cv(cell, false);
+                masked.insert({(int)kd, v});
+                return v + "k" + I((int)kd) + "_";
+            };
+            kind_used[kd] = 1;
             if (s.n_react == 1 && s.react_mult[0] == 1) {
-                h = cv(s.react_cell[0], false);
+                h = cvm(s.react_cell[0]);
             } else if (s.n_react == 1 && s.react_mult[0] == 2) {
-                h = "((" + cv(s.react_cell[0], false) + " * " + cv(s.react_cell[0], true) + ") * 0.5)";
+                h = "((" + cvm(s.react_cell[0]) + " * " + cv(s.react_cell[0], true) + ") * 0.5)";
             } else if (s.n_react == 2) {
-                h = "(" + cv(s.react_cell[0], false) + " * " + cv(s.react_cell[1], false) + ")";
+                h = "(" + cvm(s.react_cell[0]) + " * " + cv(s.react_cell[1], false) + ")";
+            } else {
+                h = mk;   // order 0: the rate itself, masked
             }
-            form[l][kd] = "k" + I(s.rule) + (h.empty() ? "" : " * " + h);
+            form[l][kd] = "k" + I(s.rule) + " * " + h;
         }
     }
     for (int s = 0; s < NS; ++s) {
@@ -1031,15 +1050,22 @@ std::string codegen_wave(const Flat &f)
         if (used_w[s] || used_wd[s]) w.line("const double xnw" + I(s) + "_ = (double)nw" + I(s) + ";");
         if (used_wd[s]) w.line("const double mnw" + I(s) + "_ = (double)(nw" + I(s) + " > 0 ? nw" + I(s) + " - 1 : 0);");
     }
+    for (size_t kd = 0; kd < kinds.size(); ++kd)
+        if (kind_used[kd])
+            w.line("const double mk" + I((int)kd) + "_ = (kind) == " + I((int)kd) + " ? 1.0 : 0.0;");
+    for (auto &mv : masked)
+        w.line("const double " + mv.second + "k" + I(mv.first) + "_ = " + mv.second + " * mk" + I(mv.first) + "_;");
     std::vector<char> zero(2 * PL, 1);
     for (int l = 0; l < PL; ++l) {
         bool any = false;
         for (size_t kd = 0; kd < kinds.size(); ++kd) any |= form[l][kd] != "0.0";
         zero[PL + l] = !any;
         if (!any) continue;
-        std::string e = "0.0";
-        for (size_t kd = kinds.size(); kd-- > 0;)
-            if (form[l][kd] != "0.0") e = "((kind) == " + I((int)kd) + " ? " + form[l][kd] + " : " + e + ")";
+        std::string e;
+        for (size_t kd = 0; kd < kinds.size(); ++kd) {
+            if (form[l][kd] == "0.0") continue;
+            e = e.empty() ? form[l][kd] : "(" + e + ") + (" + form[l][kd] + ")";
+        }
         w.line("a" + I(PL + l) + " = " + e + ";");
     }
     for (int i = PL - 1; i >= 1; --i) {
