@@ -290,6 +290,50 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
         atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);            \
     } while (0)
 
+// Queue claim of the persistent forms, called by the whole wavefront when
+// some of its lane groups (G lanes per trajectory: 1, 2 or 4) need a new
+// item; `want` is the ballot of the lanes that do.  The wanting groups take
+// the next unclaimed items in lane order with at most one queue atomic per
+// wavefront.  With chunked claims (p.chunk >= 64) they drain the
+// wavefront's window [w_next, w_end) first and claim a new chunk only when
+// it runs short, so a wavefront works on few instances at a time and its
+// accumulator rows fill up.  Returns this lane's item (for the wanting
+// lanes; >= p.G once the queue is exhausted).
+template <int G>
+__device__ __forceinline__ i64 cwc_claim(const cwc_kparams &p, u64 want, i64 &w_next, i64 &w_end)
+{
+    const u64 firsts = G == 1 ? want
+                              : want & (G == 2 ? 0x5555555555555555ull : 0x1111111111111111ull);
+    const int cnt = __popcll(firsts);
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)want) - 1;
+    const int rank = __popcll(firsts & ((1ull << (lane & ~(G - 1))) - 1ull));
+    i64 item;
+    if (p.chunk <= 1) {
+        u64 base = 0;
+        if (lane == leader) base = atomicAdd(p.cursor, (u64)cnt);
+        base = __shfl(base, leader);
+        item = (i64)base + rank;
+    } else {
+        const i64 avail = w_end - w_next;   /* >= 0 */
+        if (avail >= cnt) {
+            item = w_next + rank;
+            w_next += cnt;
+        } else {
+            // cnt - avail <= 64 <= chunk: one new chunk suffices
+            u64 base = 0;
+            if (lane == leader) base = atomicAdd(p.cursor, (u64)p.chunk);
+            base = __shfl(base, leader);
+            const i64 nb = (i64)base;
+            item = rank < avail ? w_next + rank : nb + (rank - avail);
+            w_end = nb + p.chunk < p.G ? nb + p.chunk : p.G;
+            w_next = nb + (cnt - avail);
+            if (w_next > w_end) w_next = w_end;
+        }
+    }
+    return item;
+}
+
 template <bool PERSIST, bool SHARED_K>
 __device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
 {
@@ -318,40 +362,10 @@ __device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
     if (active) CWC_BEGIN(tid);
     for (;;) {
         if (PERSIST) {
-            // lanes whose trajectory ended take the next unclaimed items, in
-            // lane order; at most one queue atomic per wavefront per refill.
-            // With chunked claims they drain the wavefront's window first and
-            // claim a new chunk only when it runs short, so a wavefront works
-            // on few instances at a time and its accumulator rows fill up.
+            // lanes whose trajectory ended take the next unclaimed items
             const u64 want = __ballot(live && !active);
             if (want) {
-                const int cnt = __popcll(want);
-                const int lane = __lane_id();
-                const int leader = __ffsll((long long)want) - 1;
-                const int rank = __popcll(want & ((1ull << lane) - 1ull));
-                i64 item;
-                if (p.chunk <= 1) {
-                    u64 base = 0;
-                    if (lane == leader) base = atomicAdd(p.cursor, (u64)cnt);
-                    base = __shfl(base, leader);
-                    item = (i64)base + rank;
-                } else {
-                    const i64 avail = w_end - w_next;   /* >= 0 */
-                    if (avail >= cnt) {
-                        item = w_next + rank;
-                        w_next += cnt;
-                    } else {
-                        // cnt - avail <= 64 <= chunk: one new chunk suffices
-                        u64 base = 0;
-                        if (lane == leader) base = atomicAdd(p.cursor, (u64)p.chunk);
-                        base = __shfl(base, leader);
-                        const i64 nb = (i64)base;
-                        item = rank < avail ? w_next + rank : nb + (rank - avail);
-                        w_end = nb + p.chunk < p.G ? nb + p.chunk : p.G;
-                        w_next = nb + (cnt - avail);
-                        if (w_next > w_end) w_next = w_end;
-                    }
-                }
+                const i64 item = cwc_claim<1>(p, want, w_next, w_end);
                 if (live && !active) {
                     if (item < p.G) {
                         CWC_BEGIN(item);
@@ -612,33 +626,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
     if (PERSIST) {                                                            \
         const u64 want = __ballot(live && !active);                           \
         if (want) {                                                           \
-            const u64 evens = want & 0x5555555555555555ull;                   \
-            const int cnt = __popcll(evens);                                  \
-            const int lane = __lane_id();                                     \
-            const int leader = __ffsll((long long)want) - 1;                  \
-            const int rank = __popcll(evens & ((1ull << (lane & ~1)) - 1ull)); \
-            i64 item;                                                         \
-            if (p.chunk <= 1) {                                               \
-                u64 base = 0;                                                 \
-                if (lane == leader) base = atomicAdd(p.cursor, (u64)cnt);     \
-                base = __shfl(base, leader);                                  \
-                item = (i64)base + rank;                                      \
-            } else {                                                          \
-                const i64 avail = w_end - w_next;                             \
-                if (avail >= cnt) {                                           \
-                    item = w_next + rank;                                     \
-                    w_next += cnt;                                            \
-                } else {                                                      \
-                    u64 base = 0;                                             \
-                    if (lane == leader) base = atomicAdd(p.cursor, (u64)p.chunk); \
-                    base = __shfl(base, leader);                              \
-                    const i64 nb = (i64)base;                                 \
-                    item = rank < avail ? w_next + rank : nb + (rank - avail); \
-                    w_end = nb + p.chunk < p.G ? nb + p.chunk : p.G;          \
-                    w_next = nb + (cnt - avail);                              \
-                    if (w_next > w_end) w_next = w_end;                       \
-                }                                                             \
-            }                                                                 \
+            const i64 item = cwc_claim<2>(p, want, w_next, w_end);           \
             if (live && !active) {                                            \
                 if (item < p.G) {                                             \
                     CWC_PBEGIN(item);                                         \
@@ -950,33 +938,7 @@ __device__ __forceinline__ void cwc_quad_main(const cwc_kparams &p)
     if (PERSIST) {                                                            \
         const u64 want = __ballot(live && !active);                           \
         if (want) {                                                           \
-            const u64 firsts = want & 0x1111111111111111ull;                  \
-            const int cnt = __popcll(firsts);                                 \
-            const int lane = __lane_id();                                     \
-            const int leader = __ffsll((long long)want) - 1;                  \
-            const int rank = __popcll(firsts & ((1ull << (lane & ~3)) - 1ull)); \
-            i64 item;                                                         \
-            if (p.chunk <= 1) {                                               \
-                u64 base = 0;                                                 \
-                if (lane == leader) base = atomicAdd(p.cursor, (u64)cnt);     \
-                base = __shfl(base, leader);                                  \
-                item = (i64)base + rank;                                      \
-            } else {                                                          \
-                const i64 avail = w_end - w_next;                             \
-                if (avail >= cnt) {                                           \
-                    item = w_next + rank;                                     \
-                    w_next += cnt;                                            \
-                } else {                                                      \
-                    u64 base = 0;                                             \
-                    if (lane == leader) base = atomicAdd(p.cursor, (u64)p.chunk); \
-                    base = __shfl(base, leader);                              \
-                    const i64 nb = (i64)base;                                 \
-                    item = rank < avail ? w_next + rank : nb + (rank - avail); \
-                    w_end = nb + p.chunk < p.G ? nb + p.chunk : p.G;          \
-                    w_next = nb + (cnt - avail);                              \
-                    if (w_next > w_end) w_next = w_end;                       \
-                }                                                             \
-            }                                                                 \
+            const i64 item = cwc_claim<4>(p, want, w_next, w_end);           \
             if (live && !active) {                                            \
                 if (item < p.G) {                                             \
                     CWC_QBEGIN(item);                                         \
