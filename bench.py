@@ -15,8 +15,8 @@ gene-regulation run in both forms, the 32-cell multi-compartment run, the
 serving trace (continuous batching, p50/p99 latency), the VALU roofline of
 the headline kernel and the CPU oracle on the host cores.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on
-one GPU.
+Prints one JSON line.  ``--gpus`` above 1 is refused: the benchmark runs
+on one GPU.
 """
 import argparse
 import json
