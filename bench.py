@@ -60,10 +60,11 @@ def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None, e2e=Fal
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     mean, var, n = r.stats()
+    kernel = r.kernel_name()
     r.close()
     sim_ms = sum(s[0] for s in sims) / len(sims)
     tot_ms = sum(s[1] for s in sims) / len(sims)
-    out = {"events_per_step": events, "ms_per_step": 1e3 * wall / steps,
+    out = {"kernel": kernel, "events_per_step": events, "ms_per_step": 1e3 * wall / steps,
            "events_per_s": events * steps / wall, "kernel_ms": sim_ms,
            "launch_ms": tot_ms, "finite_mean": bool((mean == mean).all())}
     if e2e:
@@ -222,14 +223,6 @@ def measured_traffic(source, kernel):
     return int(fig["traffic_bytes_per_launch"])
 
 
-def kernel_name(tuning, mode):
-    """The simulation kernel a run with this tuning dispatches (the lane
-    layout's module also holds the pair and quad kernels)."""
-    lpr = (tuning or {}).get("lanes_per_replica", 1)
-    fam = {2: "cwc_pair", 4: "cwc_quad", 64: "cwc_wave"}.get(lpr, "cwc_lane")
-    return "%s_%s_table" % (fam, mode)
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,7 +278,7 @@ def main():
                "sample_slots": ns}
         t2q = dict(t2p)
     else:
-        t2p = model2.autotune(run2, "persistent", budget_s=3.0)
+        t2p = model2.autotune(run2, "persistent", budget_s=5.0)
         t2q = model2.autotune(run2, "plain", budget_s=1.0)
     log("sweep: %s, %.1f algorithmic VALU slots/event; tuned persistent %s plain %s"
         % (model2.info, alg2, t2p, t2q))
@@ -341,8 +334,8 @@ def main():
     achieved = pers["events_per_step"] * alg2 / (pers["kernel_ms"] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_VALU_SLOTS,
-                "traffic": measured_traffic(model2.source(), kernel_name(t2p, "persistent")),
-                "kernel": kernel_name(t2p, "persistent"),
+                "traffic": measured_traffic(model2.source(), pers["kernel"]),
+                "kernel": pers["kernel"],
                 "work_unit": "%.1f VALU issue slots per applied event" % alg2}
     cpu = None
     if not args.no_cpu:

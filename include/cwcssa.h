@@ -185,7 +185,11 @@ cwc_status cwc_codegen(const cwc_model_desc *d, char *buf, size_t cap,
 
 typedef struct {
     int32_t block_size;        /* threads per block, multiple of 64; 0 = auto */
-    int32_t waves_per_simd;    /* persistent grid: resident waves per SIMD    */
+    int32_t waves_per_simd;    /* persistent grid: requested waves per SIMD
+                                  (1..16; 0 = 2).  More than fit wait for the
+                                  hardware dispatcher; a grid that holds every
+                                  trajectory runs without the queue, its items
+                                  still claimed longest-first               */
     int32_t refill_chunk;      /* persistent, lane layout: 1 = each idle lane
                                   claims one item from the global queue;
                                   >= 64 = a wavefront claims this many
@@ -246,6 +250,12 @@ cwc_status cwc_run_wait_for(cwc_run *r, double timeout_s);
 /* Device time of the last launch of the simulation kernel (HIP events on
  * the run's stream), and of the whole launch sequence. */
 cwc_status cwc_run_elapsed(cwc_run *r, float *sim_ms, float *total_ms);
+/* Name of the simulation kernel the run dispatches (NUL-terminated) copied
+ * into buf if it fits; *len receives the required size including the NUL.
+ * The persistent form runs a "*_persistent_*" kernel when its grid drains
+ * the queue and a "*_plain_*" kernel (items still in longest-first order)
+ * when its grid already holds every trajectory.  Valid from submission on. */
+cwc_status cwc_run_kernel_name(const cwc_run *r, char *buf, size_t cap, size_t *len);
 
 /* Statistics per (instance, sample, cell): mean and unbiased variance
  * (NaN where fewer than 1 / 2 trajectories contributed) and the number of

@@ -27,7 +27,8 @@ SYMBOLS = [
     "cwc_abi_version", "cwc_last_error", "cwc_ctx_create", "cwc_ctx_destroy",
     "cwc_model_create", "cwc_model_get_info", "cwc_model_source",
     "cwc_model_destroy", "cwc_model_describe", "cwc_codegen", "cwc_run_submit", "cwc_run_relaunch",
-    "cwc_run_query", "cwc_run_wait", "cwc_run_wait_for", "cwc_run_elapsed", "cwc_run_fetch_stats",
+    "cwc_run_query", "cwc_run_wait", "cwc_run_wait_for", "cwc_run_elapsed", "cwc_run_kernel_name",
+    "cwc_run_fetch_stats",
     "cwc_run_fetch_moments", "cwc_run_fetch_trajectories",
     "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_server_create",
     "cwc_server_submit", "cwc_server_poll", "cwc_server_job_info",
@@ -139,6 +140,7 @@ def load(path: str = LIB_PATH):
         "cwc_run_wait": [P],
         "cwc_run_wait_for": [P, ctypes.c_double],
         "cwc_run_elapsed": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+        "cwc_run_kernel_name": [P, ctypes.c_char_p, S, ctypes.POINTER(S)],
         "cwc_run_fetch_stats": [P, P, P, P, ctypes.c_int],
         "cwc_run_fetch_moments": [P, P, P, P, P, ctypes.c_int],
         "cwc_run_fetch_trajectories": [P, P, ctypes.c_int],
@@ -391,6 +393,15 @@ class Run:
         a, b = ctypes.c_float(), ctypes.c_float()
         check(load().cwc_run_elapsed(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def kernel_name(self) -> str:
+        """Name of the simulation kernel this run dispatches."""
+        L = load()
+        n = ctypes.c_size_t()
+        check(L.cwc_run_kernel_name(self.h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        check(L.cwc_run_kernel_name(self.h, buf, n.value, ctypes.byref(n)))
+        return buf.value.decode()
 
     def stats(self):
         mean = np.empty((self.I, self.K1, self.C), np.float64)

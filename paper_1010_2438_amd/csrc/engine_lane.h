@@ -344,7 +344,7 @@ __device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
 #define CWC_BEGIN(item)                                                       \
     do {                                                                      \
         i64 lg0_ = (item);                                                    \
-        if (PERSIST && p.order) {                                             \
+        if (p.order) {                                                        \
             const u32 grp_ = (u32)(item) / (u32)p.R;                          \
             const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
             lg0_ = (i64)p.order[grp_] * p.R + rep_;                           \
@@ -575,7 +575,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
 #define CWC_PBEGIN(item)                                                      \
     do {                                                                      \
         i64 lg0_ = (item);                                                    \
-        if (PERSIST && p.order) {                                             \
+        if (p.order) {                                                        \
             const u32 grp_ = (u32)(item) / (u32)p.R;                          \
             const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
             lg0_ = (i64)p.order[grp_] * p.R + rep_;                           \
@@ -889,7 +889,7 @@ __device__ __forceinline__ void cwc_quad_main(const cwc_kparams &p)
 #define CWC_QBEGIN(item)                                                      \
     do {                                                                      \
         i64 lg0_ = (item);                                                    \
-        if (PERSIST && p.order) {                                             \
+        if (p.order) {                                                        \
             const u32 grp_ = (u32)(item) / (u32)p.R;                          \
             const u32 rep_ = (u32)(item) - grp_ * (u32)p.R;                   \
             lg0_ = (i64)p.order[grp_] * p.R + rep_;                           \

@@ -122,7 +122,7 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
         if (item >= p.G) break;
         // ---- begin (or resume) trajectory
         i64 lg = item;
-        if (FORM == CWC_FORM_PERSIST && p.order) {
+        if (p.order) {
             const u32 grp = (u32)item / (u32)p.R;
             const u32 rep = (u32)item - grp * (u32)p.R;
             lg = (i64)p.order[grp] * p.R + rep;

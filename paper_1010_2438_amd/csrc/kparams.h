@@ -33,8 +33,10 @@ struct cwc_kparams {
     unsigned long long *s2_lo32;  // [I][K1][C]
     unsigned long long *rec_hist; // [I][K1+1] trajectories by recorded count
     unsigned long long *cursor;   // persistent form: next unclaimed item
-    const int *order;             // persistent form: instance claimed by the
-                                  // i-th group of R items (null = identity)
+    const int *order;             // persistent form (also when its grid holds
+                                  // every item and runs without the queue):
+                                  // instance of the i-th group of R items in
+                                  // claim order (null = identity)
     int nslot;                    // lane layout: accumulator rows per wavefront
                                   // (power of two, 1..64)
     long long chunk;              // persistent lane form: 1 = lanes claim single

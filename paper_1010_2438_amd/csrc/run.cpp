@@ -156,6 +156,16 @@ std::vector<int> instance_order(const Flat &f, const std::vector<double> &rates,
 
 bool valid_rate(double k) { return std::isfinite(k) && k > 0.0 && k <= 1e250; }
 
+// name of kernel k (plain/persistent x shared/table) of a run's family
+std::string kernel_name(int layout, int group, int k)
+{
+    static const char *forms[4] = {"plain_shared", "plain_table", "persistent_shared",
+                                   "persistent_table"};
+    const char *fam = layout == 1 ? "cwc_wave"
+                                  : (group == 4 ? "cwc_quad" : (group == 2 ? "cwc_pair" : "cwc_lane"));
+    return std::string(fam) + "_" + forms[k];
+}
+
 cwc_status ready(cwc_run *r)
 {
     if (!r) return set_err(CWC_E_INVALID, "null run");
@@ -388,15 +398,18 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     if (d->mode == CWC_MODE_PERSISTENT) {
         long long resident = (long long)ctx->n_cu * 4 * tun.waves_per_simd * 64 / r->block;
         r->grid = (unsigned)std::max(1ll, std::min(need_blocks, resident));
-        // a resident grid that already holds every trajectory has nothing
-        // to refill: the queue would stay empty, so the kernel without the
-        // refill bookkeeping runs the same computation
+        // a grid that already holds every trajectory has nothing to refill:
+        // the queue would stay empty, so the kernel without the refill
+        // bookkeeping runs the same computation, its blocks (dispatched as
+        // others finish) taking the items in the same longest-first order
         const bool covers = (long long)r->grid * per_block >= G;
         const int k = covers ? (shared ? 0 : 1) : (shared ? 2 : 3);
         r->fn = quad ? m->quad_fn[k] : (pair ? m->pair_fn[k] : m->fn[layout][k]);
+        r->kernel = kernel_name(layout, group, k);
     } else {
         const int k = shared ? 0 : 1;
         r->fn = quad ? m->quad_fn[k] : (pair ? m->pair_fn[k] : m->fn[layout][k]);
+        r->kernel = kernel_name(layout, group, k);
         r->grid = (unsigned)need_blocks;
     }
     r->n_threads = (unsigned long long)r->grid * (unsigned long long)per_block;
@@ -466,6 +479,14 @@ cwc_status cwc_run_wait_for(cwc_run *r, double timeout_s)
             return set_err(CWC_E_NOTREADY, "run still in flight after %.3f s", timeout_s);
         std::this_thread::sleep_for(std::chrono::microseconds(200));
     }
+}
+
+cwc_status cwc_run_kernel_name(const cwc_run *r, char *buf, size_t cap, size_t *len)
+{
+    if (!r) return set_err(CWC_E_INVALID, "null run");
+    if (len) *len = r->kernel.size() + 1;
+    if (buf && cap >= r->kernel.size() + 1) std::memcpy(buf, r->kernel.c_str(), r->kernel.size() + 1);
+    return CWC_OK;
 }
 
 cwc_status cwc_run_elapsed(cwc_run *r, float *sim_ms, float *total_ms)

@@ -84,6 +84,7 @@ struct cwc_run {
     int K1 = 0, C = 0, mode = 0;
     cwc_tuning tun{};
     cwc_kparams kp{};
+    std::string kernel;                  // name of the simulation kernel dispatched
     hipFunction_t fn = nullptr;
     unsigned grid = 0, block = 0;
     unsigned lds = 0;                   // dynamic LDS bytes per block

@@ -128,7 +128,11 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
     for (int lpr : lprs) {
         for (int bs : {64, 128, 256}) {
             if (persistent) {
-                for (int wps : {1, 2, 4}) cands.push_back(cwc_tuning{bs, wps, 0, lpr, 0});
+                // up to 16 requested waves per SIMD: beyond what fits, the
+                // extra blocks wait for the hardware dispatcher, and a grid
+                // that holds every item runs the queue-free kernel (items
+                // still longest-first), often the fastest for sweeps
+                for (int wps : {1, 2, 4, 8, 16}) cands.push_back(cwc_tuning{bs, wps, 0, lpr, 0});
             } else {
                 cands.push_back(cwc_tuning{bs, 2, 0, lpr, 0});
             }
