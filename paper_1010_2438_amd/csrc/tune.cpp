@@ -124,15 +124,17 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
         if (m->flat.n_leaves >= 4) lprs.push_back(4);
     }
     if (m->fits[1]) lprs.push_back(64);
+    // The first shape of each layout is its strongest guess (largest block,
+    // most waves), which stage 1 uses to compare the layouts.
     std::vector<cwc_tuning> cands;
     for (int lpr : lprs) {
-        for (int bs : {64, 128, 256}) {
+        for (int bs : {256, 128, 64}) {
             if (persistent) {
                 // up to 16 requested waves per SIMD: beyond what fits, the
                 // extra blocks wait for the hardware dispatcher, and a grid
                 // that holds every item runs the queue-free kernel (items
                 // still longest-first), often the fastest for sweeps
-                for (int wps : {1, 2, 4, 8, 16}) cands.push_back(cwc_tuning{bs, wps, 0, lpr, 0});
+                for (int wps : {16, 8, 4, 2, 1}) cands.push_back(cwc_tuning{bs, wps, 0, lpr, 0});
             } else {
                 cands.push_back(cwc_tuning{bs, 2, 0, lpr, 0});
             }
