@@ -388,6 +388,42 @@ def test_quad_layout_needs_four_leaves(ctx):
         gpu_run(ctx, model(ctx, decay2), W.make_run(replicas=8, n_samples=3), tuning=QUAD)
     assert e.value.code == -2
 
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_persistent_grid_holding_every_item(ctx, lanes):
+    """A persistent grid that holds every trajectory (16 requested waves per
+    SIMD) runs the queue-free kernel with the instances still taken
+    longest-first: results are the oracle's, trajectory by trajectory."""
+    from paper_1010_2438_amd import Run
+    m, run, orc = refill_case4() if lanes == 4 else refill_case()
+    tun = {"block_size": 256, "waves_per_simd": 16, "lanes_per_replica": lanes}
+    r = Run(ctx, model(ctx, m), run, mode="persistent", tuning=tun)
+    fam = {1: "cwc_lane", 2: "cwc_pair", 4: "cwc_quad"}[lanes]
+    assert r.kernel_name() == fam + "_plain_table"
+    r.close()
+    g = gpu_run(ctx, model(ctx, m), run, mode="persistent", tuning=tun)
+    compare_trajectories(g, orc)
+    compare_stats(g, orc)
+
+
+def test_kernel_names(ctx):
+    """cwc_run_kernel_name names the dispatched simulation kernel."""
+    from paper_1010_2438_amd import Run
+    m, run, _ = refill_case()
+    mo = model(ctx, m)
+    lv = model(ctx, W.lotka_volterra())
+    lv_run = W.make_run(replicas=64, n_samples=3)
+    cases = [(mo, run, "plain", {"lanes_per_replica": 1}, "cwc_lane_plain_table"),
+             (mo, run, "persistent", {"lanes_per_replica": 2, "block_size": 64,
+                                      "waves_per_simd": 1}, "cwc_pair_persistent_table"),
+             (lv, lv_run, "plain", {"lanes_per_replica": 4}, "cwc_quad_plain_shared"),
+             (lv, lv_run, "persistent", {"lanes_per_replica": 64}, "cwc_wave_plain_shared")]
+    for mobj, rr, mode, tun, name in cases:
+        r = Run(ctx, mobj, rr, mode=mode, tuning=tun)
+        assert r.kernel_name() == name
+        r.wait()
+        r.close()
+
 # ---------------------------------------------------------------- wave layout
 
 def test_config3_multicompartment(ctx):
