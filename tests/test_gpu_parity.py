@@ -240,12 +240,26 @@ def bursts():
     return W._single("bursts", [f"X{i}" for i in range(6)], rules, [0] * 6)
 
 
+def bursts_wide():
+    """bursts() plus 26 isomerisations among four more species: 38 slots,
+    a 64-leaf tree, so the two cells whose change fields do not fit the
+    table take the 64-bit leaf-mask path."""
+    m = bursts()
+    rules = list(m["rules"])
+    for k in range(26):
+        a, c = 6 + (k % 4), 6 + ((k + 1) % 4)
+        rules.append(W._local(0, {a: 1}, {c: 1}, 0.5 + 0.1 * k))
+    return W._single("bursts_wide", ["X%d" % i for i in range(10)], rules,
+                     [0] * 6 + [50, 50, 50, 50])
+
+
+@pytest.mark.parametrize("wide", [False, True])
 @pytest.mark.parametrize("lanes", [1, 2])
-def test_large_changes(ctx, lanes):
+def test_large_changes(ctx, lanes, wide):
     """Large net changes per event, both lane layouts and forms; with a cap
     below the largest burst the trajectories end in overflow with the state
     before the burst."""
-    m = bursts()
+    m = bursts_wide() if wide else bursts()
     tuning = PAIR if lanes == 2 else None
     run = W.make_run(seed=13, replicas=300, dt=0.1, n_samples=21)
     check(ctx, m, run, tuning=tuning)
