@@ -161,12 +161,12 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
 // The event loop is software-pipelined: the draw of event e (E = -ln u_tau,
 // U = u_sel) is ready when the iteration starts, and the draw of event e+1
 // is computed in the same straight-line block as event e's propensities,
-// waiting time, selection and candidate update, so the independent integer
-// (Philox) and floating-point (tree, division, descent) chains overlap.
-// The update is committed unless something rare happens -- a sample time
-// is crossed, the state is absorbing, a count would exceed the cap, or the
-// event cap is reached -- in which case the slow path handles it in the
-// order the direct method defines.
+// waiting time, selection and (in place) update, so the independent
+// integer (Philox) and floating-point (tree, division, descent) chains
+// overlap.  The update stands unless something rare happens -- a sample
+// time is crossed, the state is absorbing, a count would exceed the cap,
+// or the event cap is reached -- in which case the slow path takes it
+// back and handles the event in the order the direct method defines.
 
 #define CWC_LANE_LOCALS                                                       \
     const double INF = __longlong_as_double(0x7FF0000000000000ll);            \
