@@ -209,12 +209,14 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
             int base = 0;
             // level l splits the current block of 2^l lanes into halves whose
             // sums sit in the level-(l-1) butterfly values of their first lanes
+            // (R != 0 is bit base + half of a ballot of v != 0 in every
+            // lane: one vector compare instead of reading R's two halves)
 #define CWC_XLEVEL(l, v)                                                      \
             if (CWC_LP >= (l)) {                                              \
                 const int half_ = 1 << ((l) - 1);                             \
                 const double L_ = cwc_rl((v), base);                          \
-                const double R_ = cwc_rl((v), base + half_);                  \
-                if (x >= L_ && R_ != 0.0) {                                   \
+                const u64 nz_ = __ballot((v) != 0.0);                         \
+                if (x >= L_ && ((nz_ >> (base + half_)) & 1ull)) {            \
                     x = x - L_;                                               \
                     base += half_;                                            \
                 }                                                             \

@@ -1094,9 +1094,12 @@ std::string codegen_wave(const Flat &f)
             emit(L, depth + 1);
             return;
         }
+        // R != 0 in lane b is bit b of a ballot of that comparison in every
+        // lane (one vector compare instead of reading R's two halves)
         const std::string Lv = zero[L] ? "0.0" : "cwc_rl(a" + I(L) + ", (b))";
-        w.line(ind + "{ const double L_ = " + Lv + "; const double R_ = cwc_rl(a" + I(R) + ", (b));");
-        w.line(ind + "if ((x) >= L_ && R_ != 0.0) { (x) = (x) - L_;");
+        w.line(ind + "{ const double L_ = " + Lv + "; const unsigned long long nz_ = __ballot(a" + I(R) +
+               " != 0.0);");
+        w.line(ind + "if ((x) >= L_ && ((nz_ >> (b)) & 1ull)) { (x) = (x) - L_;");
         emit(R, depth + 1);
         w.line(ind + "} else {");
         emit(L, depth + 1);
