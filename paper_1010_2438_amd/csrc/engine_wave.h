@@ -209,15 +209,16 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
             int base = 0;
             // level l splits the current block of 2^l lanes into halves whose
             // sums sit in the level-(l-1) butterfly values of their first lanes
-            // (R != 0 is bit base + half of a ballot of v != 0 in every
-            // lane: one vector compare instead of reading R's two halves)
+            // (x >= L is bit base and R != 0 bit base + half of ballots of
+            // those comparisons in every lane -- x is the same in all lanes;
+            // L is read from lane base only when the descent goes right)
 #define CWC_XLEVEL(l, v)                                                      \
             if (CWC_LP >= (l)) {                                              \
                 const int half_ = 1 << ((l) - 1);                             \
-                const double L_ = cwc_rl((v), base);                          \
+                const u64 ge_ = __ballot(x >= (v));                           \
                 const u64 nz_ = __ballot((v) != 0.0);                         \
-                if (x >= L_ && ((nz_ >> (base + half_)) & 1ull)) {            \
-                    x = x - L_;                                               \
+                if (((ge_ >> base) & (nz_ >> (base + half_))) & 1ull) {       \
+                    x = x - cwc_rl((v), base);                                \
                     base += half_;                                            \
                 }                                                             \
             }

@@ -1094,12 +1094,17 @@ std::string codegen_wave(const Flat &f)
             emit(L, depth + 1);
             return;
         }
-        // R != 0 in lane b is bit b of a ballot of that comparison in every
-        // lane (one vector compare instead of reading R's two halves)
-        const std::string Lv = zero[L] ? "0.0" : "cwc_rl(a" + I(L) + ", (b))";
-        w.line(ind + "{ const double L_ = " + Lv + "; const unsigned long long nz_ = __ballot(a" + I(R) +
-               " != 0.0);");
-        w.line(ind + "if ((x) >= L_ && ((nz_ >> (b)) & 1ull)) { (x) = (x) - L_;");
+        // x >= L and R != 0 in lane b are bit b of ballots of those
+        // comparisons in every lane (x is the same in all lanes); L is read
+        // from lane b only when the descent goes right
+        if (zero[L]) {
+            w.line(ind + "{ const unsigned long long nz_ = __ballot(a" + I(R) + " != 0.0);");
+            w.line(ind + "if ((x) >= 0.0 && ((nz_ >> (b)) & 1ull)) {");
+        } else {
+            w.line(ind + "{ const unsigned long long ge_ = __ballot((x) >= a" + I(L) +
+                   "), nz_ = __ballot(a" + I(R) + " != 0.0);");
+            w.line(ind + "if (((ge_ & nz_) >> (b)) & 1ull) { (x) = (x) - cwc_rl(a" + I(L) + ", (b));");
+        }
         emit(R, depth + 1);
         w.line(ind + "} else {");
         emit(L, depth + 1);
