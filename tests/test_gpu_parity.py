@@ -485,3 +485,24 @@ def test_config3_full_size_sampled(ctx):
     assert np.array_equal(g["s1"][0], S.sum(axis=0).astype(np.uint64))
     sq = (S * S).sum(axis=0)
     assert np.array_equal(g["s2_hi32"][0].astype(np.int64) * 2 ** 32 + g["s2_lo32"][0].astype(np.int64), sq)
+
+
+def test_golden_term_without_rules(ctx):
+    """The Sec. 2.1 term (tests/golden fixture) as a model with no rules:
+    every trajectory is absorbed at t = 0 and every sample holds the term's
+    count cells, with one lane, two lanes or a wavefront per trajectory."""
+    from tests.test_oracle_golden import multiset, read_fixture
+    fx = read_fixture("term_example_sec2_1.txt")
+    sp = fx["species"].split()
+    m = {"name": "term_example", "species": sp,
+         "types": [{"name": "top", "wrap": False}, {"name": fx["comp_type"], "wrap": True}],
+         "compartments": [{"type": 0, "parent": -1}, {"type": 1, "parent": 0}],
+         "init": [multiset(sp, fx["top_content"]), multiset(sp, fx["comp_content"])],
+         "init_wrap": [None, multiset(sp, fx["comp_wrap"])], "rules": []}
+    want = np.array([int(x) for x in fx["cells"].split()], np.int32)
+    run = W.make_run(seed=4, replicas=70, dt=0.5, n_samples=6)
+    for lanes in (1, 2, 64):
+        orc = check(ctx, m, run, tuning={"lanes_per_replica": lanes})
+    assert (orc["samples"] == want).all()
+    assert (orc["events"] == 0).all() and (orc["t_final"] == 0.0).all()
+    assert (orc["status"] == 1).all()
