@@ -423,27 +423,28 @@ std::string codegen_lane(const Flat &f)
     w.end();
 
     // --- net change of the chosen leaf.  Each cell's change over the
-    // leaves is a small integer field; the fields of the cells are packed
-    // into at most two 32-bit words per leaf (first fit, a field never
-    // straddles a word), and the table of these words, one entry per leaf,
-    // is copied to LDS when the block starts: an event reads its leaf's
-    // entry once and extracts each cell's change with one bit-field
-    // extract (signed when the cell can decrease).  Cells whose fields do
-    // not fit take the change from per-digit leaf masks instead:
-    // d = sum_b ((M+_b >> j) & 1) << b - (...).  Nothing is written if any
-    // count would exceed the cap.
+    // leaves is a small integer field (signed when the cell can decrease);
+    // the fields of the cells are packed into 32-bit words per leaf (first
+    // fit, a field never straddles a word), and the table of these words,
+    // one entry per leaf, is copied to LDS when the block starts: an event
+    // reads its leaf's entry once (one LDS load) and takes each cell's
+    // change from it.  In the byte layout the fields are whole bytes or
+    // half-words, so the extension of the field folds into the add of the
+    // count (a sub-dword operand); in the dense layout they have their own
+    // widths in at most two words and are taken with bit-field extracts.
+    // Cells whose fields do not fit take the change from per-digit leaf
+    // masks instead: d = sum_b ((M+_b >> j) & 1) << b - (...).  Nothing is
+    // written if any count would exceed the cap.
     std::vector<std::vector<std::pair<int, int>>> per_cell(C);   // (leaf, delta)
     for (auto &s : f.slots)
         for (auto &dv : s.delta) per_cell[dv.first].push_back({s.leaf, dv.second});
     struct Field { int word = -1, off = 0, width = 0; bool sgn = false; };
     std::vector<Field> field(C);
-    int used[2] = {0, 0};
-    int n_words = 0;
     for (int c = 0; c < C; ++c) {
         if (per_cell[c].empty()) continue;
         int lo = 0, hi = 0;
         for (auto &ld : per_cell[c]) { lo = std::min(lo, ld.second); hi = std::max(hi, ld.second); }
-        Field fd;
+        Field &fd = field[c];
         fd.sgn = lo < 0;
         fd.width = 1;
         if (fd.sgn) {
@@ -451,22 +452,65 @@ std::string codegen_lane(const Flat &f)
         } else {
             while (hi > (1ll << fd.width) - 1) ++fd.width;
         }
-        for (int wd = 0; wd < 2; ++wd)
-            if (used[wd] + fd.width <= 32) {
-                fd.word = wd;
-                fd.off = used[wd];
-                used[wd] += fd.width;
-                n_words = std::max(n_words, wd + 1);
-                break;
-            }
-        field[c] = fd;
     }
+    // Byte layout: every field widened to 8 or 16 bits at an offset that is
+    // a multiple of its width, in up to four words, when the whole table
+    // fits the static LDS reserved for it; a cell's change is then one add
+    // of a sign- or zero-extended byte or half-word of the entry.  Otherwise
+    // the dense layout: fields of their own width, at most two words.
+    int n_words = 0;
+    {
+        std::vector<Field> bf = field;
+        int used[4] = {0, 0, 0, 0}, nw = 0;
+        bool ok = true;
+        for (int c = 0; c < C && ok; ++c) {
+            if (per_cell[c].empty()) continue;
+            Field &fd = bf[c];
+            if (fd.width > 16) { ok = false; break; }
+            fd.width = fd.width <= 8 ? 8 : 16;
+            fd.word = -1;
+            for (int wd = 0; wd < 4 && fd.word < 0; ++wd) {
+                const int off = (used[wd] + fd.width - 1) / fd.width * fd.width;
+                if (off + fd.width <= 32) {
+                    fd.word = wd;
+                    fd.off = off;
+                    used[wd] = off + fd.width;
+                    nw = std::max(nw, wd + 1);
+                }
+            }
+            if (fd.word < 0) ok = false;
+        }
+        if (nw == 3) nw = 4;
+        if (ok && (size_t)P * (size_t)nw * 4u <= kLaneStaticLdsBytes) {
+            field = bf;
+            n_words = nw;
+        } else {
+            int used2[2] = {0, 0};
+            for (int c = 0; c < C; ++c) {
+                if (per_cell[c].empty()) continue;
+                Field &fd = field[c];
+                for (int wd = 0; wd < 2; ++wd)
+                    if (used2[wd] + fd.width <= 32) {
+                        fd.word = wd;
+                        fd.off = used2[wd];
+                        used2[wd] += fd.width;
+                        n_words = std::max(n_words, wd + 1);
+                        break;
+                    }
+            }
+        }
+    }
+    const bool bytes = n_words > 0 && [&] {
+        for (int c = 0; c < C; ++c)
+            if (field[c].word >= 0 && (field[c].width % 8 != 0 || field[c].off % 8 != 0)) return false;
+        return true;
+    }();
     o << "#define CWC_DT_W " << n_words << "\n";
     if (n_words > 0) {
-        // table entry l: word 0 in the low half, word 1 in the high half
-        o << "__constant__ unsigned long long cwc_dtab_g[" << P << "] = {";
+        // table entry l: words 0..n_words-1 of leaf l
+        o << "__constant__ unsigned int cwc_dtab_g[" << P * n_words << "] = {";
         for (int l = 0; l < P; ++l) {
-            unsigned long long v = 0;
+            unsigned long long wv[4] = {0, 0, 0, 0};
             for (int c = 0; c < C; ++c) {
                 if (field[c].word < 0) continue;
                 long long d = 0;
@@ -474,25 +518,22 @@ std::string codegen_lane(const Flat &f)
                     if (ld.first == l) d += ld.second;
                 const unsigned long long bits =
                     (unsigned long long)d & ((1ull << field[c].width) - 1ull);
-                v |= bits << (32 * field[c].word + field[c].off);
+                wv[field[c].word] |= bits << field[c].off;
             }
-            char b[32];
-            std::snprintf(b, sizeof b, "%s0x%llxull", l ? ", " : "", v);
-            o << b;
+            for (int k = 0; k < n_words; ++k) {
+                char b[32];
+                std::snprintf(b, sizeof b, "%s0x%llxu", (l || k) ? ", " : "", wv[k]);
+                o << b;
+            }
         }
         o << "};\n";
         // the block's copy in LDS (every thread of the block passes here
         // before any event)
+        const char *ty = n_words == 1 ? "unsigned int" : n_words == 2 ? "uint2" : "uint4";
         w.begin("CWC_DT_SETUP");
-        if (n_words == 1) {
-            w.line("__shared__ unsigned int cwc_dtab[" + I(P) + "];");
-            w.line("for (int i_ = (int)threadIdx.x; i_ < " + I(P) +
-                   "; i_ += (int)blockDim.x) cwc_dtab[i_] = (unsigned int)cwc_dtab_g[i_];");
-        } else {
-            w.line("__shared__ unsigned long long cwc_dtab[" + I(P) + "];");
-            w.line("for (int i_ = (int)threadIdx.x; i_ < " + I(P) +
-                   "; i_ += (int)blockDim.x) cwc_dtab[i_] = cwc_dtab_g[i_];");
-        }
+        w.line(std::string("__shared__ ") + ty + " cwc_dtab[" + I(P) + "];");
+        w.line("for (int i_ = (int)threadIdx.x; i_ < " + I(P * n_words) +
+               "; i_ += (int)blockDim.x) ((unsigned int *)cwc_dtab)[i_] = cwc_dtab_g[i_];");
         w.line("__syncthreads();");
         w.end();
     } else {
@@ -516,8 +557,11 @@ std::string codegen_lane(const Flat &f)
     if (n_words == 1) {
         w.line("const unsigned dw0_ = cwc_dtab[js_];");
     } else if (n_words == 2) {
-        w.line("const unsigned long long dq_ = cwc_dtab[js_];");
-        w.line("const unsigned dw0_ = (unsigned)dq_, dw1_ = (unsigned)(dq_ >> 32);");
+        w.line("const uint2 dq_ = cwc_dtab[js_];");
+        w.line("const unsigned dw0_ = dq_.x, dw1_ = dq_.y;");
+    } else if (n_words == 4) {
+        w.line("const uint4 dq_ = cwc_dtab[js_];");
+        w.line("const unsigned dw0_ = dq_.x, dw1_ = dq_.y, dw2_ = dq_.z, dw3_ = dq_.w;");
     }
     w.line("unsigned mx_ = 0u;");
     for (int c = 0; c < C; ++c) {
@@ -528,7 +572,14 @@ std::string codegen_lane(const Flat &f)
         const Field &fd = field[c];
         if (fd.word >= 0) {
             const std::string wv = "dw" + I(fd.word) + "_";
-            if (fd.sgn)
+            const std::string sh = fd.off ? "(" + wv + " >> " + I(fd.off) + ")" : wv;
+            if (bytes && fd.sgn)
+                e = std::string("(unsigned)(int)(") + (fd.width == 8 ? "signed char" : "short") +
+                    ")" + sh;
+            else if (bytes)
+                e = std::string("(unsigned)(") + (fd.width == 8 ? "unsigned char" : "unsigned short") +
+                    ")" + sh;
+            else if (fd.sgn)
                 e = "(unsigned)__builtin_amdgcn_sbfe((int)" + wv + ", " + I(fd.off) + "u, " +
                     I(fd.width) + "u)";
             else

@@ -10,6 +10,10 @@
 
 #include "../../include/cwcssa.h"
 
+// LDS a lane-layout kernel may use statically (the per-leaf change table);
+// the host keeps it out of the dynamic LDS it gives a block.
+constexpr size_t kLaneStaticLdsBytes = 64 * 8;
+
 namespace cwc {
 
 struct Slot {

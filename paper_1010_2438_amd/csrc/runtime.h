@@ -65,7 +65,7 @@ inline size_t cwc_lane_lds_bytes(int n_cells, int waves, int nslot)
 }
 constexpr int kDefaultSampleSlots = 16;
 // static LDS of a lane-layout kernel: the per-leaf change table
-constexpr size_t kLaneStaticLds = 64 * 8;
+constexpr size_t kLaneStaticLds = kLaneStaticLdsBytes;
 // Compiles and loads the model's device code for `layout` if needed.
 cwc_status ensure_layout(cwc_model *m, int layout);
 // Directory of the compiled-code cache and the tuning table (created).

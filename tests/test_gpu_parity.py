@@ -228,38 +228,47 @@ def test_config1_full_size_sampled(ctx):
 
 # ---------------------------------------------------------------- pair layout
 
-def bursts():
+def bursts(sizes=(600, 900, 1500, 3000, 5000, 700), name="bursts"):
     """Six species made in bursts of 600 to 5000 molecules and lost one at a
-    time.  The per-leaf change fields (11 to 14 bits) fill both table words
-    and two cells take their change from per-digit leaf masks instead."""
-    sizes = [600, 900, 1500, 3000, 5000, 700]
+    time, and a seventh only made, in bursts of 300.  The change table takes
+    the byte layout: signed half-word fields for the six, an unsigned
+    half-word for the seventh, four words per leaf."""
     rules = []
     for i, b in enumerate(sizes):
         rules.append(W._local(0, {}, {i: b}, 1.0))
         rules.append(W._local(0, {i: 1}, {}, 1.0))
-    return W._single("bursts", [f"X{i}" for i in range(6)], rules, [0] * 6)
+    rules.append(W._local(0, {}, {6: 300}, 0.5))
+    return W._single(name, [f"X{i}" for i in range(7)], rules, [0] * 7)
+
+
+def bursts_dense():
+    """bursts() with one burst of 40000: its 17-bit change field does not fit
+    a half-word, so the table takes the dense layout (fields of their own
+    widths in two words) and the cells that do not fit there take their
+    change from per-digit 32-bit leaf masks."""
+    return bursts(sizes=(600, 900, 1500, 3000, 40000, 700), name="bursts_dense")
 
 
 def bursts_wide():
-    """bursts() plus 26 isomerisations among four more species: 38 slots,
-    a 64-leaf tree, so the two cells whose change fields do not fit the
-    table take the 64-bit leaf-mask path."""
+    """bursts() plus 26 isomerisations among four more species: 39 slots,
+    a 64-leaf tree, so the table takes the dense layout and the cells whose
+    change fields do not fit it take the 64-bit leaf-mask path."""
     m = bursts()
     rules = list(m["rules"])
     for k in range(26):
-        a, c = 6 + (k % 4), 6 + ((k + 1) % 4)
+        a, c = 7 + (k % 4), 7 + ((k + 1) % 4)
         rules.append(W._local(0, {a: 1}, {c: 1}, 0.5 + 0.1 * k))
-    return W._single("bursts_wide", ["X%d" % i for i in range(10)], rules,
-                     [0] * 6 + [50, 50, 50, 50])
+    return W._single("bursts_wide", ["X%d" % i for i in range(11)], rules,
+                     [0] * 7 + [50, 50, 50, 50])
 
 
-@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("table", ["bytes", "dense", "wide"])
 @pytest.mark.parametrize("lanes", [1, 2])
-def test_large_changes(ctx, lanes, wide):
-    """Large net changes per event, both lane layouts and forms; with a cap
-    below the largest burst the trajectories end in overflow with the state
-    before the burst."""
-    m = bursts_wide() if wide else bursts()
+def test_large_changes(ctx, lanes, table):
+    """Large net changes per event, each change-table layout, both lane
+    layouts and forms; with a cap below the largest burst the trajectories
+    end in overflow with the state before the burst."""
+    m = {"bytes": bursts, "dense": bursts_dense, "wide": bursts_wide}[table]()
     tuning = PAIR if lanes == 2 else None
     run = W.make_run(seed=13, replicas=300, dt=0.1, n_samples=21)
     check(ctx, m, run, tuning=tuning)
