@@ -45,16 +45,18 @@ __device__ __forceinline__ void cwc_philox(u32 c0, u32 c1, u32 c2, u32 c3,
     x0 = c0; x1 = c1; x2 = c2; x3 = c3;
 }
 
-// 53 random bits -> binary64, exact.
+// 53 random bits -> binary64, exact: with m = a 2^21 + (b >> 11), the value
+// (m + 1) 2^-53 (resp. m 2^-53) is a 2^-32 + ((b >> 11) + 1) 2^-53.  Both
+// terms are exact, and so is their sum (an integer of at most 53 bits times
+// 2^-53), so a fused multiply-add returns it without any rounding and
+// without assembling m in 64-bit integer arithmetic.
 __device__ __forceinline__ double cwc_u_open0(u32 a, u32 b)   // (0, 1]
 {
-    u64 m = ((u64)a << 21) | (u64)(b >> 11);
-    return (double)(m + 1ull) * 0x1p-53;
+    return __builtin_fma((double)a, 0x1p-32, (double)((b >> 11) + 1u) * 0x1p-53);
 }
 __device__ __forceinline__ double cwc_u_open1(u32 a, u32 b)   // [0, 1)
 {
-    u64 m = ((u64)a << 21) | (u64)(b >> 11);
-    return (double)m * 0x1p-53;
+    return __builtin_fma((double)a, 0x1p-32, (double)(b >> 11) * 0x1p-53);
 }
 
 // ------------------------------------------------------------- ssa_log
