@@ -1,0 +1,153 @@
+"""The generated per-leaf change table, checked on the host: the model's
+CWC_APPLY macro and its table (as the library generates them) are compiled
+with g++ around stand-ins for the two bit-field-extract builtins, every
+leaf's change is applied to a known state, and the result must be the net
+change the oracle's own flattening gives for that leaf (Sec. 2.1: the
+rewrite replaces the matched reactants by the products).  Covers the byte
+layout (signed and unsigned bytes and half-words, 1 to 4 words), the dense
+layout, and the per-digit leaf-mask fallback on 32- and 64-leaf trees."""
+import os
+import re
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+import workloads as W
+from tests.test_gpu_parity import bursts, bursts_dense, bursts_wide
+
+HARNESS = r"""
+#include <cstdio>
+typedef unsigned int u32;
+typedef unsigned long long u64;
+typedef int i32;
+typedef long long i64;
+struct uint2 { unsigned x, y; };
+struct uint4 { unsigned x, y, z, w; };
+#define __constant__
+#define CWC_KEEP(v) ((void)0)
+static inline int host_sbfe(int v, unsigned off, unsigned w) {
+    return (int)((unsigned)v << (32u - off - w)) >> (32u - w);
+}
+static inline unsigned host_ubfe(unsigned v, unsigned off, unsigned w) {
+    return (v >> off) & (w >= 32u ? 0xFFFFFFFFu : ((1u << w) - 1u));
+}
+#define __builtin_amdgcn_sbfe(v, o, w) host_sbfe((v), (o), (w))
+#define __builtin_amdgcn_ubfe(v, o, w) host_ubfe((v), (o), (w))
+%(table)s
+%(apply)s
+%(lds)s
+int main() {
+%(copy)s
+    for (int j = 0; j < %(P)d; ++j) {
+        for (int capcase = 0; capcase < 2; ++capcase) {
+%(decl)s
+            const unsigned cap_ = capcase ? %(base)du : 0xFFFFFFFFu;
+            bool ovf_;
+            { CWC_APPLY(j, cap_, o_); ovf_ = o_; }
+            if (!capcase) {
+                std::printf("%%d", j);
+%(print)s
+            } else {
+                std::printf(" %%d\n", ovf_ ? 1 : 0);
+            }
+        }
+    }
+    return 0;
+}
+"""
+
+BASE = 1 << 20
+
+
+def macro(src, head):
+    i = src.index("#define " + head)
+    j = src.index("/* end */", i)
+    return src[i:j] + "/* end */\n"
+
+
+def applied_changes(model):
+    """(P, C, {leaf: [change per cell]}, {leaf: overflow flag at cap = state})
+    from the generated code."""
+    from paper_1010_2438_amd import cwc_codegen
+    src = cwc_codegen(model)
+    C = int(re.search(r"#define CWC_C (\d+)", src).group(1))
+    P = int(re.search(r"#define CWC_P (\d+)", src).group(1))
+    dtw = int(re.search(r"#define CWC_DT_W (\d+)", src).group(1))
+    table = lds = copy = ""
+    if dtw:
+        table = re.search(r"__constant__ unsigned int cwc_dtab_g\[\d+\] = \{[^}]*\};", src).group(0)
+        ty = re.search(r"__shared__ (\w[\w ]*?) cwc_dtab\[", src).group(1)
+        lds = "static %s cwc_dtab[%d];" % (ty, P)
+        copy = ("    for (int i = 0; i < %d; ++i) ((unsigned *)cwc_dtab)[i] = cwc_dtab_g[i];"
+                % (P * dtw))
+    code = HARNESS % {
+        "table": "#define CWC_DT_W %d\n%s" % (dtw, table),
+        "apply": macro(src, "CWC_APPLY(j, cap, ovf)"), "lds": lds, "copy": copy, "P": P,
+        "base": BASE,
+        "decl": "\n".join("            int n%d = %d;" % (c, BASE) for c in range(C)),
+        "print": "\n".join('                std::printf(" %%d", n%d - %d);' % (c, BASE)
+                           for c in range(C))}
+    d = tempfile.mkdtemp(prefix="cwc_apply_")
+    try:
+        with open(os.path.join(d, "t.cpp"), "w") as f:
+            f.write(code)
+        subprocess.check_call(["g++", "-O1", "-w", "-o", os.path.join(d, "t"),
+                               os.path.join(d, "t.cpp")])
+        out = subprocess.check_output([os.path.join(d, "t")], text=True)
+    finally:
+        shutil.rmtree(d)
+    changes, ovf = {}, {}
+    for line in out.splitlines():
+        v = [int(x) for x in line.split()]
+        changes[v[0]] = v[1:1 + C]
+        ovf[v[0]] = v[1 + C]
+    return P, C, changes, ovf, src
+
+
+MODELS = {
+    "paper_example": W.paper_example,                  # byte layout, unsigned byte
+    "receptor_binding": W.receptor_binding,            # byte layout, two words
+    "transport7": lambda: W.transport(n_children=7),
+    "gene_regulation": lambda: W.config(1)[0],         # byte layout, four words
+    "bursts": bursts,                                  # signed and unsigned half-words
+    "bursts_dense": bursts_dense,                      # dense fields + 32-bit leaf masks
+    "bursts_wide": bursts_wide,                        # dense fields + 64-bit leaf masks
+    "one_cell": lambda: W.multi_compartment(3, n_cells_=1),   # dense, 64 leaves
+}
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+@pytest.mark.parametrize("name", sorted(MODELS))
+def test_generated_change_table(name):
+    model = MODELS[name]()
+    P, C, changes, ovf, src = applied_changes(model)
+    flat = oracle.FlatModel(model)
+    assert (P, C) == (flat.n_leaves, flat.n_cells)
+    for leaf in range(P):
+        want = [0] * C
+        for k in range(int(flat.leaf_ndelta[leaf])):
+            cell, v = (int(x) for x in flat.leaf_delta[leaf, k])
+            want[cell] += v
+        assert changes[leaf] == want, "leaf %d" % leaf
+        # with the cap at the current state, the event overflows exactly
+        # when it raises some count
+        assert ovf[leaf] == int(any(v > 0 for v in want)), "leaf %d" % leaf
+
+
+def test_layouts_covered():
+    """The models above reach every encoding of the table."""
+    from paper_1010_2438_amd import cwc_codegen
+    seen = set()
+    for name, mk in MODELS.items():
+        body = macro(cwc_codegen(mk()), "CWC_APPLY(j, cap, ovf)")
+        for key, pat in (("s8", "(signed char)"), ("u8", "(unsigned char)"),
+                         ("s16", "(short)"), ("u16", "(unsigned short)"),
+                         ("sbfe", "amdgcn_sbfe"), ("ubfe", "amdgcn_ubfe(dw"),
+                         ("mask32", "amdgcn_ubfe(0x"), ("mask64", "(js_ & 32u)"),
+                         ("w4", "uint4 dq_")):
+            if pat in body:
+                seen.add(key)
+    assert seen == {"s8", "u8", "s16", "u16", "sbfe", "ubfe", "mask32", "mask64", "w4"}
