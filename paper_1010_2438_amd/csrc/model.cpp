@@ -459,6 +459,7 @@ std::string codegen_lane(const Flat &f)
     // of a sign- or zero-extended byte or half-word of the entry.  Otherwise
     // the dense layout: fields of their own width, at most two words.
     int n_words = 0;
+    bool bytes = false;   // the byte layout was taken
     {
         std::vector<Field> bf = field;
         int used[4] = {0, 0, 0, 0}, nw = 0;
@@ -484,6 +485,7 @@ std::string codegen_lane(const Flat &f)
         if (ok && (size_t)P * (size_t)nw * 4u <= kLaneStaticLdsBytes) {
             field = bf;
             n_words = nw;
+            bytes = nw > 0;
         } else {
             int used2[2] = {0, 0};
             for (int c = 0; c < C; ++c) {
@@ -500,11 +502,6 @@ std::string codegen_lane(const Flat &f)
             }
         }
     }
-    const bool bytes = n_words > 0 && [&] {
-        for (int c = 0; c < C; ++c)
-            if (field[c].word >= 0 && (field[c].width % 8 != 0 || field[c].off % 8 != 0)) return false;
-        return true;
-    }();
     o << "#define CWC_DT_W " << n_words << "\n";
     if (n_words > 0) {
         // table entry l: words 0..n_words-1 of leaf l

@@ -107,6 +107,15 @@ def applied_changes(model):
     return P, C, changes, ovf, src
 
 
+def huge_burst():
+    """One species made 1,000,000 at a time (the largest net change the
+    library accepts) and lost one at a time: a 21-bit signed field, too
+    wide for the byte layout."""
+    return W._single("huge_burst", ["X"],
+                     [W._local(0, {}, {0: 1_000_000}, 0.01), W._local(0, {0: 1}, {}, 1.0)],
+                     [0])
+
+
 MODELS = {
     "paper_example": W.paper_example,                  # byte layout, unsigned byte
     "receptor_binding": W.receptor_binding,            # byte layout, two words
@@ -116,6 +125,7 @@ MODELS = {
     "bursts_dense": bursts_dense,                      # dense fields + 32-bit leaf masks
     "bursts_wide": bursts_wide,                        # dense fields + 64-bit leaf masks
     "one_cell": lambda: W.multi_compartment(3, n_cells_=1),   # dense, 64 leaves
+    "huge_burst": huge_burst,                          # dense, a 21-bit signed field
 }
 
 
