@@ -223,6 +223,39 @@ def measured_traffic(source, kernel):
     return int(fig["traffic_bytes_per_launch"])
 
 
+def parse_tuning(text):
+    """BLOCK,WAVES_PER_SIMD[,REFILL_CHUNK[,SLOTS[,LANES_PER_REPLICA]]]"""
+    v = [int(x) for x in text.split(",")]
+    return {"block_size": v[0], "waves_per_simd": v[1],
+            "refill_chunk": v[2] if len(v) > 2 else 0,
+            "sample_slots": v[3] if len(v) > 3 else 0,
+            "lanes_per_replica": v[4] if len(v) > 4 else 1}
+
+
+def single_workload(ctx, stream, args):
+    """One workload's persistent form alone (autotuned unless --tuning is
+    given), with the roofline of its kernel, as one JSON line."""
+    import workloads as W
+    from paper_1010_2438_amd import Model
+    m, run = W.config(args.workload)
+    model = Model(ctx, m)
+    alg = model.info["alg_slots_per_event"]
+    tun = parse_tuning(args.tuning) if args.tuning else \
+        model.autotune(run, "persistent", budget_s=2.0)
+    res = time_form(ctx, model, run, "persistent", args.steps, args.warmup, stream, tun)
+    achieved = res["events_per_step"] * alg / (res["kernel_ms"] * 1e-3)
+    print(json.dumps({
+        "workload": W.CONFIG_NAMES[args.workload], "form": "persistent",
+        "events_per_s": res["events_per_s"], "ms_per_step": res["ms_per_step"],
+        "kernel_ms": res["kernel_ms"], "events_per_step": res["events_per_step"],
+        "steps": args.steps, "warmup": args.warmup, "tuning": tun,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                     "peak": PEAK_VALU_SLOTS / 1e12, "unit": "TOP/s",
+                     "frac": achieved / PEAK_VALU_SLOTS, "kernel": res["kernel"],
+                     "work_unit": "%.1f VALU issue slots per applied event" % alg}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,7 +269,11 @@ def main():
                     help="time only the headline kernel (for profiler runs)")
     ap.add_argument("--tuning", default="",
                     metavar="BLOCK,WAVES_PER_SIMD[,REFILL_CHUNK[,SLOTS[,LANES_PER_REPLICA]]]",
-                    help="pin the headline launch shape instead of autotuning it")
+                    help="pin the launch shape (of the headline, or of --workload) instead of autotuning it")
+    ap.add_argument("--workload", type=int, default=0, choices=(0, 1, 3),
+                    help="time only the persistent form of workload 1 (gene regulation, "
+                         "16384 replicas) or 3 (multi-compartment, 2048 replicas) and print "
+                         "its own line (for profiler runs); 0 = the full benchmark")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="copy BYTES device-to-device 5 times and exit (counter calibration)")
     args = ap.parse_args()
@@ -266,16 +303,16 @@ def main():
     stream = torch.cuda.Stream()
     ctx = Context(0)
 
+    if args.workload:
+        single_workload(ctx, stream, args)
+        return
+
     # ---- headline: the batched sweep, persistent vs plain
     m2, run2 = W.config(2)
     model2 = Model(ctx, m2)
     alg2 = model2.info["alg_slots_per_event"]
     if args.tuning:
-        v = [int(x) for x in args.tuning.split(",")]
-        b, w, ch, ns = v[0], v[1], (v[2] if len(v) > 2 else 0), (v[3] if len(v) > 3 else 0)
-        lpr = v[4] if len(v) > 4 else 1
-        t2p = {"block_size": b, "waves_per_simd": w, "refill_chunk": ch, "lanes_per_replica": lpr,
-               "sample_slots": ns}
+        t2p = parse_tuning(args.tuning)
         t2q = dict(t2p)
     else:
         t2p = model2.autotune(run2, "persistent", budget_s=5.0)
