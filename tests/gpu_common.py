@@ -65,3 +65,46 @@ def compare_stats(gpu, orc):
             rel = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
             rel[both_nan] = 0
             assert np.nanmax(rel) <= 1e-12, (key, np.nanmax(rel))
+
+
+def conservation_laws(model):
+    """Integer basis of the vectors w with w . delta = 0 for the net change
+    delta of every slot (exact rational elimination over the oracle's
+    flattening): w . counts is the same in every state a trajectory
+    reaches.  Returned as an int64 matrix [cells][laws]."""
+    from fractions import Fraction
+    from math import lcm
+    import oracle
+    f = oracle.FlatModel(model)
+    C = f.n_cells
+    rows = []
+    for leaf in range(f.n_leaves):
+        if f.leaf_rule[leaf] < 0:
+            continue
+        v = [Fraction(0)] * C
+        for k in range(int(f.leaf_ndelta[leaf])):
+            cell, d = (int(x) for x in f.leaf_delta[leaf, k])
+            v[cell] += d
+        rows.append(v)
+    piv, r = [], 0
+    for c in range(C):
+        p = next((i for i in range(r, len(rows)) if rows[i][c] != 0), None)
+        if p is None:
+            continue
+        rows[r], rows[p] = rows[p], rows[r]
+        rows[r] = [x / rows[r][c] for x in rows[r]]
+        for i in range(len(rows)):
+            if i != r and rows[i][c] != 0:
+                fct = rows[i][c]
+                rows[i] = [a - fct * b for a, b in zip(rows[i], rows[r])]
+        piv.append(c)
+        r += 1
+    basis = []
+    for fc in (c for c in range(C) if c not in piv):
+        w = [Fraction(0)] * C
+        w[fc] = Fraction(1)
+        for i, pc in enumerate(piv):
+            w[pc] = -rows[i][fc]
+        den = lcm(*[x.denominator for x in w])
+        basis.append([int(x * den) for x in w])
+    return np.array(basis, dtype=np.int64).T.reshape(C, len(basis))

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.gpu_common import compare_stats, compare_trajectories, gpu_run
+from tests.gpu_common import compare_stats, compare_trajectories, conservation_laws, gpu_run
 
 pytestmark = pytest.mark.gpu
 
@@ -180,7 +180,8 @@ def test_config2_full_size(ctx):
     """Configuration 2 at full size (4096 instances x 64 replicas, t_end
     100, 201 samples) in the benchmark's launch form (persistent, default
     shape with chunked refill): 16 trajectories spread over the id range
-    match the oracle one by one, and every per-instance moment equals the
+    match the oracle one by one, every sample of every trajectory keeps the
+    model's conservation laws, and every per-instance moment equals the
     exact integer sums of the fetched samples."""
     m, run = W.config(2)
     I, R, K1 = run["n_instances"], run["replicas"], run["n_samples"]
@@ -193,8 +194,13 @@ def test_config2_full_size(ctx):
                             want_stats=False)
         compare_trajectories(g, o, g_index=[int(i)])
     S = g["samples"].reshape(I, R, K1, -1)
+    Wl = conservation_laws(m)                    # every sample keeps each law
+    base = oracle.FlatModel(m).init.astype(np.int64) @ Wl
+    assert Wl.shape[1] > 0
+    assert ((g["final_counts"].astype(np.int64) @ Wl) == base).all()
     for i0 in range(0, I, 256):
         blk = S[i0:i0 + 256].astype(np.int64)
+        assert ((blk @ Wl) == base).all()
         assert np.array_equal(g["s1"][i0:i0 + 256], blk.sum(axis=1).astype(np.uint64))
         sq = (blk * blk).sum(axis=1)
         got = g["s2_hi32"][i0:i0 + 256].astype(np.int64) * 2 ** 32 + \
@@ -207,8 +213,9 @@ def test_config2_full_size(ctx):
 def test_config1_full_size_sampled(ctx):
     """Configuration 1 at full size (16384 replicas, t_end 100) in the
     launch configuration the benchmark times: 16 trajectories spread over
-    the id range match the oracle one by one; the moments are exactly the
-    integer sums of the fetched samples."""
+    the id range match the oracle one by one; every sample keeps the
+    model's conservation laws; the moments are exactly the integer sums of
+    the fetched samples."""
     m, run = W.config(1)
     mo = model(ctx, m)
     g = gpu_run(ctx, mo, run, mode="persistent", want_traj=True)
@@ -218,6 +225,9 @@ def test_config1_full_size_sampled(ctx):
                             want_stats=False)
         compare_trajectories(g, o, g_index=[int(i)])
     S = g["samples"].astype(np.int64)
+    Wl = conservation_laws(m)                    # every sample keeps each law
+    assert Wl.shape[1] > 0
+    assert ((S @ Wl) == oracle.FlatModel(m).init.astype(np.int64) @ Wl).all()
     assert (g["n_recorded"] == run["n_samples"]).all() and (g["status"] == 0).all()
     assert np.array_equal(g["s1"][0], S.sum(axis=0).astype(np.uint64))
     sq = (S * S).sum(axis=0)
@@ -481,8 +491,9 @@ def test_wave_layout_statuses(ctx):
 
 def test_config3_full_size_sampled(ctx):
     """Configuration 3 at full size (2048 replicas, t_end 50, persistent):
-    6 trajectories match the oracle one by one; moments equal the integer
-    sums of the fetched samples."""
+    4 trajectories match the oracle one by one; every sample keeps the
+    model's conservation laws; moments equal the integer sums of the
+    fetched samples."""
     m, run = W.config(3)
     mo = model(ctx, m)
     g = gpu_run(ctx, mo, run, mode="persistent", want_traj=True)
@@ -491,6 +502,9 @@ def test_config3_full_size_sampled(ctx):
         compare_trajectories(g, o, g_index=[i])
     S = g["samples"].astype(np.int64)
     assert (g["status"] == 0).all()
+    Wl = conservation_laws(m)
+    assert Wl.shape[1] > 0
+    assert ((S @ Wl) == oracle.FlatModel(m).init.astype(np.int64) @ Wl).all()
     assert np.array_equal(g["s1"][0], S.sum(axis=0).astype(np.uint64))
     sq = (S * S).sum(axis=0)
     assert np.array_equal(g["s2_hi32"][0].astype(np.int64) * 2 ** 32 + g["s2_lo32"][0].astype(np.int64), sq)
