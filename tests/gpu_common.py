@@ -67,25 +67,12 @@ def compare_stats(gpu, orc):
             assert np.nanmax(rel) <= 1e-12, (key, np.nanmax(rel))
 
 
-def conservation_laws(model):
-    """Integer basis of the vectors w with w . delta = 0 for the net change
-    delta of every slot (exact rational elimination over the oracle's
-    flattening): w . counts is the same in every state a trajectory
-    reaches.  Returned as an int64 matrix [cells][laws]."""
+def integer_null_space(rows, C):
+    """Integer basis of the vectors w with r . w = 0 for every row r (exact
+    rational elimination), as an int64 matrix [C][basis size]."""
     from fractions import Fraction
     from math import lcm
-    import oracle
-    f = oracle.FlatModel(model)
-    C = f.n_cells
-    rows = []
-    for leaf in range(f.n_leaves):
-        if f.leaf_rule[leaf] < 0:
-            continue
-        v = [Fraction(0)] * C
-        for k in range(int(f.leaf_ndelta[leaf])):
-            cell, d = (int(x) for x in f.leaf_delta[leaf, k])
-            v[cell] += d
-        rows.append(v)
+    rows = [[Fraction(x) for x in r] for r in rows]
     piv, r = [], 0
     for c in range(C):
         p = next((i for i in range(r, len(rows)) if rows[i][c] != 0), None)
@@ -108,3 +95,21 @@ def conservation_laws(model):
         den = lcm(*[x.denominator for x in w])
         basis.append([int(x * den) for x in w])
     return np.array(basis, dtype=np.int64).T.reshape(C, len(basis))
+
+
+def conservation_laws(model):
+    """Integer basis of the vectors w with w . delta = 0 for the net change
+    delta of every slot of the oracle's flattening: w . counts is the same
+    in every state a trajectory reaches.  Int64 matrix [cells][laws]."""
+    import oracle
+    f = oracle.FlatModel(model)
+    rows = []
+    for leaf in range(f.n_leaves):
+        if f.leaf_rule[leaf] < 0:
+            continue
+        v = [0] * f.n_cells
+        for k in range(int(f.leaf_ndelta[leaf])):
+            cell, d = (int(x) for x in f.leaf_delta[leaf, k])
+            v[cell] += d
+        rows.append(v)
+    return integer_null_space(rows, f.n_cells)

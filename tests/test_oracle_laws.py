@@ -210,3 +210,30 @@ def test_thread_count_invariance():
     for key in ("digest", "events", "t_final", "n", "s1", "s2_lo", "s2_hi"):
         assert (a[key] == b[key]).all(), key
     assert np.array_equal(a["mean"], b["mean"]) and np.array_equal(a["var"], b["var"])
+
+
+@pytest.mark.parametrize("name", ["gene_regulation", "multi_compartment", "transport",
+                                  "receptor_binding"])
+def test_trajectories_keep_conservation_laws(name):
+    """Every sample of every oracle trajectory keeps each conservation law of
+    the model, the laws taken from the net changes that the brute-force
+    chain (tests/ctmc.py) enumerates from the model itself, in a state where
+    every rule can fire in every context."""
+    from tests.gpu_common import integer_null_space
+    m = {"gene_regulation": lambda: W.config(1)[0],
+         "multi_compartment": lambda: W.multi_compartment(3, n_cells_=4),
+         "transport": W.transport, "receptor_binding": W.receptor_binding}[name]()
+    rich = dict(m, init=[[5] * len(r) for r in m["init"]],
+                init_wrap=[None if w is None else [5] * len(w)
+                           for w in (m.get("init_wrap") or [None] * len(m["init"]))])
+    s0 = ctmc.initial_state(rich)
+    base = ctmc.cell_values(rich, [s0])[0]
+    rows = [ctmc.cell_values(rich, [nxt])[0] - base for _, nxt in ctmc.transitions(rich, s0)]
+    C = len(base)
+    Wl = integer_null_space([[int(x) for x in r] for r in rows], C)
+    assert Wl.shape[1] > 0
+    run = W.make_run(seed=17, replicas=12, dt=0.5, n_samples=21)
+    res = oracle.simulate(m, run, want_samples=True, want_stats=False)
+    init = oracle.FlatModel(m).init.astype(np.int64)
+    assert ((res["samples"].astype(np.int64) @ Wl) == init @ Wl).all()
+    assert ((res["final_counts"].astype(np.int64) @ Wl) == init @ Wl).all()
