@@ -481,7 +481,7 @@ std::string codegen_lane(const Flat &f)
             }
             if (fd.word < 0) ok = false;
         }
-        if (nw == 3) nw = 4;
+        if (nw == 3) nw = 4;   // a three-word entry is read as one 16-byte load
         if (ok && (size_t)P * (size_t)nw * 4u <= kLaneStaticLdsBytes) {
             field = bf;
             n_words = nw;
