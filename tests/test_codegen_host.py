@@ -1,11 +1,15 @@
-"""The generated per-leaf change table, checked on the host: the model's
+"""Generated model code checked on the host.  The per-leaf change table: the model's
 CWC_APPLY macro and its table (as the library generates them) are compiled
 with g++ around stand-ins for the two bit-field-extract builtins, every
 leaf's change is applied to a known state, and the result must be the net
 change the oracle's own flattening gives for that leaf (Sec. 2.1: the
 rewrite replaces the matched reactants by the products).  Covers the byte
 layout (signed and unsigned bytes and half-words, 1 to 4 words), the dense
-layout, and the per-digit leaf-mask fallback on 32- and 64-leaf trees."""
+layout, and the per-digit leaf-mask fallback on 32- and 64-leaf trees.  The
+selection descents (one lane; two lanes after the engine's root decision):
+compiled the same way and compared with the oracle's selection (Sec. 2.2:
+the reaction is chosen with probability proportional to its rate) on
+random trees with zero leaves and on integer trees at every tie."""
 import os
 import re
 import shutil
@@ -161,3 +165,124 @@ def test_layouts_covered():
             if pat in body:
                 seen.add(key)
     assert seen == {"s8", "u8", "s16", "u16", "sbfe", "ubfe", "mask32", "mask64", "w4"}
+
+
+DESCENT_HARNESS = r"""
+#include <cstdio>
+%(macros)s
+static int lane_descend(const double *A, double x) {
+%(adecl)s
+    int j = 0;
+    CWC_DESCEND(x, j);
+    return j;
+}
+%(pairfn)s
+int main() {
+    int T, P, K;
+    if (std::scanf("%%d %%d %%d", &T, &P, &K) != 3) return 1;
+    static double A[2 * 4096], L[4096], X[4096];
+    for (int t = 0; t < T; ++t) {
+        for (int l = 0; l < P; ++l) std::scanf("%%lf", &L[l]);
+        for (int k = 0; k < K; ++k) std::scanf("%%lf", &X[k]);
+        for (int l = 0; l < P; ++l) A[P + l] = L[l];
+        for (int i = P - 1; i >= 1; --i) A[i] = A[2 * i] + A[2 * i + 1];
+        for (int k = 0; k < K; ++k) {
+            std::printf("%%d %%d\n", lane_descend(A, X[k]), %(paircall)s);
+        }
+    }
+    return 0;
+}
+"""
+
+PAIR_FN = r"""
+// the engine's root decision over the two half sums, then the chosen half
+static int pair_descend(const double *L, int P, double x) {
+    const int B = P / 2;
+    static double Q[2][2 * 4096];
+    for (int h = 0; h < 2; ++h) {
+        for (int i = 0; i < B; ++i) Q[h][B + i] = L[h * B + i];
+        for (int i = B - 1; i >= 1; --i) Q[h][i] = Q[h][2 * i] + Q[h][2 * i + 1];
+    }
+    const double L0 = Q[0][1], R0 = Q[1][1];
+    const bool b0 = (x >= L0) && (R0 != 0.0);
+    x = b0 ? x - L0 : x;
+    const double *q = Q[b0 ? 1 : 0];
+%(qdecl)s
+    int jl = 0;
+    CWC_PAIR_DESCEND(x, jl);
+    return (b0 ? B : 0) + jl;
+}
+"""
+
+
+DESCENT_MODELS = {
+    "paper_example": W.paper_example,                       # 1 leaf of 1
+    "lotka_volterra": W.lotka_volterra,                     # 4 leaves
+    "receptor_binding": W.receptor_binding,
+    "transport7": lambda: W.transport(n_children=7),        # padding subtrees
+    "gene_regulation": lambda: W.config(1)[0],              # 32 leaves
+    "one_cell": lambda: W.multi_compartment(3, n_cells_=1),  # 64 leaves
+}
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+@pytest.mark.parametrize("name", sorted(DESCENT_MODELS))
+def test_generated_descent(name):
+    """The generated selection descents (one lane, and two lanes with the
+    engine's root decision) pick the oracle's leaf for random trees with
+    zero leaves, and for integer trees at every integer x (exact sums, so
+    every tie x == L occurs and must go right)."""
+    import numpy as np
+    from paper_1010_2438_amd import cwc_codegen
+    model = DESCENT_MODELS[name]()
+    src = cwc_codegen(model)
+    P = int(re.search(r"#define CWC_P (\d+)", src).group(1))
+    flat = oracle.FlatModel(model)
+    live = flat.leaf_rule >= 0
+    pair = "#define CWC_PAIR_DESCEND" in src
+    macros = macro(src, "CWC_DESCEND(x, j)")
+    if pair:
+        macros += macro(src, "CWC_PAIR_DESCEND(x, j)")
+    B = P // 2
+    code = DESCENT_HARNESS % {
+        "macros": macros,
+        "adecl": "\n".join("    const double a%d = A[%d]; (void)a%d;" % (i, i, i)
+                           for i in range(1, 2 * P)),
+        "pairfn": (PAIR_FN % {"qdecl": "\n".join("    const double q%d = q[%d]; (void)q%d;"
+                                                  % (i, i, i) for i in range(1, 2 * B))})
+        if pair else "",
+        "paircall": "pair_descend(L, P, X[k])" if pair else "-1"}
+    rng = np.random.default_rng(11)
+    trials = []
+    for t in range(40):
+        if t % 2:
+            lv = rng.integers(0, 4, P).astype(np.float64)         # exact sums, ties
+        else:
+            lv = rng.uniform(0.0, 3.0, P) * (rng.random(P) < 0.8)  # some zeros
+        lv[~live] = 0.0
+        a0 = oracle.select(lv, 0.0)[1]
+        if a0 == 0.0:
+            continue
+        if t % 2:
+            xs = np.arange(0.0, a0)                                 # every integer below a0
+        else:
+            xs = np.concatenate([rng.uniform(0.0, a0, 60), [0.0, np.nextafter(a0, 0.0)]])
+        trials.append((lv, xs))
+    d = tempfile.mkdtemp(prefix="cwc_desc_")
+    try:
+        with open(os.path.join(d, "t.cpp"), "w") as f:
+            f.write(code)
+        subprocess.check_call(["g++", "-O1", "-w", "-o", os.path.join(d, "t"),
+                               os.path.join(d, "t.cpp")])
+        for lv, xs in trials:
+            inp = "1 %d %d\n%s\n%s\n" % (P, len(xs), " ".join(repr(float(v)) for v in lv),
+                                        " ".join(repr(float(x)) for x in xs))
+            out = subprocess.check_output([os.path.join(d, "t")], input=inp, text=True)
+            for x, line in zip(xs, out.splitlines()):
+                jl, jp = (int(v) for v in line.split())
+                want = oracle.select(lv, float(x))[0]
+                assert jl == want, (x, jl, want)
+                if pair:
+                    assert jp == want, (x, jp, want)
+    finally:
+        shutil.rmtree(d)
