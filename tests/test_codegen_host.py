@@ -177,6 +177,7 @@ static int lane_descend(const double *A, double x) {
     return j;
 }
 %(pairfn)s
+%(quadfn)s
 int main() {
     int T, P, K;
     if (std::scanf("%%d %%d %%d", &T, &P, &K) != 3) return 1;
@@ -187,7 +188,7 @@ int main() {
         for (int l = 0; l < P; ++l) A[P + l] = L[l];
         for (int i = P - 1; i >= 1; --i) A[i] = A[2 * i] + A[2 * i + 1];
         for (int k = 0; k < K; ++k) {
-            std::printf("%%d %%d\n", lane_descend(A, X[k]), %(paircall)s);
+            std::printf("%%d %%d %%d\n", lane_descend(A, X[k]), %(paircall)s, %(quadcall)s);
         }
     }
     return 0;
@@ -214,6 +215,31 @@ static int pair_descend(const double *L, int P, double x) {
 }
 """
 
+QUAD_FN = r"""
+// the engine's two top decisions over the four quarter sums, then the quarter
+static int quad_descend(const double *L, int P, double x) {
+    const int B = P / 4;
+    static double R[4][2 * 4096];
+    for (int h = 0; h < 4; ++h) {
+        for (int i = 0; i < B; ++i) R[h][B + i] = L[h * B + i];
+        for (int i = B - 1; i >= 1; --i) R[h][i] = R[h][2 * i] + R[h][2 * i + 1];
+    }
+    const double p0 = R[0][1], p1 = R[1][1], p2 = R[2][1], p3 = R[3][1];
+    const double n1 = p0 + p1, n2 = p2 + p3;
+    const bool b0 = (x >= n1) && (n2 != 0.0);
+    x = b0 ? x - n1 : x;
+    const double L1 = b0 ? p2 : p0, R1 = b0 ? p3 : p1;
+    const bool b1 = (x >= L1) && (R1 != 0.0);
+    x = b1 ? x - L1 : x;
+    const int qq = (b0 ? 2 : 0) + (b1 ? 1 : 0);
+    const double *r = R[qq];
+%(rdecl)s
+    int jl = 0;
+    CWC_QUAD_DESCEND(x, jl);
+    return qq * B + jl;
+}
+"""
+
 
 DESCENT_MODELS = {
     "paper_example": W.paper_example,                       # 1 leaf of 1
@@ -228,8 +254,8 @@ DESCENT_MODELS = {
 @pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
 @pytest.mark.parametrize("name", sorted(DESCENT_MODELS))
 def test_generated_descent(name):
-    """The generated selection descents (one lane, and two lanes with the
-    engine's root decision) pick the oracle's leaf for random trees with
+    """The generated selection descents (one lane; two and four lanes with
+    the engine's top decisions) pick the oracle's leaf for random trees with
     zero leaves, and for integer trees at every integer x (exact sums, so
     every tie x == L occurs and must go right)."""
     import numpy as np
@@ -240,9 +266,12 @@ def test_generated_descent(name):
     flat = oracle.FlatModel(model)
     live = flat.leaf_rule >= 0
     pair = "#define CWC_PAIR_DESCEND" in src
+    quad = "#define CWC_QUAD_DESCEND" in src
     macros = macro(src, "CWC_DESCEND(x, j)")
     if pair:
         macros += macro(src, "CWC_PAIR_DESCEND(x, j)")
+    if quad:
+        macros += macro(src, "CWC_QUAD_DESCEND(x, j)")
     B = P // 2
     code = DESCENT_HARNESS % {
         "macros": macros,
@@ -251,7 +280,11 @@ def test_generated_descent(name):
         "pairfn": (PAIR_FN % {"qdecl": "\n".join("    const double q%d = q[%d]; (void)q%d;"
                                                   % (i, i, i) for i in range(1, 2 * B))})
         if pair else "",
-        "paircall": "pair_descend(L, P, X[k])" if pair else "-1"}
+        "paircall": "pair_descend(L, P, X[k])" if pair else "-1",
+        "quadfn": (QUAD_FN % {"rdecl": "\n".join("    const double r%d = r[%d]; (void)r%d;"
+                                                 % (i, i, i) for i in range(1, 2 * (P // 4)))})
+        if quad else "",
+        "quadcall": "quad_descend(L, P, X[k])" if quad else "-1"}
     rng = np.random.default_rng(11)
     trials = []
     for t in range(40):
@@ -279,10 +312,12 @@ def test_generated_descent(name):
                                         " ".join(repr(float(x)) for x in xs))
             out = subprocess.check_output([os.path.join(d, "t")], input=inp, text=True)
             for x, line in zip(xs, out.splitlines()):
-                jl, jp = (int(v) for v in line.split())
+                jl, jp, jq = (int(v) for v in line.split())
                 want = oracle.select(lv, float(x))[0]
                 assert jl == want, (x, jl, want)
                 if pair:
                     assert jp == want, (x, jp, want)
+                if quad:
+                    assert jq == want, (x, jq, want)
     finally:
         shutil.rmtree(d)
