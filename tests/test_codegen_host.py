@@ -9,7 +9,9 @@ layout, and the per-digit leaf-mask fallback on 32- and 64-leaf trees.  The
 selection descents (one lane; two lanes after the engine's root decision):
 compiled the same way and compared with the oracle's selection (Sec. 2.2:
 the reaction is chosen with probability proportional to its rate) on
-random trees with zero leaves and on integer trees at every tie."""
+random trees with zero leaves and on integer trees at every tie.  The
+propensity trees: every leaf k x (double) prod C(n, m) and every node
+left + right, bit for bit, and the pair layout's half trees equal to them."""
 import os
 import re
 import shutil
@@ -244,6 +246,7 @@ static int quad_descend(const double *L, int P, double x) {
 DESCENT_MODELS = {
     "paper_example": W.paper_example,                       # 1 leaf of 1
     "lotka_volterra": W.lotka_volterra,                     # 4 leaves
+    "dimerisation": W.dimerisation,                         # C(n, 2) factors
     "receptor_binding": W.receptor_binding,
     "transport7": lambda: W.transport(n_children=7),        # padding subtrees
     "gene_regulation": lambda: W.config(1)[0],              # 32 leaves
@@ -321,3 +324,119 @@ def test_generated_descent(name):
                     assert jq == want, (x, jq, want)
     finally:
         shutil.rmtree(d)
+
+
+TREE_HARNESS = r"""
+#include <cstdio>
+#include <cstring>
+static unsigned long long bits(double v) { unsigned long long b; std::memcpy(&b, &v, 8); return b; }
+%(macros)s
+int main() {
+    int T;
+    if (std::scanf("%%d", &T) != 1) return 1;
+    for (int t = 0; t < T; ++t) {
+        int N[%(C)d];
+        double KR[%(NR)d];
+        for (int c = 0; c < %(C)d; ++c) std::scanf("%%d", &N[c]);
+        for (int r = 0; r < %(NR)d; ++r) std::scanf("%%lf", &KR[r]);
+%(ndecl)s
+%(kdecl)s
+%(adecl)s
+        CWC_TREE;
+%(aprint)s
+        std::printf("\n");
+%(pair)s
+    }
+    return 0;
+}
+"""
+
+PAIR_TREE_PART = r"""
+        for (int h = 0; h < 2; ++h) {
+            CWC_PAIR_DECL;
+            CWC_PAIR_LOAD_K(KR, h);
+            CWC_PAIR_TREE(h);
+%(qprint)s
+            std::printf("\n");
+        }
+"""
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+@pytest.mark.parametrize("name", sorted(DESCENT_MODELS))
+def test_generated_trees(name):
+    """The generated propensity tree (one lane) has, bit for bit, leaves
+    k_r x (double)h with h the exact product of binomials C(n, m) of the
+    slot's reactant counts (Sec. 2.2) and nodes left + right; the pair
+    layout's half trees hold the same leaves and their roots are the tree's
+    two level-1 nodes."""
+    import math
+    import numpy as np
+    from paper_1010_2438_amd import cwc_codegen
+    model = DESCENT_MODELS[name]()
+    src = cwc_codegen(model)
+    C = int(re.search(r"#define CWC_C (\d+)", src).group(1))
+    P = int(re.search(r"#define CWC_P (\d+)", src).group(1))
+    NR = int(re.search(r"#define CWC_NR (\d+)", src).group(1))
+    pair = "#define CWC_PAIR_TREE" in src
+    B = P // 2
+    macros = macro(src, "CWC_TREE")
+    qnames = set()
+    if pair:
+        for head in ("CWC_PAIR_DECL", "CWC_PAIR_LOAD_K(ptr, h)", "CWC_PAIR_TREE(h)"):
+            macros += macro(src, head)
+        # the half tree declares only the nodes that can be non-zero
+        qnames = set(re.findall(r"double (q\d+) = ", macro(src, "CWC_PAIR_DECL")))
+    code = TREE_HARNESS % {
+        "macros": macros, "C": C, "NR": NR,
+        "ndecl": "\n".join("        int n%d = N[%d]; (void)n%d;" % (c, c, c) for c in range(C)),
+        "kdecl": "\n".join("        double k%d = KR[%d]; (void)k%d;" % (r, r, r) for r in range(NR)),
+        "adecl": "\n".join("        double a%d = 0.0; (void)a%d;" % (i, i) for i in range(1, 2 * P)),
+        "aprint": "\n".join('        std::printf("%%llu ", bits(a%d));' % i for i in range(1, 2 * P)),
+        "pair": (PAIR_TREE_PART % {"qprint": "\n".join(
+            '            std::printf("%%llu ", bits(%s));' % ("q%d" % i if "q%d" % i in qnames else "0.0")
+            for i in range(1, 2 * B))})
+        if pair else ""}
+    flat = oracle.FlatModel(model)
+    rng = np.random.default_rng(5)
+    trials = []
+    for t in range(30):
+        hi = [3, 50, 5000, 1_000_000][t % 4]
+        n = rng.integers(0, hi + 1, C)
+        n[rng.random(C) < 0.2] = 0
+        n[rng.random(C) < 0.1] = 1
+        k = rng.uniform(0.01, 10.0, NR)
+        trials.append((n, k))
+    inp = "%d\n" % len(trials) + "\n".join(
+        " ".join(str(int(v)) for v in n) + " " + " ".join(repr(float(v)) for v in k)
+        for n, k in trials)
+    d = tempfile.mkdtemp(prefix="cwc_tree_")
+    try:
+        with open(os.path.join(d, "t.cpp"), "w") as f:
+            f.write(code)
+        subprocess.check_call(["g++", "-O1", "-w", "-ffp-contract=off", "-o",
+                               os.path.join(d, "t"), os.path.join(d, "t.cpp")])
+        out = subprocess.check_output([os.path.join(d, "t")], input=inp, text=True).splitlines()
+    finally:
+        shutil.rmtree(d)
+    as_bits = lambda v: int(np.float64(v).view(np.uint64))
+    per = 3 if pair else 1
+    for t, (n, k) in enumerate(trials):
+        got = [int(x) for x in out[per * t].split()]
+        node = [0.0] * (2 * P)
+        for leaf in range(P):
+            if flat.leaf_rule[leaf] < 0:
+                continue
+            h = 1
+            for cell, m in flat.leaf_react[leaf]:
+                if m > 0:
+                    h *= math.comb(int(n[cell]), int(m))
+            node[P + leaf] = float(np.float64(k[flat.leaf_rule[leaf]]) * np.float64(float(h)))
+        for i in range(P - 1, 0, -1):
+            node[i] = float(np.float64(node[2 * i]) + np.float64(node[2 * i + 1]))
+        assert got == [as_bits(node[i]) for i in range(1, 2 * P)], "trial %d" % t
+        if pair:
+            for h in range(2):
+                q = [int(x) for x in out[per * t + 1 + h].split()]
+                assert q[0] == as_bits(node[2 + h]), ("half root", t, h)
+                assert q[B - 1:] == [as_bits(node[P + h * B + i]) for i in range(B)], ("leaves", t, h)
