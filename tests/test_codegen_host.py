@@ -11,7 +11,8 @@ compiled the same way and compared with the oracle's selection (Sec. 2.2:
 the reaction is chosen with probability proportional to its rate) on
 random trees with zero leaves and on integer trees at every tie.  The
 propensity trees: every leaf k x (double) prod C(n, m) and every node
-left + right, bit for bit, and the pair layout's half trees equal to them."""
+left + right, bit for bit, and the pair and quad layouts' partial trees
+equal to them."""
 import os
 import re
 import shutil
@@ -346,9 +347,20 @@ int main() {
 %(aprint)s
         std::printf("\n");
 %(pair)s
+%(quad)s
     }
     return 0;
 }
+"""
+
+QUAD_TREE_PART = r"""
+        for (int h = 0; h < 4; ++h) {
+            CWC_QUAD_DECL;
+            CWC_QUAD_LOAD_K(KR, h);
+            CWC_QUAD_TREE(h);
+%(rprint)s
+            std::printf("\n");
+        }
 """
 
 PAIR_TREE_PART = r"""
@@ -369,7 +381,8 @@ def test_generated_trees(name):
     k_r x (double)h with h the exact product of binomials C(n, m) of the
     slot's reactant counts (Sec. 2.2) and nodes left + right; the pair
     layout's half trees hold the same leaves and their roots are the tree's
-    two level-1 nodes."""
+    two level-1 nodes; the quad layout's quarter trees likewise, their roots
+    the four level-2 nodes."""
     import math
     import numpy as np
     from paper_1010_2438_amd import cwc_codegen
@@ -387,6 +400,13 @@ def test_generated_trees(name):
             macros += macro(src, head)
         # the half tree declares only the nodes that can be non-zero
         qnames = set(re.findall(r"double (q\d+) = ", macro(src, "CWC_PAIR_DECL")))
+    quad = "#define CWC_QUAD_TREE" in src
+    rnames = set()
+    Q = P // 4
+    if quad:
+        for head in ("CWC_QUAD_DECL", "CWC_QUAD_LOAD_K(ptr, h)", "CWC_QUAD_TREE(h)"):
+            macros += macro(src, head)
+        rnames = set(re.findall(r"double (r\d+) = ", macro(src, "CWC_QUAD_DECL")))
     code = TREE_HARNESS % {
         "macros": macros, "C": C, "NR": NR,
         "ndecl": "\n".join("        int n%d = N[%d]; (void)n%d;" % (c, c, c) for c in range(C)),
@@ -396,7 +416,11 @@ def test_generated_trees(name):
         "pair": (PAIR_TREE_PART % {"qprint": "\n".join(
             '            std::printf("%%llu ", bits(%s));' % ("q%d" % i if "q%d" % i in qnames else "0.0")
             for i in range(1, 2 * B))})
-        if pair else ""}
+        if pair else "",
+        "quad": (QUAD_TREE_PART % {"rprint": "\n".join(
+            '            std::printf("%%llu ", bits(%s));' % ("r%d" % i if "r%d" % i in rnames else "0.0")
+            for i in range(1, 2 * Q))})
+        if quad else ""}
     flat = oracle.FlatModel(model)
     rng = np.random.default_rng(5)
     trials = []
@@ -420,7 +444,7 @@ def test_generated_trees(name):
     finally:
         shutil.rmtree(d)
     as_bits = lambda v: int(np.float64(v).view(np.uint64))
-    per = 3 if pair else 1
+    per = 1 + (2 if pair else 0) + (4 if quad else 0)
     for t, (n, k) in enumerate(trials):
         got = [int(x) for x in out[per * t].split()]
         node = [0.0] * (2 * P)
@@ -440,3 +464,9 @@ def test_generated_trees(name):
                 q = [int(x) for x in out[per * t + 1 + h].split()]
                 assert q[0] == as_bits(node[2 + h]), ("half root", t, h)
                 assert q[B - 1:] == [as_bits(node[P + h * B + i]) for i in range(B)], ("leaves", t, h)
+        if quad:
+            base = per * t + 1 + (2 if pair else 0)
+            for h in range(4):
+                r = [int(x) for x in out[base + h].split()]
+                assert r[0] == as_bits(node[4 + h]), ("quarter root", t, h)
+                assert r[Q - 1:] == [as_bits(node[P + h * Q + i]) for i in range(Q)], ("quarter", t, h)
