@@ -479,6 +479,16 @@ def test_small_models_wave_layout(ctx, name):
     check(ctx, m, run, tuning={"lanes_per_replica": 64})
 
 
+def test_wave_layout_largest_model(ctx):
+    """The wavefront layout at its largest model: 64 compartments (63 cells
+    in an outer one), one per lane, 768 count cells, 2048 leaves; both
+    forms against the oracle."""
+    m = W.multi_compartment(3, n_cells_=63)
+    mo = model(ctx, m)
+    assert mo.info["layout"] == 1 and mo.info["n_cells"] == 768
+    check(ctx, m, W.make_run(seed=23, replicas=12, dt=0.2, n_samples=6))
+
+
 def test_wave_layout_statuses(ctx):
     m = W.multi_compartment(3, n_cells_=5)
     run = W.make_run(seed=9, replicas=20, dt=0.5, n_samples=11)
