@@ -7,13 +7,18 @@ kinetic constants are scaled by a per-instance factor 10^U(-1,1), 64
 replicas each (262144 trajectories, ~100x spread of events per trajectory),
 simulated to t = 100 with 201 sample points and reduced on line into
 per-instance, per-sample mean/variance.  Inputs are resident on the device
-before the timed region.  `value` is the batched persistent form (resident
-grid, lane refill from a longest-first work queue, replayed as a HIP graph,
-autotuned launch shape); the plain one-lane-per-trajectory launch is timed
-on the same inputs beside it.  Also reported: the 16384-replica
-gene-regulation run in both forms, the 32-cell multi-compartment run, the
-serving trace (continuous batching, p50/p99 latency), the VALU roofline of
-the headline kernel and the CPU oracle on the host cores.
+before the timed region.  `value` is the batched persistent form: instances
+taken longest-first (predicted by their total propensity at t = 0), two
+lanes per trajectory, replayed as a HIP graph, at the launch shape in
+LAUNCH (the autotuner's choice on MI355X; its grid holds every trajectory,
+so the hardware dispatcher, starting blocks as others finish, is the
+queue).  Timed beside it on the same inputs: the plain launch with one lane
+per trajectory in natural order, and the plain launch at the headline's own
+layout (two lanes per trajectory, natural order), which isolates the gain
+of the longest-first order.  Also reported: the 16384-replica
+gene-regulation run, the 32-cell multi-compartment run, the serving trace
+(continuous batching, p50/p99 latency), the VALU roofline of each kernel and
+the CPU oracle on the host cores.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: the benchmark runs
 on one GPU.
@@ -30,6 +35,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SSA events/sec on 1 GPU (batched persistent vs plain launch); p99 job latency"
 PEAK_VALU_SLOTS = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock = 3.93e13/s
+
+# Launch shapes the benchmark times: for each workload's persistent form the
+# shape the autotuner chose on MI355X (``--autotune`` searches again
+# instead), and the two plain launches of the sweep.  The full-size parity
+# tests run exactly these shapes.
+LAUNCH = {
+    # sweep: two lanes per trajectory, block 256, 16 requested waves per
+    # SIMD (a grid that holds every trajectory: the queue-free kernel)
+    "sweep": {"block_size": 256, "waves_per_simd": 16, "lanes_per_replica": 2},
+    # the plain per-trajectory launch: one lane each, natural order
+    "sweep_plain": {"block_size": 256, "lanes_per_replica": 1},
+    # the plain launch at the headline's layout: only the order differs
+    "sweep_plain_pair": {"block_size": 256, "lanes_per_replica": 2},
+    # 16384 replicas of one model: four lanes per trajectory, one wave/SIMD
+    1: {"block_size": 256, "waves_per_simd": 1, "lanes_per_replica": 4},
+    # the 32-cell model: one wavefront per trajectory
+    3: {"block_size": 256, "waves_per_simd": 8, "lanes_per_replica": 64},
+}
 
 
 def log(*a):
@@ -80,44 +103,93 @@ def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None, e2e=Fal
     return out
 
 
-def cpu_baseline(model, run, budget_s=15.0):
-    """The oracle (plain C direct method) on the host cores over a bounded
-    sample of the same workload: replica 0 of every s-th instance, s chosen
-    for about `budget_s` seconds of work, the instances spread over the
-    whole sweep (events per trajectory vary ~100x across it)."""
-    import numpy as np
+def host_cpu():
+    """(model name, usable host threads).  Threads: the CPUs this process
+    may run on, at most 16 -- the host share of one GPU on the MI355X boxes
+    this runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, max(1, min(16, n))
+
+
+def oracle_rate(model, run, ids, threads):
+    """The oracle over trajectories `ids` (one call per trajectory, spread
+    over `threads` host threads): (events, seconds)."""
+    import threading
     import oracle
-    threads = min(16, os.cpu_count() or 1)
-    I, R = run["n_instances"], run["replicas"]
     fm = oracle.FlatModel(model)
+    evs = [0] * len(ids)
 
-    def sample(stride):
-        ids = list(range(0, I, stride))
-        t0 = time.perf_counter()
-        import threading
-        evs = [0] * len(ids)
+    def work(k):
+        for q in range(k, len(ids), threads):
+            g = int(ids[q])
+            r = oracle.simulate(model, run, g0=g, g1=g + 1, want_stats=False, flat=fm)
+            evs[q] = int(r["events"][0])
 
-        def work(k):
-            for q in range(k, len(ids), threads):
-                g = ids[q] * R
-                r = oracle.simulate(model, run, g0=g, g1=g + 1, want_stats=False, flat=fm)
-                evs[q] = int(r["events"][0])
+    t0 = time.perf_counter()
+    ts = [threading.Thread(target=work, args=(k,)) for k in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    return sum(evs), time.perf_counter() - t0
 
-        ts = [threading.Thread(target=work, args=(k,)) for k in range(threads)]
-        for t in ts:
-            t.start()
-        for t in ts:
-            t.join()
-        return len(ids), sum(evs), time.perf_counter() - t0
 
-    n, ev, dt = sample(256)                                  # probe: 16 trajectories
-    rate = ev / max(dt, 1e-6) * threads / min(threads, n)    # events/s with all threads busy
-    n_want = budget_s * rate / max(ev / n, 1.0)
+def cpu_baseline(budget_s=10.0):
+    """The oracle (plain C direct method, full propensity recomputation per
+    event) on the host cores over bounded samples of the benchmark's
+    workloads.  Headline (`value`): the sweep, replica 0 of every s-th
+    instance (s chosen for about `budget_s` seconds of work on all threads;
+    the instances spread over the whole sweep, whose events per trajectory
+    vary ~100x), on every usable thread; beside it the same sample's first
+    trajectories on one thread, and prefixes of the other workloads'
+    trajectories on all threads.  Rates are events/s of the sample (a
+    prefix's rate scales linearly to the full workload: trajectories are
+    independent)."""
+    import workloads as W
+    cpu, threads = host_cpu()
+    m2, run2 = W.config(2)
+    I, R = run2["n_instances"], run2["replicas"]
+    probe = [i * R for i in range(0, I, 256)]                  # 16 trajectories
+    ev, dt = oracle_rate(m2, run2, probe, threads)
+    rate = ev / max(dt, 1e-6) * threads / min(threads, len(probe))
+    n_want = budget_s * rate / max(ev / len(probe), 1.0)
     stride = max(1, int(I / max(n_want, 1.0)))
-    n, ev, dt = sample(stride)
-    return {"value": ev / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": "replica 0 of every %d-th of %d instances (%d trajectories, %d events, "
-                      "%.1f s)" % (stride, I, n, ev, dt)}
+    ids = [i * R for i in range(0, I, stride)]
+    ev, dt = oracle_rate(m2, run2, ids, threads)
+    # one thread: an evenly spread subset of that sample sized for about a
+    # third of the budget
+    per_traj = dt * min(threads, len(ids)) / len(ids)
+    n1 = max(1, min(len(ids), int(budget_s / 3.0 / max(per_traj, 1e-9))))
+    ids1 = ids[::max(1, len(ids) // n1)][:n1]
+    ev1, dt1 = oracle_rate(m2, run2, ids1, 1)
+    out = {"value": ev / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu,
+           "sample": "sweep: replica 0 of every %d-th of %d instances (%d trajectories, %d "
+                     "events, %.1f s on %d threads)" % (stride, I, len(ids), ev, dt, threads),
+           "single_thread": {"value": ev1 / dt1, "unit": "events/s", "cores": 1,
+                             "sample": "%d of those trajectories (%d events, %.1f s)"
+                                       % (len(ids1), ev1, dt1)},
+           "other_workloads": {}}
+    for c, n in ((0, 64), (1, 8 * threads), (3, 4 * threads)):
+        m, run = W.config(c)
+        G = run["n_instances"] * run["replicas"]
+        ids = list(range(min(n, G)))
+        e, d = oracle_rate(m, run, ids, threads)
+        out["other_workloads"][W.CONFIG_NAMES[c]] = {
+            "value": e / d, "unit": "events/s", "cores": threads,
+            "sample": "trajectories 0..%d of %d (%d events, %.2f s)" % (len(ids) - 1, G, e, d)}
+    return out
 
 
 def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=64):
@@ -207,12 +279,11 @@ def fnv1a64(text):
     return "%016x" % h
 
 
-def measured_traffic(source, kernel):
-    """HBM bytes per launch of the headline kernel from its committed counter
-    summary (profiles/<kernel>_gene_regulation_sweep_i4096_r64.md), only if
-    the counters were taken on this exact kernel (same generated source);
-    else None."""
-    path = os.path.join(ROOT, "profiles", "%s_gene_regulation_sweep_i4096_r64.md" % kernel)
+def measured_traffic(source, kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from its committed
+    counter summary (profiles/<kernel>_<workload>.md), only if the counters
+    were taken on this exact kernel (same generated source); else None."""
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
     try:
         text = open(path).read()
     except OSError:
@@ -221,6 +292,31 @@ def measured_traffic(source, kernel):
     if fig.get("source_fnv1a64") != fnv1a64(source) or "traffic_bytes_per_launch" not in fig:
         return None
     return int(fig["traffic_bytes_per_launch"])
+
+
+def algorithmic_output_bytes(I, K1, C, G):
+    """Bytes the path must write per launch: the exact moments (S1, S2 as
+    two 64-bit halves) per (instance, sample, cell), the contributor count
+    per (instance, sample), mean and variance per (instance, sample, cell),
+    and per trajectory its final counts, events, final time, digest, status
+    and recorded-sample count."""
+    return I * K1 * C * (3 * 8 + 2 * 8) + I * K1 * 8 + G * (4 * C + 8 + 8 + 8 + 1 + 4)
+
+
+def roofline_of(res, alg, model, workload, run):
+    """The VALU roofline of one timed form: algorithmic issue slots per
+    applied event x events per launch / the kernel's HIP-event time."""
+    achieved = res["events_per_step"] * alg / (res["kernel_ms"] * 1e-3)
+    I, R, K1 = run["n_instances"], run["replicas"], run["n_samples"]
+    C = model.info["n_cells"]
+    traffic = measured_traffic(model.source(), res["kernel"], workload)
+    alg_bytes = algorithmic_output_bytes(I, K1, C, I * R)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
+            "unit": "TOP/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": traffic,
+            "kernel": res["kernel"], "kernel_ms": res["kernel_ms"],
+            "algorithmic_output_bytes": alg_bytes,
+            "traffic_over_algorithmic": None if traffic is None else traffic / alg_bytes,
+            "work_unit": "%.1f VALU issue slots per applied event" % alg}
 
 
 def parse_tuning(text):
@@ -233,26 +329,27 @@ def parse_tuning(text):
 
 
 def single_workload(ctx, stream, args):
-    """One workload's persistent form alone (autotuned unless --tuning is
-    given), with the roofline of its kernel, as one JSON line."""
+    """One workload's persistent form alone (at its LAUNCH shape unless
+    --tuning or --autotune is given), with the roofline of its kernel, as
+    one JSON line."""
     import workloads as W
     from paper_1010_2438_amd import Model
     m, run = W.config(args.workload)
     model = Model(ctx, m)
     alg = model.info["alg_slots_per_event"]
-    tun = parse_tuning(args.tuning) if args.tuning else \
-        model.autotune(run, "persistent", budget_s=2.0)
+    if args.tuning:
+        tun = parse_tuning(args.tuning)
+    elif args.autotune:
+        tun = model.autotune(run, "persistent", budget_s=2.0)
+    else:
+        tun = dict(LAUNCH[args.workload])
     res = time_form(ctx, model, run, "persistent", args.steps, args.warmup, stream, tun)
-    achieved = res["events_per_step"] * alg / (res["kernel_ms"] * 1e-3)
     print(json.dumps({
         "workload": W.CONFIG_NAMES[args.workload], "form": "persistent",
         "events_per_s": res["events_per_s"], "ms_per_step": res["ms_per_step"],
         "kernel_ms": res["kernel_ms"], "events_per_step": res["events_per_step"],
         "steps": args.steps, "warmup": args.warmup, "tuning": tun,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
-                     "peak": PEAK_VALU_SLOTS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / PEAK_VALU_SLOTS, "kernel": res["kernel"],
-                     "work_unit": "%.1f VALU issue slots per applied event" % alg}}),
+        "roofline": roofline_of(res, alg, model, W.CONFIG_NAMES[args.workload], run)}),
           flush=True)
 
 
@@ -269,7 +366,10 @@ def main():
                     help="time only the headline kernel (for profiler runs)")
     ap.add_argument("--tuning", default="",
                     metavar="BLOCK,WAVES_PER_SIMD[,REFILL_CHUNK[,SLOTS[,LANES_PER_REPLICA]]]",
-                    help="pin the launch shape (of the headline, or of --workload) instead of autotuning it")
+                    help="time this launch shape (of the headline, or of --workload) instead "
+                         "of the one in LAUNCH")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the autotuner for each persistent form instead of using LAUNCH")
     ap.add_argument("--workload", type=int, default=0, choices=(0, 1, 3),
                     help="time only the persistent form of workload 1 (gene regulation, "
                          "16384 replicas) or 3 (multi-compartment, 2048 replicas) and print "
@@ -311,46 +411,58 @@ def main():
     m2, run2 = W.config(2)
     model2 = Model(ctx, m2)
     alg2 = model2.info["alg_slots_per_event"]
+    t2q = dict(LAUNCH["sweep_plain"])
+    t2s = dict(LAUNCH["sweep_plain_pair"])
     if args.tuning:
         t2p = parse_tuning(args.tuning)
-        t2q = dict(t2p)
-    else:
+    elif args.autotune:
         t2p = model2.autotune(run2, "persistent", budget_s=5.0)
-        t2q = model2.autotune(run2, "plain", budget_s=1.0)
-    log("sweep: %s, %.1f algorithmic VALU slots/event; tuned persistent %s plain %s"
-        % (model2.info, alg2, t2p, t2q))
+    else:
+        t2p = dict(LAUNCH["sweep"])
+    log("sweep: %s, %.1f algorithmic VALU slots/event; persistent %s"
+        % (model2.info, alg2, t2p))
     pers = time_form(ctx, model2, run2, "persistent", args.steps, args.warmup, stream, t2p,
                      e2e=True)
     log("sweep persistent", pers)
     plain = None
     if not args.only_headline:
-        plain = time_form(ctx, model2, run2, "plain", max(1, args.steps // 2), 1, stream, t2q)
-        log("sweep plain", plain)
+        q_steps = max(1, args.steps // 2)
+        plain1 = time_form(ctx, model2, run2, "plain", q_steps, 1, stream, t2q)
+        log("sweep plain, one lane per trajectory", plain1)
+        plain2 = time_form(ctx, model2, run2, "plain", q_steps, 1, stream, t2s)
+        log("sweep plain, headline layout", plain2)
+        plain = {
+            # the plain launch: one lane per trajectory, natural order
+            "events_per_s": plain1["events_per_s"], "ms_per_step": plain1["ms_per_step"],
+            "kernel": plain1["kernel"], "tuning": t2q,
+            "persistent_over_plain": pers["events_per_s"] / plain1["events_per_s"],
+            "roofline": roofline_of(plain1, alg2, model2, W.CONFIG_NAMES[2], run2),
+            # the plain launch at the persistent form's own layout: the
+            # longest-first order alone
+            "same_layout": {
+                "events_per_s": plain2["events_per_s"], "ms_per_step": plain2["ms_per_step"],
+                "kernel": plain2["kernel"], "tuning": t2s,
+                "persistent_over_plain": pers["events_per_s"] / plain2["events_per_s"]}}
 
     # ---- the plain method at GPU scale and the multi-compartment model
     extra = {}
     if not args.no_extra:
-        m1, run1 = W.config(1)
-        model1 = Model(ctx, m1)
-        t1p = model1.autotune(run1, "persistent", budget_s=2.0)
-        t1q = model1.autotune(run1, "plain", budget_s=1.0)
-        g1p = time_form(ctx, model1, run1, "persistent", args.steps, args.warmup, stream, t1p)
-        g1q = time_form(ctx, model1, run1, "plain", args.steps, args.warmup, stream, t1q)
-        log("gene regulation persistent", g1p, "plain", g1q)
-        extra[W.CONFIG_NAMES[1]] = {
-            "persistent_events_per_s": g1p["events_per_s"], "plain_events_per_s": g1q["events_per_s"],
-            "events_per_step": g1p["events_per_step"], "tuning_persistent": t1p,
-            "tuning_plain": t1q}
-        m3, run3 = W.config(3)
-        model3 = Model(ctx, m3)
-        t3p = model3.autotune(run3, "persistent", budget_s=2.0)
-        g3p = time_form(ctx, model3, run3, "persistent", max(1, args.steps // 2), 1, stream, t3p)
-        g3q = time_form(ctx, model3, run3, "plain", max(1, args.steps // 2), 1, stream, None)
-        log("multi-compartment persistent", g3p, "plain", g3q)
-        extra[W.CONFIG_NAMES[3]] = {
-            "persistent_events_per_s": g3p["events_per_s"], "plain_events_per_s": g3q["events_per_s"],
-            "events_per_step": g3p["events_per_step"], "layout": "wavefront per trajectory",
-            "tuning_persistent": t3p}
+        for c in (1, 3):
+            m, run = W.config(c)
+            mo = Model(ctx, m)
+            alg = mo.info["alg_slots_per_event"]
+            tp = mo.autotune(run, "persistent", budget_s=2.0) if args.autotune else dict(LAUNCH[c])
+            tq = {"block_size": 256, "lanes_per_replica": 1 if mo.info["layout"] == 0 else 64}
+            steps = args.steps if c == 1 else max(1, args.steps // 2)
+            gp = time_form(ctx, mo, run, "persistent", steps, 1, stream, tp)
+            gq = time_form(ctx, mo, run, "plain", steps, 1, stream, tq)
+            log(W.CONFIG_NAMES[c], "persistent", gp, "plain", gq)
+            extra[W.CONFIG_NAMES[c]] = {
+                "persistent_events_per_s": gp["events_per_s"],
+                "plain_events_per_s": gq["events_per_s"],
+                "events_per_step": gp["events_per_step"], "ms_per_step": gp["ms_per_step"],
+                "tuning_persistent": tp, "tuning_plain": tq, "kernel_plain": gq["kernel"],
+                "roofline": roofline_of(gp, alg, mo, W.CONFIG_NAMES[c], run)}
 
     serving = None
     if not args.no_serve:
@@ -368,15 +480,10 @@ def main():
                    "sub_saturation_2GiB": small,
                    "p50_latency_s": sub["p50_latency_s"], "p99_latency_s": sub["p99_latency_s"]}
 
-    achieved = pers["events_per_step"] * alg2 / (pers["kernel_ms"] * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_VALU_SLOTS,
-                "traffic": measured_traffic(model2.source(), pers["kernel"]),
-                "kernel": pers["kernel"],
-                "work_unit": "%.1f VALU issue slots per applied event" % alg2}
+    roofline = roofline_of(pers, alg2, model2, W.CONFIG_NAMES[2], run2)
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(m2, run2)
+        cpu = cpu_baseline()
         log("cpu", cpu)
 
     out = {
@@ -393,9 +500,7 @@ def main():
                    "events_per_step": pers["events_per_step"], "tuning": t2p,
                    "host_to_host_events_per_s": pers.get("host_to_host_events_per_s"),
                    "host_to_host_ms": pers.get("host_to_host_ms")},
-        "plain": None if plain is None else {
-            "events_per_s": plain["events_per_s"], "ms_per_step": plain["ms_per_step"],
-            "tuning": t2q, "persistent_over_plain": pers["events_per_s"] / plain["events_per_s"]},
+        "plain": plain,
         "other_workloads": extra,
         "serving": serving,
         "roofline": roofline,

@@ -77,8 +77,16 @@ typedef int32_t cwc_status;
 #define CWC_REGION_CHILD  2   /* content of the child compartment            */
 
 /* Execution forms. */
-#define CWC_MODE_PLAIN      0  /* one lane per replica, grid covers all     */
-#define CWC_MODE_PERSISTENT 1  /* resident grid, lanes refill from a queue  */
+#define CWC_MODE_PLAIN      0  /* grid covers every trajectory, natural
+                                  order                                     */
+#define CWC_MODE_PERSISTENT 1  /* instances taken longest-first (Sec. 5.2
+                                  schema ii), launch replayed from a HIP
+                                  graph; a grid smaller than the run drains
+                                  a work queue (idle lanes claim the next
+                                  items), a grid that holds every
+                                  trajectory runs without one, the
+                                  hardware dispatcher starting blocks in
+                                  that order as others finish             */
 
 typedef struct cwc_ctx cwc_ctx;
 typedef struct cwc_model cwc_model;
@@ -153,8 +161,10 @@ typedef struct {
     int32_t layout;      /* 0 = lane per replica, 1 = wave per replica     */
     double alg_slots_per_event;  /* algorithmic VALU issue slots of one
                                     applied event (roofline work unit):
-                                    Philox4x32-10 + uniforms + log + time
-                                    (215), selection (1 + 5 log2 P), update
+                                    Philox4x32-10 (its key schedule, the
+                                    same in every lane, is scalar work and
+                                    not counted) + uniforms + log + time
+                                    (195), selection (1 + 5 log2 P), update
                                     (2 per changed cell), re-evaluation of
                                     the slots whose reactants changed and of
                                     their tree paths, averaged over slots  */
@@ -284,9 +294,10 @@ void cwc_run_destroy(cwc_run *r);
 
 /* ------------------------------------------------------------ autotuner */
 
-/* Times candidate launch shapes for this model and run -- layout (lane or
- * wavefront per replica, when the model fits both), block size (64, 128,
- * 256) and, in persistent mode, resident wavefronts per SIMD (1, 2, 4) --
+/* Times candidate launch shapes for this model and run -- lanes per
+ * trajectory (1, 2, 4 or a wavefront, as the model fits), block size (64,
+ * 128, 256), in persistent mode requested wavefronts per SIMD (16, 8, 4, 2,
+ * 1), then the sampling-buffer depth and the refill chunk --
  * on the run's own inputs with the horizon shortened so that the whole
  * search takes about `budget_s` seconds, and returns the fastest in *out.
  * The choice is stored in a tuning table on disk (the library's cache

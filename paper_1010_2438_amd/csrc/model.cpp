@@ -195,10 +195,12 @@ cwc_status flatten(const cwc_model_desc *d, Flat *f, std::string *err)
 // instructions -- 32x32->64 multiplies, the f64 reciprocal inside a
 // division -- count 4) that one applied event of the direct method needs,
 // independent of how the kernels are organised:
-//   draw:  Philox4x32-10, 10 rounds x (2 wide multiplies [4 each], 4 xor,
-//          2 key adds) = 140; two 53-bit uniforms 14; ssa_log 45 (split,
+//   draw:  Philox4x32-10, 10 rounds x (2 wide multiplies [4 each] and 4
+//          xor) = 120 (the key schedule's two adds per round act on the run
+//          seed, which is the same in every lane, so they are scalar work
+//          and not counted); two 53-bit uniforms 14; ssa_log 45 (split,
 //          fold, atanh series of 11 terms, one division); tau = -l/a0 and
-//          t + tau 15; one sample-time compare 1                     = 215
+//          t + tau 15; one sample-time compare 1                     = 195
 //   select: x = u*a0, then 5 per tree level (compare, zero test, and,
 //          subtract, select)                                  = 1 + 5 log2 P
 //   update: 2 per changed cell (add, cap compare)
@@ -212,7 +214,7 @@ double algorithmic_slots_per_event(const Flat &f)
     const int P = f.n_leaves;
     int D = 0;
     while ((1 << D) < P) ++D;
-    double fixed = 215.0 + 1.0 + 5.0 * D;
+    double fixed = 195.0 + 1.0 + 5.0 * D;
     if (f.slots.empty()) return fixed;
     auto cost = [](const Slot &s) {
         if (s.n_react == 0) return 0.0;

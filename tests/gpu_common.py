@@ -113,3 +113,26 @@ def conservation_laws(model):
             v[cell] += d
         rows.append(v)
     return integer_null_space(rows, f.n_cells)
+
+
+def oracle_ids(model, run, ids, threads=16, want_samples=True):
+    """The oracle's per-trajectory results for trajectories `ids` (any
+    order, any spread over the id range), one oracle call per trajectory on
+    `threads` host threads; rows in the order of `ids`."""
+    import threading
+    fm = oracle.FlatModel(model)
+    ids = [int(i) for i in ids]
+    rows = [None] * len(ids)
+
+    def work(k):
+        for q in range(k, len(ids), threads):
+            rows[q] = oracle.simulate(model, run, g0=ids[q], g1=ids[q] + 1,
+                                      want_samples=want_samples, want_stats=False, flat=fm)
+
+    ts = [threading.Thread(target=work, args=(k,)) for k in range(max(1, min(threads, len(ids))))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    keys = RESULT_KEYS + ("t_final",) + (("samples",) if want_samples else ())
+    return {k: np.concatenate([r[k] for r in rows]) for k in keys}

@@ -176,66 +176,6 @@ def test_tuning_validation(ctx, bad):
     assert e.value.code == -1
 
 
-def test_config2_full_size(ctx):
-    """Configuration 2 at full size (4096 instances x 64 replicas, t_end
-    100, 201 samples) in the benchmark's launch form (persistent, default
-    shape with chunked refill): 16 trajectories spread over the id range
-    match the oracle one by one, every sample of every trajectory keeps the
-    model's conservation laws, and every per-instance moment equals the
-    exact integer sums of the fetched samples."""
-    m, run = W.config(2)
-    I, R, K1 = run["n_instances"], run["replicas"], run["n_samples"]
-    print("case config2 full size", flush=True)
-    g = gpu_run(ctx, model(ctx, m), run, mode="persistent", want_digest=True)
-    assert (g["status"] == 0).all() and (g["n_recorded"] == K1).all()
-    ids = np.linspace(0, I * R - 1, 16).astype(int)
-    for i in ids:
-        o = oracle.simulate(m, run, g0=int(i), g1=int(i) + 1, want_samples=True,
-                            want_stats=False)
-        compare_trajectories(g, o, g_index=[int(i)])
-    S = g["samples"].reshape(I, R, K1, -1)
-    Wl = conservation_laws(m)                    # every sample keeps each law
-    base = oracle.FlatModel(m).init.astype(np.int64) @ Wl
-    assert Wl.shape[1] > 0
-    assert ((g["final_counts"].astype(np.int64) @ Wl) == base).all()
-    for i0 in range(0, I, 256):
-        blk = S[i0:i0 + 256].astype(np.int64)
-        assert ((blk @ Wl) == base).all()
-        assert np.array_equal(g["s1"][i0:i0 + 256], blk.sum(axis=1).astype(np.uint64))
-        sq = (blk * blk).sum(axis=1)
-        got = g["s2_hi32"][i0:i0 + 256].astype(np.int64) * 2 ** 32 + \
-            g["s2_lo32"][i0:i0 + 256].astype(np.int64)
-        assert np.array_equal(got, sq)
-    mean = S[:64].astype(np.float64).mean(axis=1)
-    assert np.allclose(g["mean"][:64], mean, rtol=1e-12, atol=0)
-
-
-def test_config1_full_size_sampled(ctx):
-    """Configuration 1 at full size (16384 replicas, t_end 100) in the
-    launch configuration the benchmark times: 16 trajectories spread over
-    the id range match the oracle one by one; every sample keeps the
-    model's conservation laws; the moments are exactly the integer sums of
-    the fetched samples."""
-    m, run = W.config(1)
-    mo = model(ctx, m)
-    g = gpu_run(ctx, mo, run, mode="persistent", want_traj=True)
-    ids = np.linspace(0, run["replicas"] - 1, 16).astype(int)
-    for i in ids:
-        o = oracle.simulate(m, run, g0=int(i), g1=int(i) + 1, want_samples=True,
-                            want_stats=False)
-        compare_trajectories(g, o, g_index=[int(i)])
-    S = g["samples"].astype(np.int64)
-    Wl = conservation_laws(m)                    # every sample keeps each law
-    assert Wl.shape[1] > 0
-    assert ((S @ Wl) == oracle.FlatModel(m).init.astype(np.int64) @ Wl).all()
-    assert (g["n_recorded"] == run["n_samples"]).all() and (g["status"] == 0).all()
-    assert np.array_equal(g["s1"][0], S.sum(axis=0).astype(np.uint64))
-    sq = (S * S).sum(axis=0)
-    assert np.array_equal(g["s2_hi32"][0].astype(np.int64) * 2 ** 32 + g["s2_lo32"][0].astype(np.int64), sq)
-    mean = S.mean(axis=0)
-    assert np.allclose(g["mean"][0], mean, rtol=1e-12, atol=0)
-
-
 # ---------------------------------------------------------------- pair layout
 
 def bursts(sizes=(600, 900, 1500, 3000, 5000, 700), name="bursts"):
@@ -497,27 +437,6 @@ def test_wave_layout_statuses(ctx):
     check(ctx, m, dict(run, count_cap=cap), tuning={"lanes_per_replica": 64})
     check(ctx, W.pure_decay(3.0, 4), W.make_run(replicas=9, dt=0.5, n_samples=12),
           tuning={"lanes_per_replica": 64})
-
-
-def test_config3_full_size_sampled(ctx):
-    """Configuration 3 at full size (2048 replicas, t_end 50, persistent):
-    4 trajectories match the oracle one by one; every sample keeps the
-    model's conservation laws; moments equal the integer sums of the
-    fetched samples."""
-    m, run = W.config(3)
-    mo = model(ctx, m)
-    g = gpu_run(ctx, mo, run, mode="persistent", want_traj=True)
-    for i in (0, 409, 1024, 2047):
-        o = oracle.simulate(m, run, g0=i, g1=i + 1, want_samples=True, want_stats=False)
-        compare_trajectories(g, o, g_index=[i])
-    S = g["samples"].astype(np.int64)
-    assert (g["status"] == 0).all()
-    Wl = conservation_laws(m)
-    assert Wl.shape[1] > 0
-    assert ((S @ Wl) == oracle.FlatModel(m).init.astype(np.int64) @ Wl).all()
-    assert np.array_equal(g["s1"][0], S.sum(axis=0).astype(np.uint64))
-    sq = (S * S).sum(axis=0)
-    assert np.array_equal(g["s2_hi32"][0].astype(np.int64) * 2 ** 32 + g["s2_lo32"][0].astype(np.int64), sq)
 
 
 def test_golden_term_without_rules(ctx):
