@@ -292,6 +292,54 @@ cwc_status cwc_run_fetch_counters(cwc_run *r, int64_t *events,
                                   int32_t *final_counts, int dst_is_device);
 void cwc_run_destroy(cwc_run *r);
 
+/* ------------------------------------------------- run without allocation */
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * simulation as cwc_run_submit (same kernels, bit-identical results), but
+ * the run's intermediate state -- exact moment accumulators, recorded-count
+ * histogram, queue cursor -- lives in a device array of
+ * CWC_NOALLOC_SCRATCH_BYTES that the library holds statically on every GPU
+ * it runs on (until the process ends), and the call allocates and frees
+ * nothing: it enqueues fill kernels, the simulation kernel and the two
+ * finalisation kernels on `hip_stream` and returns.  Synchronise the stream
+ * before reading the outputs.
+ *   d: as cwc_run_submit, except that rate_table ([I][n_rules] f64) and
+ *      init_table ([I][n_cells] i32) are DEVICE pointers (or NULL: the
+ *      model's own), their values are not checked (kinetic constants must be
+ *      finite and > 0, counts in [0, count_cap]), want_traj must be 0,
+ *      instances run in natural order, and tuning NULL means the library's
+ *      defaults (the stored autotuner table is not read).  The model's code
+ *      for the requested layout must already be loaded (it is for the
+ *      model's default layout; another layout is loaded by one
+ *      cwc_run_submit in it).
+ *   o: caller-owned device outputs, every pointer set: mean/var [I][K+1][C]
+ *      f64, n [I][K+1] i64, per trajectory events i64, status u8, digest
+ *      u64, t_final f64, n_recorded i32 [G], final_counts [G][C] i32.
+ * The scratch array is shared by every call on one GPU: calls whose work
+ * overlaps on the device (different streams or threads) race on it; calls
+ * on one stream are ordered and safe.
+ * Errors: CWC_E_INVALID (as cwc_run_submit, a missing output, want_traj, a
+ * layout not loaded), CWC_E_NOMEM when 24 x I x (K+1) x C + 8 x I x (K+2)
+ * bytes (each part rounded up to 256) plus 256 exceed the scratch array,
+ * CWC_E_DEVICE. */
+#define CWC_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+typedef struct {
+    double *mean;
+    double *var;
+    int64_t *n;
+    int64_t *events;
+    uint8_t *status;
+    uint64_t *digest;
+    double *t_final;
+    int32_t *n_recorded;
+    int32_t *final_counts;
+} cwc_run_outputs;
+
+cwc_status cwc_run_into(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d,
+                        const cwc_run_outputs *o, void *hip_stream);
+
 /* ------------------------------------------------------------ autotuner */
 
 /* Times candidate launch shapes for this model and run -- lanes per

@@ -30,7 +30,7 @@ SYMBOLS = [
     "cwc_run_query", "cwc_run_wait", "cwc_run_wait_for", "cwc_run_elapsed", "cwc_run_kernel_name",
     "cwc_run_fetch_stats",
     "cwc_run_fetch_moments", "cwc_run_fetch_trajectories",
-    "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_server_create",
+    "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_run_into", "cwc_server_create",
     "cwc_server_submit", "cwc_server_poll", "cwc_server_job_info",
     "cwc_server_fetch_stats", "cwc_server_fetch_counters", "cwc_server_release",
     "cwc_server_wait_idle", "cwc_server_get_stats", "cwc_server_destroy",
@@ -91,6 +91,12 @@ class cwc_run_desc(ctypes.Structure):
                 ("tuning", ctypes.POINTER(cwc_tuning))]
 
 
+class cwc_run_outputs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("mean", "var", "n", "events", "status", "digest", "t_final", "n_recorded",
+                 "final_counts")]
+
+
 class cwc_job_info(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("n_ticks", ctypes.c_int32),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
@@ -145,6 +151,7 @@ def load(path: str = LIB_PATH):
         "cwc_run_fetch_moments": [P, P, P, P, P, ctypes.c_int],
         "cwc_run_fetch_trajectories": [P, P, ctypes.c_int],
         "cwc_run_fetch_counters": [P, P, P, P, P, P, P, ctypes.c_int],
+        "cwc_run_into": [P, P, ctypes.POINTER(cwc_run_desc), ctypes.POINTER(cwc_run_outputs), P],
         "cwc_stats_finalize": [P, P, P, P, P, I64, I32, P, P, P],
         "cwc_stats_confidence": [P, P, I64, I32, ctypes.c_double, P],
         "cwc_server_create": [P, S, I32, I64, ctypes.POINTER(P)],
@@ -445,6 +452,35 @@ class Run:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def run_into(ctx: "Context", model: "Model", run: Dict, out: Dict, mode="plain",
+             want_digest=False, tuning: Optional[Dict] = None, rate_table=None,
+             init_table=None, stream=None):
+    """cwc_run_into: the run on `stream` with no device allocation by the
+    library.  ``out`` maps the output names of cwc_run_outputs (mean, var,
+    n, events, status, digest, t_final, n_recorded, final_counts) to device
+    tensors of the documented shapes and dtypes; ``rate_table`` /
+    ``init_table`` are device tensors or None (the model's own).  Returns
+    once the work is enqueued."""
+    L = load()
+    tun = None
+    if tuning:
+        tun = cwc_tuning(*[int(tuning.get(f, 0)) for f, _ in cwc_tuning._fields_])
+    d = cwc_run_desc(
+        run["seed"], run["n_instances"], run["replicas"],
+        None if rate_table is None else rate_table.data_ptr(),
+        None if init_table is None else init_table.data_ptr(),
+        run["dt"], run["n_samples"], MODE_PERSISTENT if mode == "persistent" else MODE_PLAIN,
+        0, int(want_digest), run["count_cap"], run["max_events"],
+        ctypes.pointer(tun) if tun is not None else None)
+    o = cwc_run_outputs(*[out[f].data_ptr() if out.get(f) is not None else None
+                          for f, _ in cwc_run_outputs._fields_])
+    check(L.cwc_run_into(ctx.h, model.h, ctypes.byref(d), ctypes.byref(o),
+                         _stream_handle(stream)))
 
 
 def _run_desc(run: Dict, want_digest=False):

@@ -194,19 +194,10 @@ cwc_status validate_run(const cwc_model *m, const cwc_run_desc *d, std::vector<d
                         std::vector<int> *init_out)
 {
     const Flat &f = m->flat;
-    if (d->n_instances < 1 || d->replicas_per_instance < 1)
-        return set_err(CWC_E_INVALID, "n_instances and replicas_per_instance must be >= 1");
-    if (d->n_instances > (1ll << 31) || d->replicas_per_instance > (1ll << 31) ||
-        d->n_instances * d->replicas_per_instance > (1ll << 31))
-        return set_err(CWC_E_INVALID, "at most 2^31 trajectories per run");
-    if (!(std::isfinite(d->dt) && d->dt > 0.0))
-        return set_err(CWC_E_INVALID, "dt must be finite and > 0");
-    if (d->n_samples < 1 || d->n_samples > (1 << 24))
-        return set_err(CWC_E_INVALID, "n_samples must be in [1, 2^24]");
-    if (!std::isfinite(d->dt * (double)(d->n_samples - 1)))
-        return set_err(CWC_E_INVALID, "last sample time is not finite");
-    if (d->count_cap < 1) return set_err(CWC_E_INVALID, "count_cap must be >= 1");
-    if (d->max_events < 0) return set_err(CWC_E_INVALID, "max_events must be >= 0");
+    {
+        cwc_status sst = validate_run_sizes(d);
+        if (sst != CWC_OK) return sst;
+    }
     const long long I = d->n_instances;
     const int C = f.n_cells;
     std::vector<double> &rates = *rates_out;
@@ -229,6 +220,112 @@ cwc_status validate_run(const cwc_model *m, const cwc_run_desc *d, std::vector<d
         if (v < 0 || v > d->count_cap)
             return set_err(CWC_E_INVALID, "initial count outside [0, count_cap]");
 
+    return CWC_OK;
+}
+
+// The scalar fields of a run descriptor: sizes, sample grid, caps.
+cwc_status validate_run_sizes(const cwc_run_desc *d)
+{
+    if (d->n_instances < 1 || d->replicas_per_instance < 1)
+        return set_err(CWC_E_INVALID, "n_instances and replicas_per_instance must be >= 1");
+    if (d->n_instances > (1ll << 31) || d->replicas_per_instance > (1ll << 31) ||
+        d->n_instances * d->replicas_per_instance > (1ll << 31))
+        return set_err(CWC_E_INVALID, "at most 2^31 trajectories per run");
+    if (!(std::isfinite(d->dt) && d->dt > 0.0))
+        return set_err(CWC_E_INVALID, "dt must be finite and > 0");
+    if (d->n_samples < 1 || d->n_samples > (1 << 24))
+        return set_err(CWC_E_INVALID, "n_samples must be in [1, 2^24]");
+    if (!std::isfinite(d->dt * (double)(d->n_samples - 1)))
+        return set_err(CWC_E_INVALID, "last sample time is not finite");
+    if (d->count_cap < 1) return set_err(CWC_E_INVALID, "count_cap must be >= 1");
+    if (d->max_events < 0) return set_err(CWC_E_INVALID, "max_events must be >= 0");
+    return CWC_OK;
+}
+
+// Launch shape of a run: tuning defaults and checks, layout (lanes per
+// trajectory), block (narrowed until the lane layout's LDS fits), grid and
+// kernel.  `tuned`: `tun` came from the autotuner's table.  `may_compile`:
+// the layout's module may be compiled and loaded here; otherwise it must
+// already be loaded.
+cwc_status plan_launch(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d, cwc_tuning tun,
+                       bool tuned, bool may_compile, LaunchPlan *out)
+{
+    const Flat &f = m->flat;
+    const long long G = d->n_instances * d->replicas_per_instance;
+    const int C = f.n_cells;
+    if (tun.block_size <= 0) tun.block_size = 64;
+    if (tun.block_size % 64 || tun.block_size > 256)
+        return set_err(CWC_E_INVALID, "block_size must be a multiple of 64, at most 256");
+    if (tun.waves_per_simd <= 0) tun.waves_per_simd = 2;
+    if (tun.waves_per_simd > 16) return set_err(CWC_E_INVALID, "waves_per_simd must be <= 16");
+    if (tun.refill_chunk <= 0) tun.refill_chunk = 64;
+    if (tun.refill_chunk > 1 && tun.refill_chunk < 64)
+        return set_err(CWC_E_INVALID, "refill_chunk must be 1 or at least 64");
+    if (tun.sample_slots <= 0) tun.sample_slots = kDefaultSampleSlots;
+    if (tun.sample_slots > 64 || (tun.sample_slots & (tun.sample_slots - 1)))
+        return set_err(CWC_E_INVALID, "sample_slots must be a power of two, at most 64");
+    int layout = f.layout;
+    const bool pair = tun.lanes_per_replica == 2;
+    const bool quad = tun.lanes_per_replica == 4;
+    if (tun.lanes_per_replica == 1 || pair || quad) layout = 0;
+    else if (tun.lanes_per_replica == 64) layout = 1;
+    else if (tun.lanes_per_replica != 0)
+        return set_err(CWC_E_UNSUPPORTED, "lanes_per_replica must be 0 (auto), 1, 2, 4 or 64");
+    if (may_compile) {
+        cwc_status lst = ensure_layout(const_cast<cwc_model *>(m), layout);
+        if (lst != CWC_OK) return lst;
+    } else if (!layout_loaded(m, layout)) {
+        return set_err(CWC_E_INVALID,
+                       "the model's code for the %s layout is not loaded (submit one run in "
+                       "that layout with cwc_run_submit first)",
+                       layout == 1 ? "wavefront-per-replica" : "lane-per-replica");
+    }
+    if (pair && !m->pair_fn[0])
+        return set_err(CWC_E_UNSUPPORTED, "two lanes per trajectory need at least two leaves");
+    if (quad && !m->quad_fn[0])
+        return set_err(CWC_E_UNSUPPORTED, "four lanes per trajectory need at least four leaves");
+    const int group = quad ? 4 : (pair ? 2 : 1);   // lanes per trajectory (lane module)
+    tun.lanes_per_replica = layout == 1 ? 64 : group;   // as launched
+
+    const bool shared = !(d->rate_table && f.n_rules > 0);
+    const bool wave = layout == 1;
+    if (wave && !tuned && (!d->tuning || d->tuning->block_size <= 0)) tun.block_size = 256;
+    unsigned block = (unsigned)tun.block_size;
+    // the lane layout's per-wavefront LDS (staging + accumulator cache)
+    // grows with the cell count: narrow the block until it fits
+    while (!wave && block > 64 &&
+           cwc_lane_lds_bytes(C, (int)(block / 64), tun.sample_slots) > ctx->max_lds)
+        block /= 2;
+    if (!wave && cwc_lane_lds_bytes(C, 1, tun.sample_slots) > ctx->max_lds)
+        return set_err(CWC_E_INVALID, "sample_slots too large for this model's cells");
+    // lane layout: one trajectory per lane (two or four lanes per trajectory
+    // in the pair and quad forms); wavefront layout: one per wave
+    const long long per_block = wave ? block / 64 : block / group;
+    const long long need_blocks = (G + per_block - 1) / per_block;
+    unsigned grid;
+    int k;
+    if (d->mode == CWC_MODE_PERSISTENT) {
+        long long resident = (long long)ctx->n_cu * 4 * tun.waves_per_simd * 64 / block;
+        grid = (unsigned)std::max(1ll, std::min(need_blocks, resident));
+        // a grid that already holds every trajectory has nothing to refill:
+        // the queue would stay empty, so the kernel without the refill
+        // bookkeeping runs the same computation, its blocks (dispatched as
+        // others finish) taking the items in the same longest-first order
+        const bool covers = (long long)grid * per_block >= G;
+        k = covers ? (shared ? 0 : 1) : (shared ? 2 : 3);
+    } else {
+        k = shared ? 0 : 1;
+        grid = (unsigned)need_blocks;
+    }
+    out->fn = quad ? m->quad_fn[k] : (pair ? m->pair_fn[k] : m->fn[layout][k]);
+    out->kernel = kernel_name(layout, group, k);
+    out->grid = grid;
+    out->block = block;
+    out->layout = layout;
+    out->group = group;
+    out->n_threads = (unsigned long long)grid * (unsigned long long)per_block;
+    out->lds = wave ? 0u : (unsigned)cwc_lane_lds_bytes(C, (int)(block / 64), tun.sample_slots);
+    out->tun = tun;
     return CWC_OK;
 }
 
@@ -263,34 +360,12 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     } else {
         tuned = tuning_lookup(m, d, &tun);
     }
-    if (tun.block_size <= 0) tun.block_size = 64;
-    if (tun.block_size % 64 || tun.block_size > 256)
-        return set_err(CWC_E_INVALID, "block_size must be a multiple of 64, at most 256");
-    if (tun.waves_per_simd <= 0) tun.waves_per_simd = 2;
-    if (tun.waves_per_simd > 16) return set_err(CWC_E_INVALID, "waves_per_simd must be <= 16");
-    if (tun.refill_chunk <= 0) tun.refill_chunk = 64;
-    if (tun.refill_chunk > 1 && tun.refill_chunk < 64)
-        return set_err(CWC_E_INVALID, "refill_chunk must be 1 or at least 64");
-    if (tun.sample_slots <= 0) tun.sample_slots = kDefaultSampleSlots;
-    if (tun.sample_slots > 64 || (tun.sample_slots & (tun.sample_slots - 1)))
-        return set_err(CWC_E_INVALID, "sample_slots must be a power of two, at most 64");
-    int layout = f.layout;
-    const bool pair = tun.lanes_per_replica == 2;
-    const bool quad = tun.lanes_per_replica == 4;
-    if (tun.lanes_per_replica == 1 || pair || quad) layout = 0;
-    else if (tun.lanes_per_replica == 64) layout = 1;
-    else if (tun.lanes_per_replica != 0)
-        return set_err(CWC_E_UNSUPPORTED, "lanes_per_replica must be 0 (auto), 1, 2, 4 or 64");
+    LaunchPlan plan;
     {
-        cwc_status lst = ensure_layout(const_cast<cwc_model *>(m), layout);
-        if (lst != CWC_OK) return lst;
+        cwc_status pst = plan_launch(ctx, m, d, tun, tuned, true, &plan);
+        if (pst != CWC_OK) return pst;
     }
-    if (pair && !m->pair_fn[0])
-        return set_err(CWC_E_UNSUPPORTED, "two lanes per trajectory need at least two leaves");
-    if (quad && !m->quad_fn[0])
-        return set_err(CWC_E_UNSUPPORTED, "four lanes per trajectory need at least four leaves");
-    const int group = quad ? 4 : (pair ? 2 : 1);   // lanes per trajectory (lane module)
-    tun.lanes_per_replica = layout == 1 ? 64 : group;   // as launched
+    tun = plan.tun;
 
     auto r = new cwc_run();
     r->ctx = ctx;
@@ -379,41 +454,12 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
         kp.order = d_order;
     }
 
-    const bool shared = kp.rate_stride == 0;
-    const bool wave = layout == 1;
-    if (wave && !tuned && (!d->tuning || d->tuning->block_size <= 0)) tun.block_size = 256;
-    r->block = (unsigned)tun.block_size;
-    // the lane layout's per-wavefront LDS (staging + accumulator cache)
-    // grows with the cell count: narrow the block until it fits
-    while (!wave && r->block > 64 &&
-           cwc_lane_lds_bytes(C, (int)(r->block / 64), tun.sample_slots) > ctx->max_lds)
-        r->block /= 2;
-    if (!wave && cwc_lane_lds_bytes(C, 1, tun.sample_slots) > ctx->max_lds)
-        return set_err(CWC_E_INVALID, "sample_slots too large for this model's cells");
-    // lane layout: one trajectory per lane (two or four lanes per trajectory
-    // in the pair and quad forms);
-    // wavefront layout: one per wave
-    const long long per_block = wave ? r->block / 64 : r->block / group;
-    const long long need_blocks = (G + per_block - 1) / per_block;
-    if (d->mode == CWC_MODE_PERSISTENT) {
-        long long resident = (long long)ctx->n_cu * 4 * tun.waves_per_simd * 64 / r->block;
-        r->grid = (unsigned)std::max(1ll, std::min(need_blocks, resident));
-        // a grid that already holds every trajectory has nothing to refill:
-        // the queue would stay empty, so the kernel without the refill
-        // bookkeeping runs the same computation, its blocks (dispatched as
-        // others finish) taking the items in the same longest-first order
-        const bool covers = (long long)r->grid * per_block >= G;
-        const int k = covers ? (shared ? 0 : 1) : (shared ? 2 : 3);
-        r->fn = quad ? m->quad_fn[k] : (pair ? m->pair_fn[k] : m->fn[layout][k]);
-        r->kernel = kernel_name(layout, group, k);
-    } else {
-        const int k = shared ? 0 : 1;
-        r->fn = quad ? m->quad_fn[k] : (pair ? m->pair_fn[k] : m->fn[layout][k]);
-        r->kernel = kernel_name(layout, group, k);
-        r->grid = (unsigned)need_blocks;
-    }
-    r->n_threads = (unsigned long long)r->grid * (unsigned long long)per_block;
-    r->lds = wave ? 0u : (unsigned)cwc_lane_lds_bytes(C, (int)(r->block / 64), tun.sample_slots);
+    r->block = plan.block;
+    r->grid = plan.grid;
+    r->fn = plan.fn;
+    r->kernel = plan.kernel;
+    r->n_threads = plan.n_threads;
+    r->lds = plan.lds;
 
     if (hipEventCreate(&r->ev_start) != hipSuccess || hipEventCreate(&r->ev_sim) != hipSuccess ||
         hipEventCreate(&r->ev_end) != hipSuccess) {

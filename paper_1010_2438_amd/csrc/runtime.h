@@ -25,6 +25,7 @@ struct cwc_ctx {
     std::map<void *, size_t> sizes;           // live allocations
     std::mutex mu;
     hipStream_t capture_stream = nullptr;
+    void *scratch = nullptr;            // this device's no-allocation scratch array
     // models, runs and servers hold the context: cwc_ctx_destroy marks it
     // closed and it is freed when the last of them is destroyed
     std::atomic<int> refs{0};
@@ -50,6 +51,8 @@ struct cwc_model {
                                         // shared/table); null with fewer than four leaves
     hipFunction_t pair_fn[6] = {};      // lane module's pair kernels (plain/persistent/
                                         // slice x shared/table); null with one leaf
+    double *d_k = nullptr;              // device copies of the model's kinetic
+    int *d_init = nullptr;              // constants and initial counts
     std::mutex mu;
 };
 
@@ -75,6 +78,24 @@ bool tuning_lookup(const cwc_model *m, const cwc_run_desc *d, cwc_tuning *out);
 // Checks a run descriptor; host copies of the rate / initial-state tables.
 cwc_status validate_run(const cwc_model *m, const cwc_run_desc *d, std::vector<double> *rates,
                         std::vector<int> *init);
+// Checks the scalar fields of a run descriptor (sizes, sample grid, caps).
+cwc_status validate_run_sizes(const cwc_run_desc *d);
+// Whether the model's code for `layout` is compiled and loaded.
+bool layout_loaded(const cwc_model *m, int layout);
+// Launch shape of a run (see run.cpp).
+struct LaunchPlan {
+    cwc_tuning tun{};                   // as launched
+    int layout = 0, group = 1;          // module; lanes per trajectory
+    hipFunction_t fn = nullptr;
+    std::string kernel;
+    unsigned grid = 0, block = 0, lds = 0;
+    unsigned long long n_threads = 0;   // trajectory slots of the grid
+};
+cwc_status plan_launch(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d, cwc_tuning tun,
+                       bool tuned, bool may_compile, LaunchPlan *out);
+// Device address of the no-allocation entry point's scratch array on the
+// current device (looked up once per device).
+cwc_status scratch_address(int device, void **ptr);
 }
 
 struct cwc_run {
