@@ -231,7 +231,7 @@ typedef struct {
     double dt;                      /* sample spacing > 0                       */
     int32_t n_samples;              /* K + 1 >= 1 sample times k*dt             */
     int32_t mode;                   /* CWC_MODE_*                               */
-    int32_t want_traj;              /* keep samples [G][K+1][C]                 */
+    int32_t want_traj;              /* keep samples [K+1][C][G]                 */
     int32_t want_digest;            /* keep an FNV-1a digest of fired leaves    */
     int32_t count_cap;              /* > 0; typically INT32_MAX                 */
     int64_t max_events;             /* per trajectory; 0 = unlimited            */
@@ -279,8 +279,15 @@ cwc_status cwc_run_fetch_stats(cwc_run *r, double *mean, double *var,
 cwc_status cwc_run_fetch_moments(cwc_run *r, uint64_t *s1, uint64_t *s2_hi32,
                                  uint64_t *s2_lo32, int64_t *n,
                                  int dst_is_device);
-/* Samples [G][K+1][C] int32 (requires want_traj); entries at or after a
- * trajectory's n_recorded are unspecified. */
+/* Sampled trajectories (paper Sec. 3: states at fixed simulation times,
+ * the simulator's primary output beside the on-line statistics).  Layout
+ * [K+1][C][G] int32, trajectory fastest: cell c of sample k of trajectory g
+ * is dst[(k * C + c) * G + g] (the kernels write it in place, so lanes that
+ * record the same sample write neighbouring words).  Requires want_traj;
+ * entries of samples at or after a trajectory's n_recorded are unspecified.
+ * dst is caller-owned, G * (K+1) * C int32, host or device memory
+ * (dst_is_device).  Errors: CWC_E_NOTREADY before completion, CWC_E_INVALID
+ * for a run submitted without want_traj. */
 cwc_status cwc_run_fetch_trajectories(cwc_run *r, int32_t *dst,
                                       int dst_is_device);
 /* Per trajectory [G]: applied events, terminal status, digest (0 unless

@@ -437,8 +437,16 @@ class Run:
                                                    "n_recorded", "final_counts")], 0))
         return out
 
-    def trajectories(self):
-        t = np.empty((self.G, self.K1, self.C), np.int32)
+    def trajectories(self, out=None):
+        """Samples [K+1][C][G] int32 (trajectory fastest).  With ``out`` (a
+        contiguous int32 device tensor of that shape) they are copied device
+        to device into it and it is returned."""
+        if out is not None:
+            assert out.is_cuda and out.dtype.itemsize == 4 and out.is_contiguous()
+            assert tuple(out.shape) == (self.K1, self.C, self.G)
+            check(load().cwc_run_fetch_trajectories(self.h, out.data_ptr(), 1))
+            return out
+        t = np.empty((self.K1, self.C, self.G), np.int32)
         check(load().cwc_run_fetch_trajectories(self.h, t.ctypes.data, 0))
         return t
 

@@ -46,6 +46,14 @@
 // back.  h maps the consecutive samples of one instance to consecutive
 // slots and scatters instances over the slots.  All sums are exact
 // integers: the result does not depend on the order or on the depth.
+// Sampled trajectories are kept [sample][cell][trajectory], trajectory
+// fastest: cell c of sample k of local trajectory lg sits at
+// (k * C + c) * G + lg, so the lanes of a wavefront that record the same
+// sample write neighbouring words of each cell row.  The pointer to
+// (k, cell 0, lg); cell c is c * G further on.
+#define CWC_TRAJ_AT(p, lg, kn)                                                \
+    ((p).traj ? (p).traj + (i64)(kn) * (i64)CWC_C * (p).G + (lg) : (i32 *)0)
+
 struct cwc_acc {
     unsigned long long *tag;   // [nslot]  instance * K1 + sample, ~0 = empty
     unsigned long long *s1;    // [nslot][C]
@@ -129,7 +137,7 @@ __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const cwc
                 atomicAdd(r1 + c, x);
                 atomicAdd(r2 + c, q & 0xFFFFFFFFull);
                 if (q >> 32) atomicAdd(p.s2_hi32 + key * (u64)CWC_C + c, q >> 32);
-                if (tr) tr[c] = v;
+                if (tr) tr[(i64)c * p.G] = v;
             }
             pending = false;
         }
@@ -232,7 +240,7 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
 // emit sample kn of the current state and move to the next sample time
 #define CWC_EMIT()                                                            \
     do {                                                                      \
-        i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+        i32 *tr_ = CWC_TRAJ_AT(p, lg, kn); \
         CWC_STAGE(col, 64);                                                   \
         cwc_emit_moments(p, acc, col, inst, kn, tr_);                         \
         kn += 1;                                                              \
@@ -606,7 +614,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
 #define CWC_PEMIT()                                                           \
     do {                                                                      \
         if (h_ == 0) {                                                        \
-            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+            i32 *tr_ = CWC_TRAJ_AT(p, lg, kn); \
             CWC_STAGE(col, 64);                                               \
             cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
         }                                                                     \
@@ -714,7 +722,7 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
 #define CWC_PEMIT()                                                           \
     do {                                                                      \
         if (h_ == 0) {                                                        \
-            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+            i32 *tr_ = CWC_TRAJ_AT(p, lg, kn); \
             CWC_STAGE(col, 64);                                               \
             cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
         }                                                                     \
@@ -918,7 +926,7 @@ __device__ __forceinline__ void cwc_quad_main(const cwc_kparams &p)
 #define CWC_QEMIT()                                                           \
     do {                                                                      \
         if (h_ == 0) {                                                        \
-            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+            i32 *tr_ = CWC_TRAJ_AT(p, lg, kn); \
             CWC_STAGE(col, 64);                                               \
             cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
         }                                                                     \

@@ -84,7 +84,7 @@ __device__ __forceinline__ void cwc_wave_emit(const cwc_kparams &p, const i32 *c
         atomicAdd(p.s1 + row + cell, x);
         atomicAdd(p.s2_lo32 + row + cell, q & 0xFFFFFFFFull);
         if (q >> 32) atomicAdd(p.s2_hi32 + row + cell, q >> 32);
-        if (tr) tr[cell] = v;
+        if (tr) tr[(i64)cell * p.G] = v;   /* [sample][cell][trajectory] */
     }
 }
 
@@ -159,7 +159,7 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
     do {                                                                      \
         if (kind >= 0) {                                                      \
             const i64 row_ = (inst * (i64)p.K1 + kn) * (i64)CWC_C;            \
-            i32 *tr_ = p.traj ? p.traj + (lg * p.K1 + kn) * (i64)CWC_C : (i32 *)0; \
+            i32 *tr_ = p.traj ? p.traj + (i64)kn * (i64)CWC_C * p.G + lg : (i32 *)0; \
             CWC_STAGE(col, 64);                                               \
             cwc_wave_emit(p, col, row_, tr_, cb, wb);                         \
         }                                                                     \

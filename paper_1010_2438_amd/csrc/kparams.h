@@ -26,7 +26,7 @@ struct cwc_kparams {
     unsigned long long *digest;  // [G]
     unsigned char *status;    // [G]
     int *n_recorded;          // [G]
-    int *traj;                // [G][K1][C] or null
+    int *traj;                // [K1][C][G] (trajectory fastest) or null
     // on-line moments, indexed by instance ((g - g_base) / R) and sample
     unsigned long long *s1;       // [I][K1][C]
     unsigned long long *s2_hi32;  // [I][K1][C]

@@ -19,8 +19,20 @@ def gpu_run(ctx, model_obj, run, mode="plain", want_traj=True, want_digest=True,
     out["mean"], out["var"], out["n"] = r.stats()
     out["s1"], out["s2_hi32"], out["s2_lo32"], _ = r.moments()
     if want_traj:
-        out["samples"] = r.trajectories()
+        out["samples"] = per_trajectory(r.trajectories())
     r.close()
+    return out
+
+
+def per_trajectory(t):
+    """The library's sample layout [sample][cell][trajectory] as
+    [trajectory][sample][cell] (the oracle's), copied in blocks of
+    trajectories so each read is a run of contiguous words."""
+    K1, C, G = t.shape
+    out = np.empty((G, K1, C), t.dtype)
+    step = 8192
+    for g0 in range(0, G, step):
+        out[g0:g0 + step] = t[:, :, g0:g0 + step].transpose(2, 0, 1)
     return out
 
 

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.gpu_common import compare_stats, compare_trajectories
+from tests.gpu_common import compare_stats, compare_trajectories, per_trajectory
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +29,7 @@ def results(r, want_traj=True):
     out["mean"], out["var"], out["n"] = r.stats()
     out["s1"], out["s2_hi32"], out["s2_lo32"], _ = r.moments()
     if want_traj:
-        out["samples"] = r.trajectories()
+        out["samples"] = per_trajectory(r.trajectories())
     return out
 
 
