@@ -6,3 +6,4 @@ imports nor links anything from here.
 """
 from .cwc import (FlatModel, build, draw, finalize, philox, select, simulate,  # noqa: F401
                   ssa_log, STATUS)
+from .gcwc import GModel, gsimulate  # noqa: F401

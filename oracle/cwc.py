@@ -47,7 +47,7 @@ STATUS = {0: "OK", 1: "ABSORBED", 2: "OVERFLOW", 3: "EVENT_CAP"}
 
 
 def build(force: bool = True) -> str:
-    """Compile ssa.c with gcc: -O2, no contraction of a*b+c into FMA, no
+    """Compile ssa.c and gcwc.c with gcc: -O2, no contraction of a*b+c into FMA, no
     fast-math, so every floating-point operation is one IEEE binary64
     rounding."""
     os.makedirs(BUILD, exist_ok=True)
@@ -55,7 +55,8 @@ def build(force: bool = True) -> str:
         tmp = LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
-             "-fPIC", "-shared", "-o", tmp, os.path.join(HERE, "ssa.c"), "-lm"])
+             "-fPIC", "-shared", "-o", tmp, os.path.join(HERE, "ssa.c"),
+             os.path.join(HERE, "gcwc.c"), "-lm"])
         os.replace(tmp, LIB)
     return LIB
 

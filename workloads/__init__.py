@@ -38,6 +38,8 @@ __all__ = [
     "transport", "receptor_binding", "paper_example",
     "make_run", "sweep_rate_table", "arrival_trace", "config",
     "n_cells", "CONFIG_NAMES",
+    "general_from_fixed", "cell_birth_death", "cell_dissolution", "nested_export",
+    "receptor_internalisation", "cell_colony",
 ]
 
 CONFIG_NAMES = {
@@ -266,6 +268,153 @@ def receptor_binding(k_on=0.02, k_off=0.5, k_int=0.1, n_lig=40, n_rec=10,
                       {"name": "cell", "wrap": True}],
             "compartments": comps, "init": init, "init_wrap": init_wrap,
             "rules": rules}
+
+
+# ---------------------------------------------------------------------------
+# General CWC models: compartments created, dissolved and deleted at run
+# time; patterns that reach a grandchild compartment (paper Sec. 2.1)
+# ---------------------------------------------------------------------------
+#
+# A general model lists ``labels`` (compartment types with a wrap flag), a
+# slot capacity ``max_comp`` (<= 64), the initial ``term`` (compartments in
+# preorder, each {"label", "parent", "content", "wrap"}; entry 0 is the top
+# level) and ``rules``, each applied in the content of a compartment of
+# label ``context``, naming optionally a ``child`` compartment of a label
+# inside it and a ``grandchild`` inside that (-1 = none).  ``lhs``/``rhs``
+# give atom multiplicities per region: "c" the context's content, "w1"/"c1"
+# the child's wrap/content, "w2"/"c2" the grandchild's; unnamed atoms of a
+# region are the pattern's variable (x / X) and are kept.  ``action``:
+#   "create"   a compartment {"label", "wrap", "content"} (``new``) in the
+#              context (level 0), the child (1) or the grandchild (2);
+#   "dissolve" the child (level 1) or grandchild (2): its content (atoms and
+#              compartments), and its wrap atoms if ``release_wrap``, pass to
+#              its parent's content -- O = X in the pattern (x | X)^l -> X;
+#   "delete"   the child or grandchild with everything in it.
+
+def _grule(context, lhs, rhs, k, child=-1, grandchild=-1, action="none", level=0, new=None,
+           release_wrap=False):
+    return {"context": int(context), "child": int(child), "grandchild": int(grandchild),
+            "lhs": {r: {int(a): int(m) for a, m in v.items()} for r, v in lhs.items()},
+            "rhs": {r: {int(a): int(m) for a, m in v.items()} for r, v in rhs.items()},
+            "action": action, "level": int(level), "new": new,
+            "release_wrap": bool(release_wrap), "k": float(k)}
+
+
+def general_from_fixed(model, max_comp=None):
+    """A fixed-tree model written as a general one (same compartments as the
+    initial term, same rules, no structural action): the general engine
+    must simulate it exactly as the fixed-tree engine does."""
+    comps = model["compartments"]
+    iw = model.get("init_wrap") or [None] * len(comps)
+    term = [{"label": c["type"], "parent": c["parent"], "content": list(model["init"][i]),
+             "wrap": None if iw[i] is None else list(iw[i])} for i, c in enumerate(comps)]
+    rules = []
+    for r in model["rules"]:
+        reg = {"p": "c", "w": "w1", "c": "c1"}
+        lhs = {reg[q]: v for q, v in r["lhs"].items()}
+        rhs = {reg[q]: v for q, v in r["rhs"].items()}
+        rules.append(_grule(r["parent"], lhs, rhs, r["k"], child=r["child"]))
+    return {"name": model["name"] + "_general", "species": list(model["species"]),
+            "labels": [dict(t) for t in model["types"]],
+            "max_comp": int(max_comp or len(comps)), "term": term, "rules": rules}
+
+
+def cell_birth_death(lam=3.0, mu=1.0, n0=2, max_comp=32):
+    """Cells appear in the top level at rate lam (an empty compartment is
+    created) and each is removed at rate mu: the number of cells is a
+    birth-death process, Binomial(n0, e^-mu t) + Poisson(lam/mu (1 - e^-mu t))."""
+    term = [{"label": 0, "parent": -1, "content": [0], "wrap": None}]
+    term += [{"label": 1, "parent": 0, "content": [0], "wrap": [0]} for _ in range(n0)]
+    rules = [_grule(0, {}, {}, lam, action="create", level=0,
+                    new={"label": 1, "wrap": [0], "content": [0]}),
+             _grule(0, {}, {}, mu, child=1, action="delete", level=1)]
+    return {"name": "cell_birth_death", "species": ["a"],
+            "labels": [{"name": "top", "wrap": False}, {"name": "cell", "wrap": True}],
+            "max_comp": max_comp, "term": term, "rules": rules}
+
+
+def cell_dissolution(n_cells_=3, a_per_cell=2, w_per_cell=1, mu=0.7, k_out=0.5,
+                     release_wrap=True, max_comp=8):
+    """Cells holding atoms a (content) and w (wrap) dissolve at rate mu,
+    releasing their content -- and their wrap atoms if ``release_wrap`` --
+    into the top level, where a decays at rate k_out.  (x | X)^cell -> X."""
+    A, Wd = 0, 1
+    term = [{"label": 0, "parent": -1, "content": [0, 0], "wrap": None}]
+    term += [{"label": 1, "parent": 0, "content": [a_per_cell, 0], "wrap": [0, w_per_cell]}
+             for _ in range(n_cells_)]
+    rules = [_grule(0, {}, {}, mu, child=1, action="dissolve", level=1,
+                    release_wrap=release_wrap),
+             _grule(0, {"c": {A: 1}}, {}, k_out)]
+    return {"name": "cell_dissolution", "species": ["a", "w"],
+            "labels": [{"name": "top", "wrap": False}, {"name": "cell", "wrap": True}],
+            "max_comp": max_comp, "term": term, "rules": rules}
+
+
+def nested_export(n_outer=2, n_inner=2, s0=2, k_mk=0.8, k_exp=1.3, k_deg=0.4, max_comp=16):
+    """Two levels below the top: outer compartments hold inner ones.  Inner
+    compartments turn s into b; a depth-2 pattern at the top moves b from an
+    inner compartment's content to its outer's,
+    (x | (y | b Y)^in X)^out -> (x | (y | Y)^in b X)^out; b decays in outers."""
+    S, B = 0, 1
+    term = [{"label": 0, "parent": -1, "content": [0, 0], "wrap": None}]
+    for o in range(n_outer):
+        po = len(term)
+        term.append({"label": 1, "parent": 0, "content": [0, 0], "wrap": [0, 0]})
+        for _ in range(n_inner):
+            term.append({"label": 2, "parent": po, "content": [s0, 0], "wrap": [0, 0]})
+    rules = [_grule(2, {"c": {S: 1}}, {"c": {B: 1}}, k_mk),
+             _grule(0, {"c2": {B: 1}}, {"c1": {B: 1}}, k_exp, child=1, grandchild=2),
+             _grule(1, {"c": {B: 1}}, {}, k_deg)]
+    return {"name": "nested_export", "species": ["s", "b"],
+            "labels": [{"name": "top", "wrap": False}, {"name": "out", "wrap": True},
+                       {"name": "in", "wrap": True}],
+            "max_comp": max_comp, "term": term, "rules": rules}
+
+
+def receptor_internalisation(n_cells_=2, r0=3, l0=4, k_on=0.3, k_int=0.8, k_ves=0.6,
+                             max_comp=16):
+    """Wrap variables and creation below the context: a ligand L in the top
+    binds a receptor R on a cell's wrap, L (R x | X)^cell -> (RL x | X)^cell;
+    a bound receptor is internalised by creating a vesicle inside the cell,
+    (RL x | X)^cell -> (x | (RL | )^ves X)^cell; vesicles dissolve into the
+    cell's content, releasing RL there."""
+    L, R, RL = 0, 1, 2
+    term = [{"label": 0, "parent": -1, "content": [l0, 0, 0], "wrap": None}]
+    term += [{"label": 1, "parent": 0, "content": [0, 0, 0], "wrap": [0, r0, 0]}
+             for _ in range(n_cells_)]
+    rules = [_grule(0, {"c": {L: 1}, "w1": {R: 1}}, {"w1": {RL: 1}}, k_on, child=1),
+             _grule(0, {"w1": {RL: 1}}, {}, k_int, child=1, action="create", level=1,
+                    new={"label": 2, "wrap": [0, 0, 1], "content": [0, 0, 0]}),
+             _grule(1, {}, {}, k_ves, child=2, action="dissolve", level=1, release_wrap=True)]
+    return {"name": "receptor_internalisation", "species": ["L", "R", "RL"],
+            "labels": [{"name": "top", "wrap": False}, {"name": "cell", "wrap": True},
+                       {"name": "ves", "wrap": True}],
+            "max_comp": max_comp, "term": term, "rules": rules}
+
+
+def cell_colony(n0=8, nutrient=2000, k_up=0.002, k_grow=1.0, k_div=0.05, k_die=0.02,
+                k_feed=200.0, max_comp=64, model_seed=5):
+    """A colony of cells in a nutrient bath: nutrients N enter cells across
+    the wrap, N (x | X)^cell -> (x | N X)^cell; inside, N becomes biomass A;
+    a cell with two units of biomass divides, creating a new cell in the
+    top level that takes one unit, (x | A A X)^cell -> (x | A X)^cell (| A)^cell;
+    cells die (deleted with their content); nutrients are fed to the top.
+    Initial cell contents are drawn once from ``model_seed``."""
+    Nn, A = 0, 1
+    rng = np.random.default_rng(model_seed)
+    term = [{"label": 0, "parent": -1, "content": [nutrient, 0], "wrap": None}]
+    for _ in range(n0):
+        term.append({"label": 1, "parent": 0, "content": [0, int(rng.integers(1, 6))],
+                     "wrap": [0, 0]})
+    rules = [_grule(0, {"c": {Nn: 1}}, {"c1": {Nn: 1}}, k_up, child=1),
+             _grule(1, {"c": {Nn: 1}}, {"c": {A: 1}}, k_grow),
+             _grule(0, {"c1": {A: 2}}, {"c1": {A: 1}}, k_div, child=1, action="create",
+                    level=0, new={"label": 1, "wrap": [0, 0], "content": [0, 1]}),
+             _grule(0, {}, {}, k_die, child=1, action="delete", level=1),
+             _grule(0, {}, {"c": {Nn: 1}}, k_feed)]
+    return {"name": "cell_colony", "species": ["N", "A"],
+            "labels": [{"name": "top", "wrap": False}, {"name": "cell", "wrap": True}],
+            "max_comp": max_comp, "term": term, "rules": rules}
 
 
 # ---------------------------------------------------------------------------
