@@ -55,11 +55,21 @@ LAUNCH = {
 }
 
 
+# streamed run of the sweep: sample points per window
+STREAM_WINDOW = 20
+# serving policy of the predictive replays: slices of 4 sample points
+# (constant simulation time), at most 65536 draws, predictive order
+SERVE_PREDICTED = {"slice_events": 65536, "slice_samples": 4, "predicted": True}
+# a pool small enough that admission waits for memory on the trace prefix
+SERVE_SMALL_POOL = 48 << 20
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None, e2e=False):
+def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None, e2e=False,
+              want_traj=False):
     """Warm up, then time exactly `steps` launches bracketed by device
     synchronisation; per-launch simulation time from the library's HIP events
     on the launch stream.  With e2e, also one untimed-for-`value` cycle from
@@ -67,7 +77,7 @@ def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None, e2e=Fal
     mean/variance/n copied back), wall clock."""
     import torch
     from paper_1010_2438_amd import Run
-    r = Run(ctx, model, run, mode=mode, stream=stream, tuning=tuning)
+    r = Run(ctx, model, run, mode=mode, stream=stream, tuning=tuning, want_traj=want_traj)
     r.wait()
     for _ in range(warmup):
         r.relaunch(stream)
@@ -101,6 +111,49 @@ def time_form(ctx, model, run, mode, steps, warmup, stream, tuning=None, e2e=Fal
         out["host_to_host_ms"] = 1e3 * wall
         out["host_to_host_events_per_s"] = events / wall
     return out
+
+
+def time_stream(ctx, model, run, window, stream, run_bytes):
+    """The run streamed in windows of `window` sample points (bounded device
+    memory, statistics handed out per window while the next one runs), one
+    pass after one untimed pass: wall time from opening to the last window's
+    statistics on the host, events/s, and the device memory held against
+    the whole run's."""
+    import torch
+    from paper_1010_2438_amd import Stream
+    for timed in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = Stream(ctx, model, run, window, stream=stream)
+        sim_ms = 0.0
+        rows = 0
+        for k0, mean, var, n in s:
+            rows += mean.shape[1]
+            sim_ms += s.info()["last_window_ms"]
+        wall = time.perf_counter() - t0
+        info = s.info()
+        events = int(s.counters()["events"].sum())
+        s.close()
+    assert rows == run["n_samples"]
+    return {"window": info["window"], "windows": info["n_windows"], "kernel": info["kernel"],
+            "events": events, "wall_s": wall, "events_per_s": events / wall,
+            "sum_window_kernel_ms": sim_ms, "device_bytes": info["device_bytes"],
+            "whole_run_device_bytes": run_bytes}
+
+
+def run_device_bytes(model, run, want_traj=False):
+    """Device bytes cwc_run_submit allocates for `run` (the buffers listed
+    in run.cpp: tables, per-trajectory outputs, moments, histogram, n and
+    mean/variance)."""
+    I, R, K1 = run["n_instances"], run["replicas"], run["n_samples"]
+    C, NR = model.info["n_cells"], model.info["n_rules"]
+    G, mom = I * R, I * K1 * C
+    b = (I if run.get("rate_table") is not None else 1) * NR * 8
+    b += (I if run.get("init_table") is not None else 1) * C * 4
+    b += G * (4 * C + 8 + 8 + 8 + 1 + 4)
+    b += (G * K1 * C * 4) if want_traj else 0
+    b += mom * 8 * 3 + I * (K1 + 1) * 8 + 8 + I * 4 + I * K1 * 8 + mom * 8 * 2
+    return b
 
 
 def host_cpu():
@@ -192,7 +245,8 @@ def cpu_baseline(budget_s=10.0):
     return out
 
 
-def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=64):
+def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=64,
+                slice_samples=0, predicted=False):
     """Replays the first n_jobs of the serving trace (Poisson arrivals, mixed
     configurations 0-3, 64..8192 replicas, t_end 5..100) against the
     continuous-batching server; arrival times are multiplied by time_scale.
@@ -211,6 +265,7 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
             mo[key] = Model(ctx, m)
     tab, _ = W.sweep_rate_table(models[1], 4096, 2)
     srv = Server(ctx, hbm_budget=budget, max_active=max_active, slice_events=slice_events)
+    srv.set_policy(slice_samples, predicted)
 
     def run_of(job):
         c = job["config"]
@@ -225,6 +280,7 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
 
     runs = [run_of(j) for j in trace]
     ids = [None] * len(trace)
+    config_of = {}
     t_start = time.perf_counter()
     err = []
 
@@ -236,18 +292,30 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
                 if dt > 0:
                     time.sleep(dt)
                 ids[i] = srv.submit(mo[id(models[job["config"]])], runs[i])
+                config_of[ids[i]] = job["config"]
         except Exception as e:       # surfaced below
             err.append(e)
 
     th = threading.Thread(target=submitter)
     th.start()
     infos = {}
+    # Lotka-Volterra jobs carry a count cap (prey explode once predators die
+    # out): how many of their trajectories end in OVERFLOW
+    overflow = {"lotka_volterra_jobs": 0, "trajectories": 0, "overflow_trajectories": 0,
+                "jobs_with_overflow": 0}
     last = time.perf_counter()
     while len(infos) < len(trace):
         if err:
             raise err[0]
         for jid in srv.poll():
             infos[jid] = srv.info(jid)
+            if config_of[jid] == 0:
+                st = srv.counters(jid)["status"]
+                no = int((st == 2).sum())
+                overflow["lotka_volterra_jobs"] += 1
+                overflow["trajectories"] += int(st.size)
+                overflow["overflow_trajectories"] += no
+                overflow["jobs_with_overflow"] += int(no > 0)
             srv.release(jid)
         if time.perf_counter() - last > 10.0:
             last = time.perf_counter()
@@ -269,7 +337,10 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
             "events": int(ev), "achieved_events_per_s": ev / wall,
             "offered_events_per_s": ev / max(span, 1e-9),
             "makespan_s": wall, "ticks": st["ticks"],
-            "hbm_budget_bytes": st["pool_bytes"], "pool_peak_bytes": st["pool_peak"]}
+            "policy": {"slice_events": slice_events, "slice_samples": slice_samples,
+                       "order": "predicted" if predicted else "fifo"},
+            "hbm_budget_bytes": st["pool_bytes"], "pool_peak_bytes": st["pool_peak"],
+            "lotka_volterra_count_cap": {"cap": 100000, **overflow}}
 
 
 def fnv1a64(text):
@@ -463,22 +534,48 @@ def main():
                 "events_per_step": gp["events_per_step"], "ms_per_step": gp["ms_per_step"],
                 "tuning_persistent": tp, "tuning_plain": tq, "kernel_plain": gq["kernel"],
                 "roofline": roofline_of(gp, alg, mo, W.CONFIG_NAMES[c], run)}
+            if c == 1:
+                # the same launch keeping every sampled state: [K+1][C][G]
+                # int32 written in place by the kernel
+                gt = time_form(ctx, mo, run, "persistent", steps, 1, stream, tp, want_traj=True)
+                tb = run["replicas"] * run["n_instances"] * run["n_samples"] * mo.info["n_cells"] * 4
+                extra[W.CONFIG_NAMES[c]]["with_trajectories"] = {
+                    "events_per_s": gt["events_per_s"], "kernel_ms": gt["kernel_ms"],
+                    "kernel": gt["kernel"], "trajectory_bytes": tb,
+                    "trajectory_write_GB_per_s": tb / (gt["kernel_ms"] * 1e-3) / 1e9,
+                    "over_stats_only_ms": gt["kernel_ms"] / gp["kernel_ms"]}
+                log(W.CONFIG_NAMES[c], "with trajectories", extra[W.CONFIG_NAMES[c]]["with_trajectories"])
+
+    # ---- the sweep streamed in windows (bounded device memory)
+    streamed = None
+    if not args.no_extra:
+        streamed = time_stream(ctx, model2, run2, STREAM_WINDOW, stream,
+                               run_device_bytes(model2, run2))
+        log("sweep streamed", streamed)
 
     serving = None
     if not args.no_serve:
         sat = serve_trace(ctx, args.serve_jobs, 1.0, 16 << 30)
         log("serving (trace rate)", sat)
-        # a labelled sub-saturation run: arrivals stretched so the offered
-        # load is about 70% of the achieved rate above
+        # labelled sub-saturation runs: arrivals stretched so the offered
+        # load is about 70% of the achieved rate above; draw-bounded slices
+        # in FIFO order, then slices of a few sample points (constant
+        # simulation time) with the predictive order, then the latter in a
+        # pool small enough that admission waits for memory
         scale = max(1.0, sat["offered_events_per_s"] / (0.7 * sat["achieved_events_per_s"]))
         sub = serve_trace(ctx, args.serve_jobs, scale, 16 << 30)
-        log("serving (sub-saturation)", sub)
-        small = serve_trace(ctx, args.serve_jobs, scale, 2 << 30)
-        log("serving (sub-saturation, 2 GiB budget)", small)
+        log("serving (sub-saturation, FIFO)", sub)
+        pred = serve_trace(ctx, args.serve_jobs, scale, 16 << 30, **SERVE_PREDICTED)
+        log("serving (sub-saturation, predicted)", pred)
+        small = serve_trace(ctx, args.serve_jobs, scale, SERVE_SMALL_POOL, **SERVE_PREDICTED)
+        log("serving (sub-saturation, predicted, small pool)", small)
+        best = min((sub, pred), key=lambda r: r["p99_latency_s"])
         serving = {"trace": "first %d jobs of %s" % (args.serve_jobs, W.CONFIG_NAMES[4]),
                    "at_trace_rate": sat, "sub_saturation": dict(sub, time_scale=scale),
-                   "sub_saturation_2GiB": small,
-                   "p50_latency_s": sub["p50_latency_s"], "p99_latency_s": sub["p99_latency_s"]}
+                   "sub_saturation_predicted": dict(pred, time_scale=scale),
+                   "sub_saturation_small_pool": dict(small, time_scale=scale),
+                   "p50_latency_s": best["p50_latency_s"], "p99_latency_s": best["p99_latency_s"],
+                   "p_latency_policy": best["policy"]}
 
     roofline = roofline_of(pers, alg2, model2, W.CONFIG_NAMES[2], run2)
     cpu = None
@@ -502,6 +599,7 @@ def main():
                    "host_to_host_ms": pers.get("host_to_host_ms")},
         "plain": plain,
         "other_workloads": extra,
+        "streamed": streamed,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define CWC_ABI_VERSION 1u
+#define CWC_ABI_VERSION 2u
 
 typedef int32_t cwc_status;
 #define CWC_OK             0
@@ -92,6 +92,7 @@ typedef struct cwc_ctx cwc_ctx;
 typedef struct cwc_model cwc_model;
 typedef struct cwc_run cwc_run;
 typedef struct cwc_server cwc_server;
+typedef struct cwc_stream cwc_stream;
 
 /* --------------------------------------------------------------- basics */
 
@@ -347,6 +348,63 @@ typedef struct {
 cwc_status cwc_run_into(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d,
                         const cwc_run_outputs *o, void *hip_stream);
 
+/* -------------------------------------------------------- streamed runs */
+
+/* Bounded-memory execution of a run in windows of sample points (paper
+ * Sec. 5.2: schema ii time-slices instances at constant simulation time,
+ * stopping and restarting them under a scheduler with predictive
+ * heuristics from their history; schema iii reduces a running window of
+ * all trajectories on line while later parts are produced, so the reduced
+ * part leaves memory).  The K+1 sample points are cut into windows of
+ * `window` points; each window is one time-sliced launch that advances
+ * every unfinished trajectory to just before the window's end and suspends
+ * it to a device checkpoint; the window's rows of exact moments are then
+ * finalised and handed out while the next window already runs.  Device
+ * memory is O(G C + I window C), independent of K.  Wavefronts are
+ * dispatched heaviest first: by total propensity at t = 0 for the first
+ * window, then by the events their trajectories applied in the previous
+ * window.  Every trajectory, statistic and counter equals that of
+ * cwc_run_submit on the same descriptor bit for bit. */
+
+/* d: as cwc_run_submit, except want_traj must be 0 (statistics only), mode
+ * is ignored and tuning is read only for lanes_per_replica (0 = two lanes
+ * per trajectory where the model has two leaves, else one; 1, 2, or 64 for
+ * one wavefront per trajectory).  window >= 1 sample points (clamped to
+ * K+1).  Host tables are copied.  The first window is enqueued on
+ * hip_stream before return.  Errors: as cwc_run_submit; CWC_E_UNSUPPORTED
+ * for want_traj or another lanes_per_replica. */
+cwc_status cwc_stream_open(cwc_ctx *ctx, const cwc_model *m,
+                           const cwc_run_desc *d, int32_t window,
+                           void *hip_stream, cwc_stream **out);
+/* Waits for the next window, returns its first sample index in *k0 and its
+ * number of sample points in *rows (0 once every window has been
+ * returned), and copies its statistics: mean and var [I][rows][C] f64
+ * (NaN where fewer than 1 / 2 trajectories contributed) and n [I][rows]
+ * i64 contributing trajectories.  Destinations are caller-owned host
+ * memory, or device memory with dst_is_device; any may be NULL.  Before it
+ * returns, the following window is already enqueued. */
+cwc_status cwc_stream_next(cwc_stream *s, int32_t *k0, int32_t *rows,
+                           double *mean, double *var, int64_t *n,
+                           int dst_is_device);
+typedef struct {
+    size_t device_bytes;     /* device memory the stream holds               */
+    int32_t window;          /* sample points per window                     */
+    int32_t n_windows;
+    int32_t windows_done;    /* windows returned by cwc_stream_next          */
+    float last_window_ms;    /* simulation time of the last window returned  */
+    char kernel[48];         /* the time-sliced kernel the windows launch    */
+} cwc_stream_info_t;
+cwc_status cwc_stream_info(const cwc_stream *s, cwc_stream_info_t *info);
+/* Per-trajectory results (as cwc_run_fetch_counters), once every window has
+ * been returned; CWC_E_NOTREADY before. */
+cwc_status cwc_stream_fetch_counters(cwc_stream *s, int64_t *events,
+                                     uint8_t *status, uint64_t *digest,
+                                     double *t_final, int32_t *n_recorded,
+                                     int32_t *final_counts,
+                                     int dst_is_device);
+/* Waits for enqueued work and releases the stream's device memory. */
+void cwc_stream_destroy(cwc_stream *s);
+
 /* ------------------------------------------------------------ autotuner */
 
 /* Times candidate launch shapes for this model and run -- lanes per
@@ -406,6 +464,21 @@ typedef struct {
  * trajectory per tick (>= 1).  Errors: CWC_E_INVALID, CWC_E_NOMEM. */
 cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active,
                              int64_t slice_events, cwc_server **out);
+/* Scheduling (paper Sec. 5.2 schema ii: slices at constant simulation
+ * time; dispatching guided by predictive heuristics from the instances'
+ * history).  slice_samples > 0: a slice also ends, for each trajectory,
+ * before it records its slice_samples-th sample point of the slice, so a
+ * job advances by equal spans of simulation time per slice (0: slices are
+ * bounded by slice_events draws only); it applies to jobs admitted after
+ * the call.  policy CWC_SCHED_FIFO: an idle stream takes the oldest ready
+ * job's model group; CWC_SCHED_PREDICTED: jobs that have had no slice
+ * first (in arrival order), then the job whose predicted remaining time --
+ * remaining slices (sample points left / slice_samples) times its mean
+ * slice wall time so far -- is longest (FIFO while slice_samples is 0).
+ * Results never depend on either setting.  Errors: CWC_E_INVALID. */
+#define CWC_SCHED_FIFO      0
+#define CWC_SCHED_PREDICTED 1
+cwc_status cwc_server_set_policy(cwc_server *s, int32_t slice_samples, int32_t policy);
 /* Queues a job (never blocks).  Tables are copied.  mode and tuning of `d`
  * are ignored (the server's time-sliced form is used).  CWC_E_NOMEM if the
  * job alone exceeds the pool; CWC_E_INVALID as cwc_run_submit. */
@@ -431,6 +504,21 @@ cwc_status cwc_server_get_stats(cwc_server *s, cwc_server_stats *st);
 void cwc_server_destroy(cwc_server *s);
 
 /* --------------------------------------------------------------- stats */
+
+/* Realignment onto the sample grid (paper Sec. 5.2 schema i: fixed-step
+ * sampling simplifies the on-line reduction; trajectories recorded at
+ * other times can be realigned while buffered).  Host function, no device.
+ * times[n] non-decreasing, values[n][n_cells]: a piecewise-constant,
+ * right-continuous trajectory (values[i] holds from times[i] on).  For
+ * k = 0..n_samples-1, out[k][c] = values[j][c] with j the last index whose
+ * times[j] <= k * dt (k * dt formed as the kernels form sample times), or
+ * `fill` where no record precedes k * dt.  A trajectory the library
+ * sampled on a grid of step dt / m realigned onto step dt gives the run on
+ * step dt bit for bit.  Errors: CWC_E_INVALID (sizes, NULL arrays, dt not
+ * finite and > 0, times NaN or decreasing). */
+cwc_status cwc_realign(const double *times, const int32_t *values, int64_t n,
+                       int32_t n_cells, double dt, int32_t n_samples,
+                       int32_t fill, int32_t *out);
 
 /* Confidence bands of the on-line statistics (paper Sec. 5.2 schema iii:
  * the reduction reports mean, variance and a confidence interval per

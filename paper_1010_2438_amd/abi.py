@@ -30,11 +30,14 @@ SYMBOLS = [
     "cwc_run_query", "cwc_run_wait", "cwc_run_wait_for", "cwc_run_elapsed", "cwc_run_kernel_name",
     "cwc_run_fetch_stats",
     "cwc_run_fetch_moments", "cwc_run_fetch_trajectories",
-    "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_run_into", "cwc_server_create",
+    "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_run_into",
+    "cwc_stream_open", "cwc_stream_next", "cwc_stream_info", "cwc_stream_fetch_counters",
+    "cwc_stream_destroy", "cwc_server_create", "cwc_server_set_policy",
     "cwc_server_submit", "cwc_server_poll", "cwc_server_job_info",
     "cwc_server_fetch_stats", "cwc_server_fetch_counters", "cwc_server_release",
     "cwc_server_wait_idle", "cwc_server_get_stats", "cwc_server_destroy",
     "cwc_autotune",
+    "cwc_realign",
     "cwc_stats_confidence",
     "cwc_stats_finalize",
 ]
@@ -44,6 +47,12 @@ class CwcError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s: %s" % (ERRORS.get(code, str(code)), msg))
         self.code = code
+
+
+class cwc_stream_info_t(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_size_t), ("window", ctypes.c_int32),
+                ("n_windows", ctypes.c_int32), ("windows_done", ctypes.c_int32),
+                ("last_window_ms", ctypes.c_float), ("kernel", ctypes.c_char * 48)]
 
 
 class cwc_term(ctypes.Structure):
@@ -152,11 +161,17 @@ def load(path: str = LIB_PATH):
         "cwc_run_fetch_trajectories": [P, P, ctypes.c_int],
         "cwc_run_fetch_counters": [P, P, P, P, P, P, P, ctypes.c_int],
         "cwc_run_into": [P, P, ctypes.POINTER(cwc_run_desc), ctypes.POINTER(cwc_run_outputs), P],
+        "cwc_stream_open": [P, P, ctypes.POINTER(cwc_run_desc), I32, P, ctypes.POINTER(P)],
+        "cwc_stream_next": [P, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P, ctypes.c_int],
+        "cwc_stream_info": [P, ctypes.POINTER(cwc_stream_info_t)],
+        "cwc_stream_fetch_counters": [P, P, P, P, P, P, P, ctypes.c_int],
         "cwc_stats_finalize": [P, P, P, P, P, I64, I32, P, P, P],
         "cwc_stats_confidence": [P, P, I64, I32, ctypes.c_double, P],
+        "cwc_realign": [P, P, I64, I32, ctypes.c_double, I32, I32, P],
         "cwc_server_create": [P, S, I32, I64, ctypes.POINTER(P)],
         "cwc_autotune": [P, P, ctypes.POINTER(cwc_run_desc), ctypes.c_double,
                          ctypes.POINTER(cwc_tuning)],
+        "cwc_server_set_policy": [P, I32, I32],
         "cwc_server_submit": [P, P, ctypes.POINTER(cwc_run_desc), ctypes.POINTER(ctypes.c_uint64)],
         "cwc_server_poll": [P, P, I32, ctypes.POINTER(I32)],
         "cwc_server_job_info": [P, ctypes.c_uint64, ctypes.POINTER(cwc_job_info)],
@@ -171,7 +186,7 @@ def load(path: str = LIB_PATH):
         fn.argtypes = args
         fn.restype = ctypes.c_int32
     for name in ("cwc_ctx_destroy", "cwc_model_destroy", "cwc_run_destroy",
-                 "cwc_server_destroy"):
+                 "cwc_server_destroy", "cwc_stream_destroy"):
         getattr(L, name).argtypes = [P]
         getattr(L, name).restype = None
     _lib = L
@@ -232,6 +247,21 @@ def confidence(var, n, level: float = 0.9):
     out = np.empty_like(var)
     check(load().cwc_stats_confidence(var.ctypes.data, n.ctypes.data, rows, cells,
                                       float(level), out.ctypes.data))
+    return out
+
+
+def realign(times, values, dt: float, n_samples: int, fill: int = -1):
+    """cwc_realign: a trajectory recorded at `times` (non-decreasing) with
+    states `values` [n][cells] onto the grid k*dt, k < n_samples
+    (right-continuous); rows before the first record get `fill`."""
+    times = np.ascontiguousarray(times, dtype=np.float64)
+    values = np.ascontiguousarray(values, dtype=np.int32)
+    n = times.shape[0]
+    cells = values.shape[1] if values.ndim == 2 else 1
+    assert values.size == n * cells
+    out = np.empty((n_samples, cells), np.int32)
+    check(load().cwc_realign(times.ctypes.data, values.ctypes.data, n, cells, float(dt),
+                             int(n_samples), int(fill), out.ctypes.data))
     return out
 
 
@@ -491,6 +521,85 @@ def run_into(ctx: "Context", model: "Model", run: Dict, out: Dict, mode="plain",
                          _stream_handle(stream)))
 
 
+class Stream:
+    """cwc_stream_*: a run executed in windows of ``window`` sample points
+    with bounded device memory; iterate to get each window's statistics."""
+
+    def __init__(self, ctx: Context, model: Model, run: Dict, window: int,
+                 want_digest=False, lanes_per_replica: int = 0, stream=None):
+        self.ctx, self.model = ctx, model
+        self.I, self.R = run["n_instances"], run["replicas"]
+        self.G = self.I * self.R
+        self.K1 = run["n_samples"]
+        self.C = model.info["n_cells"]
+        d, self._rate, self._init = _run_desc(run, want_digest)
+        self._tun = None
+        if lanes_per_replica:
+            self._tun = cwc_tuning(*[int(lanes_per_replica) if f == "lanes_per_replica" else 0
+                                     for f, _ in cwc_tuning._fields_])
+            d.tuning = ctypes.pointer(self._tun)
+        h = ctypes.c_void_p()
+        check(load().cwc_stream_open(ctx.h, model.h, ctypes.byref(d), int(window),
+                                     _stream_handle(stream), ctypes.byref(h)))
+        self.h = h
+        self.window = self.info()["window"]
+
+    def next(self):
+        """(k0, mean [I][rows][C], var, n [I][rows]) of the next window, or
+        None once every window has been returned."""
+        W = self.window
+        mean = np.empty((self.I, W, self.C), np.float64)
+        var = np.empty_like(mean)
+        n = np.empty((self.I, W), np.int64)
+        k0, rows = ctypes.c_int32(), ctypes.c_int32()
+        check(load().cwc_stream_next(self.h, ctypes.byref(k0), ctypes.byref(rows),
+                                     mean.ctypes.data, var.ctypes.data, n.ctypes.data, 0))
+        r = rows.value
+        if r == 0:
+            return None
+        # the library packs [I][rows][C] (and [I][rows]) contiguously
+        flat_m = mean.ravel()[: self.I * r * self.C].reshape(self.I, r, self.C)
+        flat_v = var.ravel()[: self.I * r * self.C].reshape(self.I, r, self.C)
+        flat_n = n.ravel()[: self.I * r].reshape(self.I, r)
+        return k0.value, flat_m.copy(), flat_v.copy(), flat_n.copy()
+
+    def __iter__(self):
+        while True:
+            w = self.next()
+            if w is None:
+                return
+            yield w
+
+    def info(self) -> Dict:
+        i = cwc_stream_info_t()
+        check(load().cwc_stream_info(self.h, ctypes.byref(i)))
+        return {"device_bytes": int(i.device_bytes), "window": i.window,
+                "n_windows": i.n_windows, "windows_done": i.windows_done,
+                "last_window_ms": float(i.last_window_ms), "kernel": i.kernel.decode()}
+
+    def counters(self):
+        G, C = self.G, self.C
+        out = {"events": np.empty(G, np.int64), "status": np.empty(G, np.uint8),
+               "digest": np.empty(G, np.uint64), "t_final": np.empty(G, np.float64),
+               "n_recorded": np.empty(G, np.int32),
+               "final_counts": np.empty((G, C), np.int32)}
+        check(load().cwc_stream_fetch_counters(
+            self.h, *[out[k].ctypes.data for k in ("events", "status", "digest", "t_final",
+                                                   "n_recorded", "final_counts")], 0))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().cwc_stream_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _run_desc(run: Dict, want_digest=False):
     """cwc_run_desc for a workloads.make_run dictionary (tables kept alive by
     the returned tuple)."""
@@ -519,6 +628,11 @@ class Server:
         self.h = h
         self.ctx = ctx
         self.shapes = {}
+
+    def set_policy(self, slice_samples: int = 0, predicted: bool = False):
+        """cwc_server_set_policy: slices of `slice_samples` sample points (0:
+        draw-bounded only) and the predictive dispatch order."""
+        check(load().cwc_server_set_policy(self.h, int(slice_samples), 1 if predicted else 0))
 
     def submit(self, model: Model, run: Dict, want_digest=False) -> int:
         d, _r, _i = _run_desc(run, want_digest)

@@ -21,6 +21,9 @@ typedef long long i64;
 #define CWC_ST_OVERFLOW 2
 #define CWC_ST_EVENT_CAP 3
 #define CWC_ST_RUNNING (-1)
+// suspended before recording sample k_stop (the end of a streamed run's
+// window); the trajectory resumes from its checkpoint in the next window
+#define CWC_ST_WINDOW (-2)
 
 // ------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64

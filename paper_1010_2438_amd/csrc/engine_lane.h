@@ -50,12 +50,17 @@
 // fastest: cell c of sample k of local trajectory lg sits at
 // (k * C + c) * G + lg, so the lanes of a wavefront that record the same
 // sample write neighbouring words of each cell row.  The pointer to
-// (k, cell 0, lg); cell c is c * G further on.
+// (k, cell 0, lg); cell c is c * G further on.  A streamed run keeps only
+// the rows of its current window: sample k is row k - k_base.
+// Accumulator row of sample kn of instance inst: [I][KR] rows, row 0 being
+// sample k_base (KR = K + 1 and k_base = 0 unless the run is streamed).
+#define CWC_ROW(p, inst, kn) ((i64)(inst) * (i64)(p).KR + (i64)((kn) - (p).k_base))
+
 #define CWC_TRAJ_AT(p, lg, kn)                                                \
-    ((p).traj ? (p).traj + (i64)(kn) * (i64)CWC_C * (p).G + (lg) : (i32 *)0)
+    ((p).traj ? (p).traj + (i64)((kn) - (p).k_base) * (i64)CWC_C * (p).G + (lg) : (i32 *)0)
 
 struct cwc_acc {
-    unsigned long long *tag;   // [nslot]  instance * K1 + sample, ~0 = empty
+    unsigned long long *tag;   // [nslot]  accumulator row (CWC_ROW), ~0 = empty
     unsigned long long *s1;    // [nslot][C]
     unsigned long long *s2;    // [nslot][C] low 32-bit halves of x^2
     int mask;                  // nslot - 1
@@ -122,7 +127,8 @@ __device__ __forceinline__ void cwc_acc_flush_slot(const cwc_kparams &p, const c
 __device__ __forceinline__ void cwc_emit_moments(const cwc_kparams &p, const cwc_acc &a,
                                                  const i32 *col, i64 inst, i32 kn, i32 *tr)
 {
-    const unsigned long long key = (unsigned long long)(inst * (i64)p.K1 + kn);
+    const unsigned long long key = (unsigned long long)CWC_ROW(p, inst, kn);
+    if (p.n_rows) atomicAdd(p.n_rows + key, 1ull);
     const int sl = cwc_acc_slot(a, inst, kn);
     unsigned long long *r1 = a.s1 + sl * CWC_C, *r2 = a.s2 + sl * CWC_C;
     bool pending = true;
@@ -201,9 +207,18 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
     u64 e = 0, dig = 0;             /* applied events (= next draw), digest */ \
     i64 g = 0, lg = 0, inst = 0;    /* global / local id, instance */         \
     i32 kn = 0;                     /* next sample index */                   \
+    i32 kstop = p.k_stop;           /* suspend before recording this one */   \
     double E = 0.0, U = 0.0;        /* draw e: -ln(u_tau), u_sel */           \
     CWC_DT_SETUP;                   /* per-leaf change table -> LDS */        \
     (void)INF;
+
+// time-sliced kernels: a slice of p.k_slice sample points (constant
+// simulation time) ends before the trajectory records sample kn + k_slice
+#define CWC_SLICE_STOP()                                                      \
+    do {                                                                      \
+        if (p.k_slice > 0 && (long long)kn + p.k_slice < (long long)p.k_stop) \
+            kstop = kn + p.k_slice;                                           \
+    } while (0)
 
 // draw e of trajectory g
 #define CWC_DRAW(ee, EO, UO)                                                  \
@@ -268,12 +283,14 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
         } else if (a0_ == 0.0) {                                              \
             /* absorbing state: remaining samples hold the current counts */  \
             CWC_UNDO();                                                       \
-            while (kn < p.K1) CWC_EMIT();                                     \
-            (st) = CWC_ST_ABSORBED;                                           \
+            while (kn < p.K1 && kn < kstop) CWC_EMIT();                    \
+            (st) = kn < p.K1 ? CWC_ST_WINDOW : CWC_ST_ABSORBED;               \
         } else {                                                              \
             CWC_UNDO();                                                       \
-            while (t_next < tn_) CWC_EMIT();                                  \
-            if (kn >= p.K1) {                                                 \
+            while (t_next < tn_ && kn < kstop) CWC_EMIT();                 \
+            if (t_next < tn_) {                                               \
+                (st) = CWC_ST_WINDOW;   /* the window's last sample is done */ \
+            } else if (kn >= p.K1) {                                          \
                 (st) = CWC_ST_OK;       /* this draw lies past the horizon */ \
             } else if (ovf_) {                                                \
                 (st) = CWC_ST_OVERFLOW;                                       \
@@ -295,7 +312,7 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
         p.digest[lg] = p.want_digest ? dig : 0ull;                            \
         p.status[lg] = (unsigned char)(st);                                   \
         p.n_recorded[lg] = kn;                                                \
-        atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);            \
+        if (p.rec_hist) atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull); \
     } while (0)
 
 // Queue claim of the persistent forms, called by the whole wavefront when
@@ -428,18 +445,20 @@ __device__ __forceinline__ void cwc_lane_slice(const cwc_kparams *jobs, const in
             t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
             CWC_DRAW(e, E, U);
         }
+        CWC_SLICE_STOP();
     }
     long long n = 0;
     while (__any(active)) {
         if (!active) continue;
         int st = CWC_ST_RUNNING;
         CWC_STEP(st);
-        if (st != CWC_ST_RUNNING) {
+        ++n;
+        if (st != CWC_ST_RUNNING && st != CWC_ST_WINDOW) {
             CWC_FINISH(st);
             p.ck_state[lg] = 2;
             atomicAdd(p.done_count, 1ull);
             active = false;
-        } else if (++n == budget) {
+        } else if (st == CWC_ST_WINDOW || n == budget) {
             { i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(ck_); }
             p.ck_t[lg] = t;
             p.ck_e[lg] = e;
@@ -547,12 +566,14 @@ __device__ __forceinline__ double cwc_pair_dpp(double v)
             if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
         } else if (a0_ == 0.0) {                                              \
             CWC_UNDO();                                                       \
-            while (kn < p.K1) CWC_PEMIT();                                    \
-            (st) = CWC_ST_ABSORBED;                                           \
+            while (kn < p.K1 && kn < kstop) CWC_PEMIT();                   \
+            (st) = kn < p.K1 ? CWC_ST_WINDOW : CWC_ST_ABSORBED;               \
         } else {                                                              \
             CWC_UNDO();                                                       \
-            while (t_next < tn_) CWC_PEMIT();                                 \
-            if (kn >= p.K1) {                                                 \
+            while (t_next < tn_ && kn < kstop) CWC_PEMIT();                \
+            if (t_next < tn_) {                                               \
+                (st) = CWC_ST_WINDOW;                                         \
+            } else if (kn >= p.K1) {                                          \
                 (st) = CWC_ST_OK;                                             \
             } else if (ovf_) {                                                \
                 (st) = CWC_ST_OVERFLOW;                                       \
@@ -717,6 +738,7 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
             t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
         }
         CWC_DRAW(e, E, U);
+        CWC_SLICE_STOP();
     }
     long long n = 0;
 #define CWC_PEMIT()                                                           \
@@ -732,14 +754,14 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
     // after a step: finish, or suspend once the slice's draws are used
 #define CWC_PSLICE_AFTER(st)                                                  \
     do {                                                                      \
-        if ((st) != CWC_ST_RUNNING) {                                         \
+        if ((st) != CWC_ST_RUNNING && (st) != CWC_ST_WINDOW) {                \
             if (h_ == 0) {                                                    \
                 CWC_FINISH(st);                                               \
                 p.ck_state[lg] = 2;                                           \
                 atomicAdd(p.done_count, 1ull);                                \
             }                                                                 \
             active = false;                                                   \
-        } else if (n == budget) {                                             \
+        } else if ((st) == CWC_ST_WINDOW || n == budget) {                    \
             if (h_ == 0) {                                                    \
                 { i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(ck_); } \
                 p.ck_t[lg] = t;                                               \

@@ -150,6 +150,11 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
             const i32 *ini = p.init + (i64)p.init_stride * inst;
             CWC_LOAD_COUNTS(ini, cb, wb, pbase);
         }
+        // a time slice of p.k_slice sample points ends before this sample
+        i32 kstop = p.k_stop;
+        if (FORM == CWC_FORM_SLICE && p.k_slice > 0 &&
+            (long long)kn + p.k_slice < (long long)p.k_stop)
+            kstop = kn + p.k_slice;
         bool have_batch = false;
         double Eb = 0.0, Ub = 0.0;          // this lane's draw of the batch
         int st = CWC_ST_RUNNING;
@@ -158,8 +163,10 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
 #define CWC_WEMIT()                                                           \
     do {                                                                      \
         if (kind >= 0) {                                                      \
-            const i64 row_ = (inst * (i64)p.K1 + kn) * (i64)CWC_C;            \
-            i32 *tr_ = p.traj ? p.traj + (i64)kn * (i64)CWC_C * p.G + lg : (i32 *)0; \
+            const i64 rw_ = (i64)(inst) * (i64)p.KR + (i64)(kn - p.k_base);  \
+            const i64 row_ = rw_ * (i64)CWC_C;                                \
+            i32 *tr_ = p.traj ? p.traj + (i64)(kn - p.k_base) * (i64)CWC_C * p.G + lg : (i32 *)0; \
+            if (p.n_rows && lane == 0) atomicAdd(p.n_rows + rw_, 1ull);       \
             CWC_STAGE(col, 64);                                               \
             cwc_wave_emit(p, col, row_, tr_, cb, wb);                         \
         }                                                                     \
@@ -193,13 +200,17 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
             }
             const int di = (int)(e - e0);
             if (a0 == 0.0) {
-                while (kn < p.K1) CWC_WEMIT();
-                st = CWC_ST_ABSORBED;
+                while (kn < p.K1 && kn < kstop) CWC_WEMIT();
+                st = kn < p.K1 ? CWC_ST_WINDOW : CWC_ST_ABSORBED;
                 break;
             }
             const double tau = cwc_rl(Eb, di) / a0;
             const double tn = t + tau;
-            while (t_next < tn) CWC_WEMIT();
+            while (t_next < tn && kn < kstop) CWC_WEMIT();
+            if (t_next < tn) {
+                st = CWC_ST_WINDOW;     // the window's last sample is done
+                break;
+            }
             if (kn >= p.K1) {
                 st = CWC_ST_OK;
                 break;
@@ -251,7 +262,7 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
             }
         }
 #undef CWC_WEMIT
-        if (st == CWC_ST_RUNNING) {
+        if (st == CWC_ST_RUNNING || st == CWC_ST_WINDOW) {
             // ---- suspend (time-sliced form): back to the checkpoint
             i32 *ck = p.ck_counts + lg * (i64)CWC_C;
             if (kind >= 0) { CWC_STORE_COUNTS(ck, cb, wb); }
@@ -275,7 +286,7 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
             p.digest[lg] = p.want_digest ? dig : 0ull;
             p.status[lg] = (unsigned char)st;
             p.n_recorded[lg] = kn;
-            atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);
+            if (p.rec_hist) atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);
             if (FORM == CWC_FORM_SLICE) {
                 p.ck_state[lg] = 2;
                 atomicAdd(p.done_count, 1ull);

@@ -15,6 +15,13 @@ struct cwc_kparams {
     unsigned int cap;         // count cap (<= INT32_MAX)
     int rate_stride;          // 0: one shared rate row; else n_rules
     int init_stride;          // 0: one shared init row; else n_cells
+    int KR;                   // accumulator (and trajectory) rows per instance
+    int k_base;               // sample index of row 0
+    int k_stop;               // suspend before recording this sample (streamed
+                              // runs, time-sliced kernels only); >= K1: never
+    int k_slice;              // time-sliced kernels: a slice also ends before a
+                              // trajectory records its k_slice-th sample point
+                              // of the slice (constant simulation time); 0: no
     int want_traj;
     int want_digest;
     const double *rates;      // [I or 1][n_rules]
@@ -26,12 +33,14 @@ struct cwc_kparams {
     unsigned long long *digest;  // [G]
     unsigned char *status;    // [G]
     int *n_recorded;          // [G]
-    int *traj;                // [K1][C][G] (trajectory fastest) or null
+    int *traj;                // [KR][C][G] (trajectory fastest) or null
     // on-line moments, indexed by instance ((g - g_base) / R) and sample
-    unsigned long long *s1;       // [I][K1][C]
-    unsigned long long *s2_hi32;  // [I][K1][C]
-    unsigned long long *s2_lo32;  // [I][K1][C]
-    unsigned long long *rec_hist; // [I][K1+1] trajectories by recorded count
+    unsigned long long *s1;       // [I][KR][C]
+    unsigned long long *s2_hi32;  // [I][KR][C]
+    unsigned long long *s2_lo32;  // [I][KR][C]
+    unsigned long long *rec_hist; // [I][K1+1] trajectories by recorded count, or null
+    unsigned long long *n_rows;   // [I][KR] trajectories that recorded each row, or
+                                  // null (streamed runs count here instead)
     unsigned long long *cursor;   // persistent form: next unclaimed item
     const int *order;             // persistent form (also when its grid holds
                                   // every item and runs without the queue):

@@ -116,6 +116,11 @@ extern "C" cwc_status cwc_run_into(cwc_ctx *ctx, const cwc_model *m, const cwc_r
     kp.max_events = d->max_events;
     kp.dt = d->dt;
     kp.K1 = K1;
+    kp.KR = kp.K1;          // one accumulator row per sample
+    kp.k_base = 0;
+    kp.k_stop = 0x7FFFFFFF; // no window: trajectories run to the horizon
+    kp.k_slice = 0;
+    kp.n_rows = nullptr;
     kp.cap = (unsigned)d->count_cap;
     const bool rate_rows = d->rate_table && f.n_rules > 0;
     kp.rate_stride = rate_rows ? f.n_rules : 0;

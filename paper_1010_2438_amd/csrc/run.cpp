@@ -127,32 +127,6 @@ cwc_status launch(cwc_run *r, hipStream_t s)
     return CWC_OK;
 }
 
-// Total propensity of each instance's initial state (host, for scheduling
-// only) and the instance order by decreasing value.
-std::vector<int> instance_order(const Flat &f, const std::vector<double> &rates,
-                                const std::vector<int> &init, int I, bool rate_rows,
-                                bool init_rows)
-{
-    std::vector<double> cost(I, 0.0);
-    for (int i = 0; i < I; ++i) {
-        const double *k = rates.data() + (rate_rows ? (size_t)i * f.n_rules : 0);
-        const int *n = init.data() + (init_rows ? (size_t)i * f.n_cells : 0);
-        double a0 = 0.0;
-        for (const Slot &s : f.slots) {
-            double h = 1.0;
-            for (int t = 0; t < s.n_react; ++t) {
-                const double x = n[s.react_cell[t]];
-                h *= s.react_mult[t] == 2 ? x * std::max(x - 1.0, 0.0) * 0.5 : x;
-            }
-            a0 += k[s.rule] * h;
-        }
-        cost[i] = a0;
-    }
-    std::vector<int> order(I);
-    for (int i = 0; i < I; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    return order;
-}
 
 bool valid_rate(double k) { return std::isfinite(k) && k > 0.0 && k <= 1e250; }
 
@@ -187,6 +161,34 @@ cwc_status copy_out(void *dst, const void *src, size_t bytes, int dst_is_device)
 }  // namespace
 
 namespace cwc {
+
+// Total propensity of each instance's initial state (host, for scheduling
+// only) and the instance order by decreasing value.
+std::vector<int> instance_order(const Flat &f, const std::vector<double> &rates,
+                                const std::vector<int> &init, int I, bool rate_rows,
+                                bool init_rows)
+{
+    std::vector<double> cost(I, 0.0);
+    for (int i = 0; i < I; ++i) {
+        const double *k = rates.data() + (rate_rows ? (size_t)i * f.n_rules : 0);
+        const int *n = init.data() + (init_rows ? (size_t)i * f.n_cells : 0);
+        double a0 = 0.0;
+        for (const Slot &s : f.slots) {
+            double h = 1.0;
+            for (int t = 0; t < s.n_react; ++t) {
+                const double x = n[s.react_cell[t]];
+                h *= s.react_mult[t] == 2 ? x * std::max(x - 1.0, 0.0) * 0.5 : x;
+            }
+            a0 += k[s.rule] * h;
+        }
+        cost[i] = a0;
+    }
+    std::vector<int> order(I);
+    for (int i = 0; i < I; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    return order;
+}
+
 
 // Checks a run descriptor against the model and returns host copies of the
 // rate and initial-state tables (one shared row when not given).
@@ -429,6 +431,11 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     kp.max_events = d->max_events;
     kp.dt = d->dt;
     kp.K1 = K1;
+    kp.KR = kp.K1;          // one accumulator row per sample
+    kp.k_base = 0;
+    kp.k_stop = 0x7FFFFFFF; // no window: trajectories run to the horizon
+    kp.k_slice = 0;
+    kp.n_rows = nullptr;
     kp.cap = (unsigned)d->count_cap;
     kp.rate_stride = (d->rate_table && f.n_rules > 0) ? NR : 0;
     kp.init_stride = d->init_table ? C : 0;

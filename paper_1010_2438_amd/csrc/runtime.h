@@ -82,6 +82,11 @@ cwc_status validate_run(const cwc_model *m, const cwc_run_desc *d, std::vector<d
 cwc_status validate_run_sizes(const cwc_run_desc *d);
 // Whether the model's code for `layout` is compiled and loaded.
 bool layout_loaded(const cwc_model *m, int layout);
+// Total propensity of each instance's initial state (host, for scheduling
+// only) and the instance order by decreasing value.
+std::vector<int> instance_order(const Flat &f, const std::vector<double> &rates,
+                                const std::vector<int> &init, int I, bool rate_rows,
+                                bool init_rows);
 // Launch shape of a run (see run.cpp).
 struct LaunchPlan {
     cwc_tuning tun{};                   // as launched

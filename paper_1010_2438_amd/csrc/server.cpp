@@ -117,6 +117,12 @@ struct Job {
     int state = CWC_JOB_QUEUED;
     int slot = -1;
     int n_ticks = 0;
+    // history for the predictive policy: slices taken, their wall time, and
+    // sample points done (exact with time slices: every unfinished
+    // trajectory advances by the slice's sample points)
+    int k_slice = 0;
+    int samples_done = 0;
+    double slice_wall = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     long long events = 0;
 };
@@ -148,6 +154,8 @@ struct cwc_server {
     Pool pool;
     int max_active = 0;
     long long slice = 0;
+    int slice_samples = 0;                   // guarded by mu (read at admission)
+    int policy = CWC_SCHED_FIFO;             // guarded by mu
     std::chrono::steady_clock::time_point t0;
     std::thread th;
     std::mutex mu;                       // guards everything below
@@ -172,6 +180,7 @@ struct cwc_server {
     std::vector<int> h_wave_job[kStreams];         // tables of the slice in flight
     std::vector<long long> h_wave_first[kStreams];
     hipEvent_t ev_slice[kStreams] = {};           // end of each stream's slice
+    double t_slice[kStreams] = {};                 // launch time of each stream's slice
 };
 
 namespace {
@@ -253,6 +262,11 @@ bool init_job(cwc_server *s, Job *j, int slot)
     kp.max_events = j->d.max_events;
     kp.dt = j->d.dt;
     kp.K1 = j->K1;
+    kp.KR = kp.K1;          // one accumulator row per sample
+    kp.k_base = 0;
+    kp.k_stop = 0x7FFFFFFF; // no window: trajectories run to the horizon
+    kp.k_slice = j->k_slice;            // 0: slices bounded by draws only
+    kp.n_rows = nullptr;
     kp.cap = (unsigned)j->d.count_cap;
     kp.rate_stride = j->shared_k ? 0 : j->NR;
     kp.init_stride = j->d.init_table ? j->C : 0;
@@ -408,6 +422,7 @@ void scheduler(cwc_server *s)
                     Job *j = s->jobs[s->queue.front()].get();
                     if (!reserve(s, j)) break;
                     j->slot = s->free_slots.back();
+                    j->k_slice = s->slice_samples;
                     s->free_slots.pop_back();
                     s->queue.pop_front();
                     admitted.push_back(j);
@@ -450,7 +465,10 @@ void scheduler(cwc_server *s)
                 break;
             }
             progressed = true;
+            const double dt_slice = now_s(s->t0) - s->t_slice[i];
             for (Job *j : inflight[i]) {
+                j->slice_wall += dt_slice;
+                if (j->k_slice > 0) j->samples_done = std::min(j->K1, j->samples_done + j->k_slice);
                 if ((long long)done[j->slot] == j->G) {
                     if (!finish_job(s, j)) {
                         ok = false;
@@ -475,7 +493,31 @@ void scheduler(cwc_server *s)
                 s->stats.events += j->events;
             }
         }
-        // launches: an idle stream takes the oldest ready job's group
+        // launches: an idle stream takes the group of the first ready job:
+        // the oldest (FIFO), or under the predictive policy (paper Sec. 5.2
+        // schema ii: heuristics from the instances' history) jobs without a
+        // slice yet first, in arrival order (one slice gives a short job its
+        // result, a long one its history), then the job with the longest
+        // predicted remaining time: its remaining slices times its mean slice
+        // wall time so far
+        int policy = CWC_SCHED_FIFO;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            policy = s->policy;
+        }
+        if (policy == CWC_SCHED_PREDICTED && ready.size() > 1) {
+            auto predicted = [](const Job *j) {
+                if (j->n_ticks == 0 || j->k_slice <= 0) return -1.0;
+                const double left = (double)(j->K1 - j->samples_done) / (double)j->k_slice;
+                return std::max(0.0, left) * j->slice_wall / (double)j->n_ticks;
+            };
+            std::stable_sort(ready.begin(), ready.end(), [&](const Job *a, const Job *b) {
+                const bool na = a->n_ticks == 0, nb = b->n_ticks == 0;
+                if (na != nb) return na;
+                if (na) return a->id < b->id;
+                return predicted(a) > predicted(b);
+            });
+        }
         for (int i = 0; ok && !stopping && i < kStreams && !ready.empty(); ++i) {
             if (!inflight[i].empty()) continue;
             const Job *lead = ready.front();
@@ -493,6 +535,7 @@ void scheduler(cwc_server *s)
                 }
             }
             ready.swap(rest);
+            s->t_slice[i] = now_s(s->t0);
             if (!launch_slice(s, i, take_jobs)) {
                 ok = false;
                 break;
@@ -587,6 +630,18 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
     cwc_server *raw = s.release();
     raw->th = std::thread(scheduler, raw);
     *out = raw;
+    return CWC_OK;
+}
+
+cwc_status cwc_server_set_policy(cwc_server *s, int32_t slice_samples, int32_t policy)
+{
+    if (!s) return set_err(CWC_E_INVALID, "null server");
+    if (slice_samples < 0) return set_err(CWC_E_INVALID, "slice_samples must be >= 0");
+    if (policy != CWC_SCHED_FIFO && policy != CWC_SCHED_PREDICTED)
+        return set_err(CWC_E_INVALID, "unknown scheduling policy %d", policy);
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->slice_samples = slice_samples;
+    s->policy = policy;
     return CWC_OK;
 }
 

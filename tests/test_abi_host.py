@@ -41,7 +41,7 @@ def test_exports_every_declared_symbol(P):
                          text=True).stdout
     for n in names:
         assert re.search(r"\sT\s%s$" % n, out, re.M), n
-    assert L.cwc_abi_version() == 1
+    assert L.cwc_abi_version() == 2
 
 
 def test_context_without_device_fails_cleanly(P):

@@ -47,8 +47,13 @@ def same_stats(a, b):
             assert np.array_equal(x, y)
 
 
-def test_alone_vs_mix(ctx):
+@pytest.mark.parametrize("slice_samples,predicted", [(0, False), (3, True), (5, False)])
+def test_alone_vs_mix(ctx, slice_samples, predicted):
+    """Every job of the mix equals the job run alone, with slices bounded by
+    draws only, and with slices of a few sample points (constant simulation
+    time) under the predictive and the FIFO dispatch order."""
     from paper_1010_2438_amd import Model, Server
+    print("case serving mix slice_samples", slice_samples, "predicted", predicted, flush=True)
     specs = job_specs()
     models = {}
     for m, _ in specs:
@@ -63,6 +68,7 @@ def test_alone_vs_mix(ctx):
     compare_trajectories(alone[0], orc)
     # the mix: every job admitted at once, sliced every 997 draws
     srv = Server(ctx, hbm_budget=256 << 20, max_active=16, slice_events=997)
+    srv.set_policy(slice_samples, predicted)
     ids = [srv.submit(models[repr(m)], run, want_digest=True) for m, run in specs]
     srv.wait_idle(300)
     done = set(srv.poll())
@@ -77,6 +83,11 @@ def test_alone_vs_mix(ctx):
         same_stats(srv.stats(jid), (g["mean"], g["var"], g["n"]))
         assert info["events"] == int(g["events"].sum())
     assert max(srv.info(j)["n_ticks"] for j in ids) > 3     # really sliced
+    if slice_samples:
+        # a job of K+1 sample points needs at least ceil((K+1) / slice) slices
+        for jid, (m, run) in zip(ids, specs):
+            if srv.info(jid)["events"] and run["max_events"] == 0:
+                assert srv.info(jid)["n_ticks"] >= -(-run["n_samples"] // slice_samples)
     st = srv.server_stats()
     assert st["jobs_done"] == len(ids) and st["pool_peak"] <= st["pool_bytes"]
     for j in ids:
@@ -117,6 +128,14 @@ def test_admission_within_budget(ctx):
     solo = gpu_run(ctx, mo, runs[4], mode="plain", want_traj=False)
     assert np.array_equal(kept["final_counts"], solo["final_counts"])
     assert np.array_equal(kept["events"], solo["events"])
+    srv.close()
+
+
+def test_policy_validation(ctx):
+    from paper_1010_2438_amd import CwcError, Server
+    srv = Server(ctx, hbm_budget=2 << 20, max_active=4, slice_events=1024)
+    with pytest.raises(CwcError):
+        srv.set_policy(-1, False)
     srv.close()
 
 
