@@ -52,6 +52,8 @@ LAUNCH = {
     1: {"block_size": 256, "waves_per_simd": 1, "lanes_per_replica": 4},
     # the 32-cell model: one wavefront per trajectory
     3: {"block_size": 256, "waves_per_simd": 8, "lanes_per_replica": 64},
+    # the general-term cell colony: one wavefront per trajectory
+    5: {"block_size": 256, "waves_per_simd": 8},
 }
 
 
@@ -62,6 +64,20 @@ STREAM_WINDOW = 20
 SERVE_PREDICTED = {"slice_events": 65536, "slice_samples": 4, "predicted": True}
 # a pool small enough that admission waits for memory on the trace prefix
 SERVE_SMALL_POOL = 48 << 20
+
+
+# the general-term workload: the cell colony (compartments created and
+# deleted at run time), 2048 trajectories
+GENERAL_NAME = "cell_colony_general_r2048"
+
+
+def general_workload():
+    """The cell colony in a fed nutrient bath at a settled size (about 28 of
+    its 64 slots live; biomass spent, cells dying), 2048 trajectories to
+    t = 100, 201 sample points."""
+    import workloads as W
+    m = W.cell_colony(nutrient=0, k_feed=100.0, k_up=0.05, k_div=0.05, k_die=0.3, k_decay=0.5)
+    return m, W.make_run(seed=0, replicas=2048, dt=0.5, n_samples=201)
 
 
 def log(*a):
@@ -234,6 +250,16 @@ def cpu_baseline(budget_s=10.0):
                              "sample": "%d of those trajectories (%d events, %.1f s)"
                                        % (len(ids1), ev1, dt1)},
            "other_workloads": {}}
+    gm_dict, grun = general_workload()
+    gids = list(range(4 * threads))
+    t0 = time.perf_counter()
+    import oracle as _oracle
+    gres = _oracle.gsimulate(gm_dict, grun, g0=0, g1=len(gids), want_stats=False, threads=threads)
+    gdt = time.perf_counter() - t0
+    out["other_workloads"][GENERAL_NAME] = {
+        "value": float(gres["events"].sum()) / gdt, "unit": "events/s", "cores": threads,
+        "sample": "trajectories 0..%d of 2048 (%d events, %.2f s)"
+                  % (len(gids) - 1, int(gres["events"].sum()), gdt)}
     for c, n in ((0, 64), (1, 8 * threads), (3, 4 * threads)):
         m, run = W.config(c)
         G = run["n_instances"] * run["replicas"]
@@ -404,9 +430,15 @@ def single_workload(ctx, stream, args):
     --tuning or --autotune is given), with the roofline of its kernel, as
     one JSON line."""
     import workloads as W
-    from paper_1010_2438_amd import Model
-    m, run = W.config(args.workload)
-    model = Model(ctx, m)
+    from paper_1010_2438_amd import GModel, Model
+    if args.workload == 5:
+        m, run = general_workload()
+        model = GModel(ctx, m)
+        name = GENERAL_NAME
+    else:
+        m, run = W.config(args.workload)
+        model = Model(ctx, m)
+        name = W.CONFIG_NAMES[args.workload]
     alg = model.info["alg_slots_per_event"]
     if args.tuning:
         tun = parse_tuning(args.tuning)
@@ -416,11 +448,11 @@ def single_workload(ctx, stream, args):
         tun = dict(LAUNCH[args.workload])
     res = time_form(ctx, model, run, "persistent", args.steps, args.warmup, stream, tun)
     print(json.dumps({
-        "workload": W.CONFIG_NAMES[args.workload], "form": "persistent",
+        "workload": name, "form": "persistent",
         "events_per_s": res["events_per_s"], "ms_per_step": res["ms_per_step"],
         "kernel_ms": res["kernel_ms"], "events_per_step": res["events_per_step"],
         "steps": args.steps, "warmup": args.warmup, "tuning": tun,
-        "roofline": roofline_of(res, alg, model, W.CONFIG_NAMES[args.workload], run)}),
+        "roofline": roofline_of(res, alg, model, name, run)}),
           flush=True)
 
 
@@ -441,10 +473,11 @@ def main():
                          "of the one in LAUNCH")
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner for each persistent form instead of using LAUNCH")
-    ap.add_argument("--workload", type=int, default=0, choices=(0, 1, 3),
+    ap.add_argument("--workload", type=int, default=0, choices=(0, 1, 3, 5),
                     help="time only the persistent form of workload 1 (gene regulation, "
-                         "16384 replicas) or 3 (multi-compartment, 2048 replicas) and print "
-                         "its own line (for profiler runs); 0 = the full benchmark")
+                         "16384 replicas), 3 (multi-compartment, 2048 replicas) or 5 (the "
+                         "general-term cell colony, 2048 replicas) and print its own line "
+                         "(for profiler runs); 0 = the full benchmark")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="copy BYTES device-to-device 5 times and exit (counter calibration)")
     args = ap.parse_args()
@@ -545,6 +578,21 @@ def main():
                     "trajectory_write_GB_per_s": tb / (gt["kernel_ms"] * 1e-3) / 1e9,
                     "over_stats_only_ms": gt["kernel_ms"] / gp["kernel_ms"]}
                 log(W.CONFIG_NAMES[c], "with trajectories", extra[W.CONFIG_NAMES[c]]["with_trajectories"])
+
+    # ---- a general CWC model: the cell colony (cells divide, die, take up
+    # nutrients; up to 64 compartments per term), 2048 trajectories
+    if not args.no_extra:
+        from paper_1010_2438_amd import GModel
+        gm_dict, grun = general_workload()
+        gmo = GModel(ctx, gm_dict)
+        gr = time_form(ctx, gmo, grun, "persistent", args.steps, 1, stream,
+                       {"block_size": 256, "waves_per_simd": 8})
+        log(GENERAL_NAME, gr)
+        extra[GENERAL_NAME] = {
+            "persistent_events_per_s": gr["events_per_s"], "events_per_step": gr["events_per_step"],
+            "ms_per_step": gr["ms_per_step"], "kernel": gr["kernel"],
+            "roofline": roofline_of(gr, gmo.info["alg_slots_per_event"], gmo, GENERAL_NAME, grun)}
+        gmo.close()
 
     # ---- the sweep streamed in windows (bounded device memory)
     streamed = None

@@ -192,6 +192,89 @@ cwc_status cwc_model_describe(const cwc_model_desc *d, cwc_model_info *info);
 cwc_status cwc_codegen(const cwc_model_desc *d, char *buf, size_t cap,
                        size_t *len);
 
+/* ------------------------------------------------------- general models */
+
+/* General CWC terms (paper Sec. 2.1): compartments are created, dissolved
+ * and deleted while a trajectory runs, and a rule's pattern may name a
+ * child compartment of its context and a grandchild inside that child.
+ * The term is held as a pool of max_comp compartment slots (one wavefront
+ * lane each, so max_comp <= 64): the initial compartments take slots 0..n-1
+ * in preorder (slot 0 the top level, which never goes away), a new
+ * compartment the lowest free slot.  Each live slot anchors one match per
+ * rule whose deepest named label is its label; the match's rate is k times
+ * the product of binomial(n, m) over the pattern's atoms (total order <=
+ * 2), and summing a rule over its matching compartments is the paper's
+ * count_compartments (Fig. "simd", Match).  Leaves are slot-major, the
+ * rules anchored at a label in ascending index, padded to a power of two;
+ * slots padded to a power of two.  The outputs ("cells") are observables:
+ * per label in label order, the content atom totals over its live
+ * compartments, the wrap atom totals (labels with a wrap), the number of
+ * live compartments.  An event that would exceed count_cap or needs a slot
+ * the pool does not have is not applied: status OVERFLOW. */
+
+#define CWC_ACT_NONE     0
+#define CWC_ACT_CREATE   1   /* a compartment in the context (level 0), the
+                                child (1) or the grandchild (2)           */
+#define CWC_ACT_DISSOLVE 2   /* the child (1) or grandchild (2): its content
+                                atoms and compartments (and its wrap atoms
+                                with release_wrap) pass to its parent    */
+#define CWC_ACT_DELETE   3   /* the child or grandchild with its content  */
+
+typedef struct {
+    int32_t label;
+    int32_t parent;            /* index in the list (preorder); -1 for [0]  */
+    const int32_t *wrap;       /* [n_species] or NULL (none)                */
+    const int32_t *content;    /* [n_species] or NULL (none)                */
+} cwc_gcomp;
+
+typedef struct {
+    int32_t context;           /* label of the compartment whose content the
+                                  rule rewrites                              */
+    int32_t child;             /* label of a child it names, or -1          */
+    int32_t grandchild;        /* label of a compartment inside that child,
+                                  or -1 (needs child)                        */
+    int32_t n_lhs;
+    const cwc_term *lhs;       /* region 0 context content, 1 child wrap,
+                                  2 child content, 3 grandchild wrap,
+                                  4 grandchild content                       */
+    int32_t n_rhs;
+    const cwc_term *rhs;       /* atoms the rule puts back (same regions)   */
+    int32_t action;            /* CWC_ACT_*                                 */
+    int32_t level;             /* see CWC_ACT_*                             */
+    int32_t new_label;         /* create: the new compartment's label ...   */
+    const int32_t *new_wrap;   /* ... its wrap [n_species] or NULL ...      */
+    const int32_t *new_content;/* ... and content [n_species] or NULL       */
+    int32_t release_wrap;      /* dissolve: wrap atoms join the parent      */
+    double k;                  /* kinetic constant > 0                      */
+} cwc_grule;
+
+typedef struct {
+    int32_t n_species;         /* 1..32                                     */
+    int32_t n_labels;          /* 1..16                                     */
+    const int32_t *has_wrap;   /* [n_labels]                                */
+    int32_t max_comp;          /* 1..64 compartment slots                   */
+    int32_t n_comp;            /* initial compartments, 1..max_comp         */
+    const cwc_gcomp *comps;    /* [n_comp], preorder                        */
+    int32_t n_rules;           /* 0..64                                     */
+    const cwc_grule *rules;    /* [n_rules]                                 */
+} cwc_gmodel_desc;
+
+/* Validates `d` (copied), generates the general engine's model header and
+ * compiles it for the context's device.  The model is used like any other
+ * with cwc_run_submit (plain or persistent form, one wavefront per
+ * trajectory; lanes_per_replica 0 or 64; rate tables allowed, init_table
+ * must be NULL, the initial term is the model's; want_traj keeps the
+ * observables [K+1][C][G]) and cwc_run_fetch_term.  Streamed runs and the
+ * server take fixed-tree models only.  Errors: CWC_E_INVALID (indices,
+ * rates, counts, regions beyond the pattern, non-preorder term),
+ * CWC_E_UNSUPPORTED (max_comp > 64, order > 2), CWC_E_COMPILE. */
+cwc_status cwc_gmodel_create(cwc_ctx *ctx, const cwc_gmodel_desc *d,
+                             cwc_model **out);
+/* Host-only: validates `d` and returns the generated model header plus the
+ * engine source (as cwc_model_source), no device. */
+cwc_status cwc_gcodegen(const cwc_gmodel_desc *d, char *buf, size_t cap,
+                        size_t *len);
+
 /* ----------------------------------------------------------------- run */
 
 typedef struct {
@@ -291,6 +374,11 @@ cwc_status cwc_run_fetch_moments(cwc_run *r, uint64_t *s1, uint64_t *s2_hi32,
  * for a run submitted without want_traj. */
 cwc_status cwc_run_fetch_trajectories(cwc_run *r, int32_t *dst,
                                       int dst_is_device);
+/* General models: each trajectory's final term, [G][max_comp][3 + 2 NS]
+ * int32 rows (alive 0/1, label or -1, parent slot or -1, wrap atoms [NS],
+ * content atoms [NS]); free slots hold 0, -1, -1 and zeros.  CWC_E_INVALID
+ * for a fixed-tree model. */
+cwc_status cwc_run_fetch_term(cwc_run *r, int32_t *dst, int dst_is_device);
 /* Per trajectory [G]: applied events, terminal status, digest (0 unless
  * want_digest), final simulation time, number of recorded samples, final
  * counts [G][C].  Any pointer may be NULL. */

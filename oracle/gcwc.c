@@ -233,10 +233,13 @@ static int apply(const goracle_model *M, pool_t *T, int r, const int m[3], int64
         for (int s = 0; s < M->max_comp; ++s)
             if (gone[s]) free_slot(&U, s);
     }
+    /* counts compared as unsigned 32-bit values: a sum that wrapped past
+     * 2^31 - 1 is above any cap as well */
     for (int s = 0; s < M->max_comp; ++s) {
         if (!U.alive[s]) continue;
         for (int a = 0; a < NS; ++a)
-            if ((int64_t)U.wrap[s][a] > cap || (int64_t)U.content[s][a] > cap) return 1;
+            if ((uint32_t)U.wrap[s][a] > (uint32_t)cap || (uint32_t)U.content[s][a] > (uint32_t)cap)
+                return 1;
     }
     *T = U;
     return 0;

@@ -26,10 +26,11 @@ REGION = {"p": 0, "w": 1, "c": 2}
 SYMBOLS = [
     "cwc_abi_version", "cwc_last_error", "cwc_ctx_create", "cwc_ctx_destroy",
     "cwc_model_create", "cwc_model_get_info", "cwc_model_source",
-    "cwc_model_destroy", "cwc_model_describe", "cwc_codegen", "cwc_run_submit", "cwc_run_relaunch",
+    "cwc_model_destroy", "cwc_model_describe", "cwc_codegen", "cwc_gmodel_create",
+    "cwc_gcodegen", "cwc_run_submit", "cwc_run_relaunch",
     "cwc_run_query", "cwc_run_wait", "cwc_run_wait_for", "cwc_run_elapsed", "cwc_run_kernel_name",
     "cwc_run_fetch_stats",
-    "cwc_run_fetch_moments", "cwc_run_fetch_trajectories",
+    "cwc_run_fetch_moments", "cwc_run_fetch_trajectories", "cwc_run_fetch_term",
     "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_run_into",
     "cwc_stream_open", "cwc_stream_next", "cwc_stream_info", "cwc_stream_fetch_counters",
     "cwc_stream_destroy", "cwc_server_create", "cwc_server_set_policy",
@@ -65,6 +66,28 @@ class cwc_rule(ctypes.Structure):
                 ("n_lhs", ctypes.c_int32), ("lhs", ctypes.POINTER(cwc_term)),
                 ("n_rhs", ctypes.c_int32), ("rhs", ctypes.POINTER(cwc_term)),
                 ("k", ctypes.c_double)]
+
+
+class cwc_gcomp(ctypes.Structure):
+    _fields_ = [("label", ctypes.c_int32), ("parent", ctypes.c_int32),
+                ("wrap", ctypes.c_void_p), ("content", ctypes.c_void_p)]
+
+
+class cwc_grule(ctypes.Structure):
+    _fields_ = [("context", ctypes.c_int32), ("child", ctypes.c_int32),
+                ("grandchild", ctypes.c_int32), ("n_lhs", ctypes.c_int32),
+                ("lhs", ctypes.c_void_p), ("n_rhs", ctypes.c_int32), ("rhs", ctypes.c_void_p),
+                ("action", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("new_label", ctypes.c_int32), ("new_wrap", ctypes.c_void_p),
+                ("new_content", ctypes.c_void_p), ("release_wrap", ctypes.c_int32),
+                ("k", ctypes.c_double)]
+
+
+class cwc_gmodel_desc(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_labels", ctypes.c_int32),
+                ("has_wrap", ctypes.c_void_p), ("max_comp", ctypes.c_int32),
+                ("n_comp", ctypes.c_int32), ("comps", ctypes.c_void_p),
+                ("n_rules", ctypes.c_int32), ("rules", ctypes.c_void_p)]
 
 
 class cwc_model_desc(ctypes.Structure):
@@ -159,6 +182,9 @@ def load(path: str = LIB_PATH):
         "cwc_run_fetch_stats": [P, P, P, P, ctypes.c_int],
         "cwc_run_fetch_moments": [P, P, P, P, P, ctypes.c_int],
         "cwc_run_fetch_trajectories": [P, P, ctypes.c_int],
+        "cwc_run_fetch_term": [P, P, ctypes.c_int],
+        "cwc_gmodel_create": [P, ctypes.POINTER(cwc_gmodel_desc), ctypes.POINTER(P)],
+        "cwc_gcodegen": [ctypes.POINTER(cwc_gmodel_desc), ctypes.c_char_p, S, ctypes.POINTER(S)],
         "cwc_run_fetch_counters": [P, P, P, P, P, P, P, ctypes.c_int],
         "cwc_run_into": [P, P, ctypes.POINTER(cwc_run_desc), ctypes.POINTER(cwc_run_outputs), P],
         "cwc_stream_open": [P, P, ctypes.POINTER(cwc_run_desc), I32, P, ctypes.POINTER(P)],
@@ -233,6 +259,70 @@ class _ModelDesc:
         self.desc = cwc_model_desc(ns, len(types), len(comps), self.has_wrap,
                                    self.comp_type, self.comp_parent, self.init,
                                    len(rules), self.rules)
+
+
+GREGION = {"c": 0, "w1": 1, "c1": 2, "w2": 3, "c2": 4}
+GACTION = {"none": 0, "create": 1, "dissolve": 2, "delete": 3}
+
+
+class _GModelDesc:
+    """Keeps the ctypes arrays of a cwc_gmodel_desc alive (general models
+    of the ``workloads`` module)."""
+
+    def __init__(self, model: Dict):
+        ns = len(model["species"])
+        labels = model["labels"]
+        keep = self.keep = []
+
+        def ivec(v):
+            if v is None:
+                return None
+            if isinstance(v, dict):
+                x = [0] * ns
+                for a, m in v.items():
+                    x[int(a)] += int(m)
+                v = x
+            arr = (ctypes.c_int32 * ns)(*[int(t) for t in v])
+            keep.append(arr)
+            return ctypes.addressof(arr)
+
+        self.has_wrap = (ctypes.c_int32 * len(labels))(*[int(bool(l["wrap"])) for l in labels])
+        comps = [cwc_gcomp(c["label"], c["parent"], ivec(c.get("wrap")), ivec(c.get("content")))
+                 for c in model["term"]]
+        self.comps = (cwc_gcomp * len(comps))(*comps)
+        rules = []
+        for r in model["rules"]:
+            sides = []
+            for side in ("lhs", "rhs"):
+                ts = [cwc_term(GREGION[reg], int(sp), int(m))
+                      for reg, atoms in r.get(side, {}).items() for sp, m in atoms.items()
+                      if int(m) > 0]
+                arr = (cwc_term * max(1, len(ts)))(*ts)
+                keep.append(arr)
+                sides.append((len(ts), ctypes.addressof(arr)))
+            nw = r.get("new") or {}
+            rules.append(cwc_grule(r["context"], r.get("child", -1), r.get("grandchild", -1),
+                                   sides[0][0], sides[0][1], sides[1][0], sides[1][1],
+                                   GACTION[r.get("action", "none")], int(r.get("level", 0)),
+                                   int(nw.get("label", -1)), ivec(nw.get("wrap")),
+                                   ivec(nw.get("content")), int(bool(r.get("release_wrap"))),
+                                   float(r["k"])))
+        self.rules = (cwc_grule * max(1, len(rules)))(*rules)
+        self.desc = cwc_gmodel_desc(ns, len(labels), ctypes.addressof(self.has_wrap),
+                                    int(model["max_comp"]), len(comps),
+                                    ctypes.addressof(self.comps), len(rules),
+                                    ctypes.addressof(self.rules))
+
+
+def gcodegen(model: Dict) -> str:
+    """cwc_gcodegen: the generated device source of a general model (host only)."""
+    L = load()
+    md = _GModelDesc(model)
+    n = ctypes.c_size_t()
+    check(L.cwc_gcodegen(ctypes.byref(md.desc), None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    check(L.cwc_gcodegen(ctypes.byref(md.desc), buf, n.value, ctypes.byref(n)))
+    return buf.value.decode()
 
 
 def confidence(var, n, level: float = 0.9):
@@ -368,6 +458,25 @@ class Model:
             pass
 
 
+class GModel(Model):
+    """cwc_gmodel_create from a general model dictionary (compartments
+    created, dissolved and deleted at run time); runs like any Model."""
+
+    def __init__(self, ctx: Context, model: Dict):
+        L = load()
+        self.ctx = ctx
+        self.dict = model
+        md = _GModelDesc(model)
+        h = ctypes.c_void_p()
+        check(L.cwc_gmodel_create(ctx.h, ctypes.byref(md.desc), ctypes.byref(h)))
+        self.h = h
+        info = cwc_model_info()
+        check(L.cwc_model_get_info(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in cwc_model_info._fields_}
+        self.max_comp = int(model["max_comp"])
+        self.n_species = len(model["species"])
+
+
 class Run:
     """cwc_run_submit and the fetches.  ``run`` is a workloads.make_run
     dictionary; ``mode`` 'plain' or 'persistent'."""
@@ -478,6 +587,14 @@ class Run:
             return out
         t = np.empty((self.K1, self.C, self.G), np.int32)
         check(load().cwc_run_fetch_trajectories(self.h, t.ctypes.data, 0))
+        return t
+
+    def term(self):
+        """General models: the final term [G][max_comp][alive, label, parent,
+        wrap NS, content NS]."""
+        m = self.model
+        t = np.empty((self.G, m.max_comp, 3 + 2 * m.n_species), np.int32)
+        check(load().cwc_run_fetch_term(self.h, t.ctypes.data, 0))
         return t
 
     def close(self):

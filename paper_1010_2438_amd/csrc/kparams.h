@@ -34,6 +34,7 @@ struct cwc_kparams {
     unsigned char *status;    // [G]
     int *n_recorded;          // [G]
     int *traj;                // [KR][C][G] (trajectory fastest) or null
+    int *final_term;          // general models: [G][max_comp][3 + 2 NS] or null
     // on-line moments, indexed by instance ((g - g_base) / R) and sample
     unsigned long long *s1;       // [I][KR][C]
     unsigned long long *s2_hi32;  // [I][KR][C]

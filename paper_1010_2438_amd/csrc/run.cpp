@@ -135,7 +135,7 @@ std::string kernel_name(int layout, int group, int k)
 {
     static const char *forms[4] = {"plain_shared", "plain_table", "persistent_shared",
                                    "persistent_table"};
-    const char *fam = layout == 1 ? "cwc_wave"
+    const char *fam = layout == 2 ? "cwc_gen" : layout == 1 ? "cwc_wave"
                                   : (group == 4 ? "cwc_quad" : (group == 2 ? "cwc_pair" : "cwc_lane"));
     return std::string(fam) + "_" + forms[k];
 }
@@ -213,6 +213,9 @@ cwc_status validate_run(const cwc_model *m, const cwc_run_desc *d, std::vector<d
         rates = f.k;
         if (rates.empty()) rates.assign(1, 1.0);
     }
+    if (d->init_table && m->gen)
+        return set_err(CWC_E_UNSUPPORTED,
+                       "a general model starts from its own term: init_table must be NULL");
     if (d->init_table) {
         init.assign(d->init_table, d->init_table + I * C);
     } else {
@@ -269,7 +272,13 @@ cwc_status plan_launch(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d, 
     int layout = f.layout;
     const bool pair = tun.lanes_per_replica == 2;
     const bool quad = tun.lanes_per_replica == 4;
-    if (tun.lanes_per_replica == 1 || pair || quad) layout = 0;
+    if (layout == 2) {
+        // general terms: one wavefront per trajectory, lane = compartment slot
+        if (tun.lanes_per_replica != 0 && tun.lanes_per_replica != 64)
+            return set_err(CWC_E_UNSUPPORTED,
+                           "a general model runs one wavefront per trajectory "
+                           "(lanes_per_replica 0 or 64)");
+    } else if (tun.lanes_per_replica == 1 || pair || quad) layout = 0;
     else if (tun.lanes_per_replica == 64) layout = 1;
     else if (tun.lanes_per_replica != 0)
         return set_err(CWC_E_UNSUPPORTED, "lanes_per_replica must be 0 (auto), 1, 2, 4 or 64");
@@ -280,17 +289,18 @@ cwc_status plan_launch(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *d, 
         return set_err(CWC_E_INVALID,
                        "the model's code for the %s layout is not loaded (submit one run in "
                        "that layout with cwc_run_submit first)",
-                       layout == 1 ? "wavefront-per-replica" : "lane-per-replica");
+                       layout == 2 ? "general-term"
+                                   : (layout == 1 ? "wavefront-per-replica" : "lane-per-replica"));
     }
     if (pair && !m->pair_fn[0])
         return set_err(CWC_E_UNSUPPORTED, "two lanes per trajectory need at least two leaves");
     if (quad && !m->quad_fn[0])
         return set_err(CWC_E_UNSUPPORTED, "four lanes per trajectory need at least four leaves");
     const int group = quad ? 4 : (pair ? 2 : 1);   // lanes per trajectory (lane module)
-    tun.lanes_per_replica = layout == 1 ? 64 : group;   // as launched
+    tun.lanes_per_replica = layout >= 1 ? 64 : group;   // as launched
 
     const bool shared = !(d->rate_table && f.n_rules > 0);
-    const bool wave = layout == 1;
+    const bool wave = layout >= 1;
     if (wave && !tuned && (!d->tuning || d->tuning->block_size <= 0)) tun.block_size = 256;
     unsigned block = (unsigned)tun.block_size;
     // the lane layout's per-wavefront LDS (staging + accumulator cache)
@@ -406,6 +416,7 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m, const cwc_run_desc *
     ALLOC(kp.status, G);
     ALLOC(kp.n_recorded, G);
     if (d->want_traj) ALLOC(kp.traj, G * (long long)K1 * C);
+    if (m->gen) ALLOC(kp.final_term, G * (long long)m->gen->max_comp * (3 + 2 * m->gen->n_species));
     ALLOC(kp.s1, mom);
     ALLOC(kp.s2_hi32, mom);
     ALLOC(kp.s2_lo32, mom);
@@ -580,6 +591,17 @@ cwc_status cwc_run_fetch_trajectories(cwc_run *r, int32_t *dst, int dst_is_devic
     if (st != CWC_OK) return st;
     if (!r->kp.traj) return set_err(CWC_E_INVALID, "run was submitted without want_traj");
     return copy_out(dst, r->kp.traj, (size_t)r->G * r->K1 * r->C * sizeof(int32_t), dst_is_device);
+}
+
+cwc_status cwc_run_fetch_term(cwc_run *r, int32_t *dst, int dst_is_device)
+{
+    cwc_status st = ready(r);
+    if (st != CWC_OK) return st;
+    if (!r->m->gen) return set_err(CWC_E_INVALID, "not a general model: its term is fixed");
+    const GFlat &g = *r->m->gen;
+    return copy_out(dst, r->kp.final_term,
+                    (size_t)r->G * g.max_comp * (3 + 2 * g.n_species) * sizeof(int32_t),
+                    dst_is_device);
 }
 
 cwc_status cwc_run_fetch_counters(cwc_run *r, int64_t *events, uint8_t *status, uint64_t *digest,

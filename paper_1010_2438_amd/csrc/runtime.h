@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <memory>
 #include <map>
 #include <mutex>
 #include <string>
@@ -11,6 +12,7 @@
 
 #include "../../include/cwcssa.h"
 #include "kparams.h"
+#include "gmodel.h"
 #include "model.h"
 
 struct cwc_ctx {
@@ -43,10 +45,12 @@ void ctx_drop_final(cwc_ctx *ctx);
 struct cwc_model {
     cwc_ctx *ctx = nullptr;
     cwc::Flat flat;                     // flat.layout = the default layout
-    int fits[2] = {0, 0};               // layouts the model fits (lane, wave)
-    std::string source[2];              // per layout, generated on demand
-    hipModule_t module[2] = {nullptr, nullptr};
-    hipFunction_t fn[2][6] = {};        // [layout][plain/persistent/slice x shared/table]
+    int fits[3] = {0, 0, 0};            // layouts the model fits (lane, wave, general)
+    std::string source[3];              // per layout, generated on demand
+    hipModule_t module[3] = {nullptr, nullptr, nullptr};
+    hipFunction_t fn[3][6] = {};        // [layout][plain/persistent/slice x shared/table]
+                                        // (the general engine has no slice form)
+    std::shared_ptr<cwc::GFlat> gen;    // general models (layout 2): the term and rules
     hipFunction_t quad_fn[4] = {};      // lane module's quad kernels (plain/persistent x
                                         // shared/table); null with fewer than four leaves
     hipFunction_t pair_fn[6] = {};      // lane module's pair kernels (plain/persistent/
@@ -131,5 +135,6 @@ cwc_status set_err(cwc_status code, const char *fmt, ...);
 cwc_status compile_source(const std::string &src, const std::string &arch,
                           std::vector<char> *code);
 std::string model_source(const Flat &f, int layout);
+std::string gmodel_source(const GFlat &g);
 }  // namespace cwc
 #endif

@@ -650,6 +650,9 @@ cwc_status cwc_server_submit(cwc_server *s, const cwc_model *m, const cwc_run_de
 {
     if (!s || !m || !d || !job_id) return set_err(CWC_E_INVALID, "null argument");
     if (m->ctx != s->ctx) return set_err(CWC_E_INVALID, "model belongs to another context");
+    if (m->gen)
+        return set_err(CWC_E_UNSUPPORTED, "the server takes fixed-tree models (no time-sliced "
+                                          "kernel for general terms)");
     auto j = std::make_unique<Job>();
     cwc_status st = validate_run(m, d, &j->rates, &j->init);
     if (st != CWC_OK) return st;

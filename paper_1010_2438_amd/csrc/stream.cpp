@@ -181,6 +181,9 @@ extern "C" cwc_status cwc_stream_open(cwc_ctx *ctx, const cwc_model *m, const cw
     if (window < 1) return set_err(CWC_E_INVALID, "window must be >= 1 sample point");
     if (d->want_traj)
         return set_err(CWC_E_UNSUPPORTED, "a streamed run keeps statistics only: want_traj must be 0");
+    if (m->gen)
+        return set_err(CWC_E_UNSUPPORTED, "streamed runs take fixed-tree models (no time-sliced "
+                                          "kernel for general terms)");
     std::vector<double> rates;
     std::vector<int> init;
     cwc_status st = validate_run(m, d, &rates, &init);

@@ -43,7 +43,9 @@ std::string tune_key(const cwc_model *m, const cwc_run_desc *d)
     while ((1ll << (lg + 1)) <= G) ++lg;
     char b[160];
     std::snprintf(b, sizeof b, "%016llx_m%d_t%d_g%d",
-                  (unsigned long long)hash_str(model_source(m->flat, m->flat.layout)), d->mode,
+                  (unsigned long long)hash_str(m->gen ? gmodel_source(*m->gen)
+                                                      : model_source(m->flat, m->flat.layout)),
+                  d->mode,
                   d->rate_table ? 1 : 0, lg);
     return b;
 }
@@ -112,6 +114,15 @@ extern "C" cwc_status cwc_autotune(cwc_ctx *ctx, const cwc_model *m, const cwc_r
 {
     if (!ctx || !m || !d || !out) return set_err(CWC_E_INVALID, "null argument");
     if (!(budget_s > 0)) return set_err(CWC_E_INVALID, "budget_s must be > 0");
+    if (m->gen) {
+        // one layout: one wavefront per trajectory; only the block varies
+        // little, so the library's choice stands
+        *out = cwc_tuning{};
+        out->block_size = 256;
+        out->waves_per_simd = 8;
+        out->lanes_per_replica = 64;
+        return CWC_OK;
+    }
     const bool persistent = d->mode == CWC_MODE_PERSISTENT;
     const int C = m->flat.n_cells;
     // stage 1 and 2 candidates: layout x block shape (x resident waves)

@@ -393,13 +393,15 @@ def receptor_internalisation(n_cells_=2, r0=3, l0=4, k_on=0.3, k_int=0.8, k_ves=
 
 
 def cell_colony(n0=8, nutrient=2000, k_up=0.002, k_grow=1.0, k_div=0.05, k_die=0.02,
-                k_feed=200.0, max_comp=64, model_seed=5):
+                k_feed=200.0, max_comp=64, model_seed=5, k_decay=0.0):
     """A colony of cells in a nutrient bath: nutrients N enter cells across
     the wrap, N (x | X)^cell -> (x | N X)^cell; inside, N becomes biomass A;
     a cell with two units of biomass divides, creating a new cell in the
     top level that takes one unit, (x | A A X)^cell -> (x | A X)^cell (| A)^cell;
     cells die (deleted with their content); nutrients are fed to the top.
-    Initial cell contents are drawn once from ``model_seed``."""
+    Initial cell contents are drawn once from ``model_seed``.  Feeding is
+    left out with ``k_feed`` = 0.  With ``k_decay`` > 0 biomass is also spent, A -> 0 inside cells, so the colony
+    can settle instead of filling its slots."""
     Nn, A = 0, 1
     rng = np.random.default_rng(model_seed)
     term = [{"label": 0, "parent": -1, "content": [nutrient, 0], "wrap": None}]
@@ -410,8 +412,11 @@ def cell_colony(n0=8, nutrient=2000, k_up=0.002, k_grow=1.0, k_div=0.05, k_die=0
              _grule(1, {"c": {Nn: 1}}, {"c": {A: 1}}, k_grow),
              _grule(0, {"c1": {A: 2}}, {"c1": {A: 1}}, k_div, child=1, action="create",
                     level=0, new={"label": 1, "wrap": [0, 0], "content": [0, 1]}),
-             _grule(0, {}, {}, k_die, child=1, action="delete", level=1),
-             _grule(0, {}, {"c": {Nn: 1}}, k_feed)]
+             _grule(0, {}, {}, k_die, child=1, action="delete", level=1)]
+    if k_feed > 0:
+        rules.append(_grule(0, {}, {"c": {Nn: 1}}, k_feed))
+    if k_decay > 0:
+        rules.append(_grule(1, {"c": {A: 1}}, {}, k_decay))
     return {"name": "cell_colony", "species": ["N", "A"],
             "labels": [{"name": "top", "wrap": False}, {"name": "cell", "wrap": True}],
             "max_comp": max_comp, "term": term, "rules": rules}
