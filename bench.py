@@ -59,9 +59,9 @@ LAUNCH = {
 
 # streamed run of the sweep: sample points per window
 STREAM_WINDOW = 20
-# serving policy of the predictive replays: slices of 4 sample points
-# (constant simulation time), at most 65536 draws, predictive order
-SERVE_PREDICTED = {"slice_events": 65536, "slice_samples": 4, "predicted": True}
+# serving policy of the predictive replays: slices of at most 64 sample
+# points (constant simulation time) and 16384 draws, predictive order
+SERVE_PREDICTED = {"slice_events": 16384, "slice_samples": 64, "predicted": True}
 # a pool small enough that admission waits for memory on the trace prefix
 SERVE_SMALL_POOL = 48 << 20
 
