@@ -271,12 +271,38 @@ def cpu_baseline(budget_s=10.0):
     return out
 
 
+def chain_seconds_per_event(ctx, stream):
+    """The shortest per-event time of one trajectory's dependent chain:
+    64 Lotka-Volterra trajectories (the smallest model of the trace) to
+    t = 20 in one plain launch with two lanes per trajectory, a wavefront
+    or two on an otherwise idle GPU, so the launch lasts as long as its
+    longest trajectory; kernel time / that trajectory's events."""
+    import workloads as W
+    from paper_1010_2438_amd import Model, Run
+    model = Model(ctx, W.lotka_volterra())
+    run = W.make_run(seed=0, replicas=64, dt=0.05, n_samples=401)
+    best = None
+    for lanes in (1, 2):
+        r = Run(ctx, model, run, mode="plain", stream=stream,
+                tuning={"block_size": 64, "lanes_per_replica": lanes})
+        r.wait()
+        r.relaunch(stream)
+        r.wait()
+        sec = r.elapsed_ms()[0] * 1e-3 / int(r.counters()["events"].max())
+        r.close()
+        best = sec if best is None else min(best, sec)
+    model.close()
+    return best
+
+
 def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=64,
-                slice_samples=0, predicted=False):
+                slice_samples=0, predicted=False, chain_s_per_event=None):
     """Replays the first n_jobs of the serving trace (Poisson arrivals, mixed
     configurations 0-3, 64..8192 replicas, t_end 5..100) against the
     continuous-batching server; arrival times are multiplied by time_scale.
-    Returns latency percentiles (submit -> statistics ready) and rates."""
+    Returns latency percentiles (submit -> statistics ready) and rates; with
+    chain_s_per_event, also each job's latency floor (its longest
+    trajectory's events x that time)."""
     import threading
     import numpy as np
     import workloads as W
@@ -325,6 +351,7 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
     th = threading.Thread(target=submitter)
     th.start()
     infos = {}
+    longest = {}            # per job: events of its longest trajectory
     # Lotka-Volterra jobs carry a count cap (prey explode once predators die
     # out): how many of their trajectories end in OVERFLOW
     overflow = {"lotka_volterra_jobs": 0, "trajectories": 0, "overflow_trajectories": 0,
@@ -335,8 +362,10 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
             raise err[0]
         for jid in srv.poll():
             infos[jid] = srv.info(jid)
+            cnt = srv.counters(jid)
+            longest[jid] = int(cnt["events"].max())
             if config_of[jid] == 0:
-                st = srv.counters(jid)["status"]
+                st = cnt["status"]
                 no = int((st == 2).sum())
                 overflow["lotka_volterra_jobs"] += 1
                 overflow["trajectories"] += int(st.size)
@@ -355,18 +384,28 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
     lat = np.array([infos[j]["t_done"] - infos[j]["t_submit"] for j in ids])
     ev = sum(infos[j]["events"] for j in ids)
     span = trace[-1]["arrival_s"] * time_scale
-    return {"jobs": len(trace), "arrival_span_s": span,
-            "offered_jobs_per_s": len(trace) / max(span, 1e-9),
-            "p50_latency_s": float(np.percentile(lat, 50)),
-            "p99_latency_s": float(np.percentile(lat, 99)),
-            "max_latency_s": float(lat.max()),
-            "events": int(ev), "achieved_events_per_s": ev / wall,
-            "offered_events_per_s": ev / max(span, 1e-9),
-            "makespan_s": wall, "ticks": st["ticks"],
-            "policy": {"slice_events": slice_events, "slice_samples": slice_samples,
-                       "order": "predicted" if predicted else "fifo"},
-            "hbm_budget_bytes": st["pool_bytes"], "pool_peak_bytes": st["pool_peak"],
-            "lotka_volterra_count_cap": {"cap": 100000, **overflow}}
+    out = {"jobs": len(trace), "arrival_span_s": span,
+           "offered_jobs_per_s": len(trace) / max(span, 1e-9),
+           "p50_latency_s": float(np.percentile(lat, 50)),
+           "p99_latency_s": float(np.percentile(lat, 99)),
+           "max_latency_s": float(lat.max()),
+           "events": int(ev), "achieved_events_per_s": ev / wall,
+           "offered_events_per_s": ev / max(span, 1e-9),
+           "makespan_s": wall, "ticks": st["ticks"],
+           "policy": {"slice_events": slice_events, "slice_samples": slice_samples,
+                      "order": "predicted" if predicted else "fifo"},
+           "hbm_budget_bytes": st["pool_bytes"], "pool_peak_bytes": st["pool_peak"],
+           "lotka_volterra_count_cap": {"cap": 100000, **overflow}}
+    if chain_s_per_event:
+        # no schedule finishes a job before its longest trajectory's events
+        # have run one after another at the fastest per-event chain
+        floor = np.array([longest[j] * chain_s_per_event for j in ids])
+        out["latency_floor"] = {
+            "chain_us_per_event": chain_s_per_event * 1e6,
+            "p50_s": float(np.percentile(floor, 50)), "p99_s": float(np.percentile(floor, 99)),
+            "max_s": float(floor.max()),
+            "longest_trajectory_events_max": int(max(longest.values()))}
+    return out
 
 
 def fnv1a64(text):
@@ -603,6 +642,8 @@ def main():
 
     serving = None
     if not args.no_serve:
+        chain = chain_seconds_per_event(ctx, stream)
+        log("one trajectory's event chain: %.3f us per event" % (chain * 1e6))
         sat = serve_trace(ctx, args.serve_jobs, 1.0, 16 << 30)
         log("serving (trace rate)", sat)
         # labelled sub-saturation runs: arrivals stretched so the offered
@@ -611,7 +652,7 @@ def main():
         # simulation time) with the predictive order, then the latter in a
         # pool small enough that admission waits for memory
         scale = max(1.0, sat["offered_events_per_s"] / (0.7 * sat["achieved_events_per_s"]))
-        sub = serve_trace(ctx, args.serve_jobs, scale, 16 << 30)
+        sub = serve_trace(ctx, args.serve_jobs, scale, 16 << 30, chain_s_per_event=chain)
         log("serving (sub-saturation, FIFO)", sub)
         pred = serve_trace(ctx, args.serve_jobs, scale, 16 << 30, **SERVE_PREDICTED)
         log("serving (sub-saturation, predicted)", pred)

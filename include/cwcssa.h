@@ -105,7 +105,8 @@ const char *cwc_last_error(void);
 
 /* ------------------------------------------------------------- context */
 
-/* Creates a context on HIP device `device`.
+/* Creates a context on HIP device `device` (the simulation engine of
+ * Sec. 2.3, here one GPU running many instances at once, Sec. 3.1.2).
  *   arena, arena_bytes: optional caller-owned device buffer (e.g. a torch
  *     tensor's storage) from which all run buffers are sub-allocated; the
  *     library never frees it.  NULL/0: the library allocates device memory
@@ -171,8 +172,9 @@ typedef struct {
                                     their tree paths, averaged over slots  */
 } cwc_model_info;
 
-/* Validates and flattens `d` into rule/context slots, generates the model's
- * device code and compiles it for the context's device (compiled code is
+/* Validates and flattens `d` into rule/context slots (Sec. 2.1: the terms
+ * and rules of a model; Sec. 2.3: a rule is matched once per compartment of
+ * its label, each match a propensity), generates the model's device code and compiles it for the context's device (compiled code is
  * cached on disk by content hash).  `d` is copied; the caller keeps it.
  * Errors: CWC_E_INVALID (bad indices, k <= 0 or not finite, negative
  * counts, non-preorder tree), CWC_E_UNSUPPORTED, CWC_E_COMPILE. */
@@ -322,7 +324,11 @@ typedef struct {
     const cwc_tuning *tuning;       /* NULL = library choice                    */
 } cwc_run_desc;
 
-/* Enqueues a run on `hip_stream` (a hipStream_t; NULL = the null stream).
+/* Enqueues a run on `hip_stream` (a hipStream_t; NULL = the null stream):
+ * G = I x R independent simulations by the direct method (Sec. 2.2 and
+ * 2.3), the replicas of one model or the instances of a parameter sweep
+ * (Sec. 3.1.2), each sampled at t_k = k dt and reduced on line into
+ * per-sample moments (Sec. 3, Sec. 5.2 schema iii).
  * Host tables are copied before return.  Buffers come from the context's
  * arena (CWC_E_NOMEM if it is too small) or from hipMalloc.
  * Errors: CWC_E_INVALID, CWC_E_NOMEM, CWC_E_DEVICE. */
@@ -330,10 +336,15 @@ cwc_status cwc_run_submit(cwc_ctx *ctx, const cwc_model *m,
                           const cwc_run_desc *d, void *hip_stream,
                           cwc_run **out);
 /* Re-enqueues the same run (same inputs, same buffers; results are
- * overwritten with identical values).  In persistent mode the launch
+ * overwritten with identical values, each trajectory's random stream being
+ * fixed by (seed, trajectory, draw): Sec. 2.2's draws made reproducible).  In persistent mode the launch
  * sequence is replayed from a captured HIP graph.  On another stream the
  * relaunch first waits for the previous launch to end. */
 cwc_status cwc_run_relaunch(cwc_run *r, void *hip_stream);
+/* Completion of the launch sequence (Sec. 5.2: the instances' results
+ * gathered once every instance has reached its end time): query sets
+ * *done to 1 or 0 without blocking; wait blocks until the end.  Errors:
+ * CWC_E_DEVICE if the launch failed. */
 cwc_status cwc_run_query(cwc_run *r, int *done);
 cwc_status cwc_run_wait(cwc_run *r);
 /* Waits at most `timeout_s` seconds (a host-side watchdog): CWC_OK once
@@ -351,14 +362,17 @@ cwc_status cwc_run_elapsed(cwc_run *r, float *sim_ms, float *total_ms);
  * when its grid already holds every trajectory.  Valid from submission on. */
 cwc_status cwc_run_kernel_name(const cwc_run *r, char *buf, size_t cap, size_t *len);
 
-/* Statistics per (instance, sample, cell): mean and unbiased variance
+/* On-line statistics (Sec. 3 and Fig. "simout": mean and variance of the
+ * instances' states at each sample time; Sec. 5.2 schema iii).
+ * Statistics per (instance, sample, cell): mean and unbiased variance
  * (NaN where fewer than 1 / 2 trajectories contributed) and the number of
  * contributing trajectories per (instance, sample).  Layout [I][K+1][C] and
  * [I][K+1].  Any pointer may be NULL.  dst_is_device: destinations are
  * device pointers.  CWC_E_NOTREADY before completion. */
 cwc_status cwc_run_fetch_stats(cwc_run *r, double *mean, double *var,
                                int64_t *n, int dst_is_device);
-/* Exact integer moments: S1 = sum x, S2 = sum x^2 split as
+/* The reduction's exact state (Sec. 5.2 schema iii, the partial sums the
+ * statistics are computed from): S1 = sum x, S2 = sum x^2 split as
  * s2_hi32 * 2^32 + s2_lo32 (each an exact uint64 sum), layout [I][K+1][C]. */
 cwc_status cwc_run_fetch_moments(cwc_run *r, uint64_t *s1, uint64_t *s2_hi32,
                                  uint64_t *s2_lo32, int64_t *n,
@@ -379,13 +393,18 @@ cwc_status cwc_run_fetch_trajectories(cwc_run *r, int32_t *dst,
  * content atoms [NS]); free slots hold 0, -1, -1 and zeros.  CWC_E_INVALID
  * for a fixed-tree model. */
 cwc_status cwc_run_fetch_term(cwc_run *r, int32_t *dst, int dst_is_device);
-/* Per trajectory [G]: applied events, terminal status, digest (0 unless
- * want_digest), final simulation time, number of recorded samples, final
- * counts [G][C].  Any pointer may be NULL. */
+/* Per trajectory [G] (each instance's end state, Sec. 2.3: the loop ends
+ * at the end time, when no rule applies, or at a cap): applied events,
+ * terminal status, digest (0 unless want_digest), final simulation time,
+ * number of recorded samples, final counts [G][C].  Any pointer may be
+ * NULL; caller-owned destinations (dst_is_device as above).  Errors:
+ * CWC_E_NOTREADY before completion. */
 cwc_status cwc_run_fetch_counters(cwc_run *r, int64_t *events,
                                   uint8_t *status, uint64_t *digest,
                                   double *t_final, int32_t *n_recorded,
                                   int32_t *final_counts, int dst_is_device);
+/* Releases the run's device buffers (arena regions or hipMalloc'd memory)
+ * after waiting for its launch to end; NULL is ignored. */
 void cwc_run_destroy(cwc_run *r);
 
 /* ------------------------------------------------- run without allocation */

@@ -68,7 +68,13 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
     const int pbase = (kind >= 0 && mypar >= 0) ? cwc_cbase[mypar] : -1;
     CWC_DECL_K;
     CWC_DECL_STATE;
-    if (SHARED_K) { CWC_LOAD_K(p.rates); }
+    if (SHARED_K) {
+        if (FORM == CWC_FORM_PERSIST) {
+            CWC_LOAD_K_FREE(p.rates);
+        } else {
+            CWC_LOAD_K(p.rates);
+        }
+    }
 
     i64 item = FORM == CWC_FORM_SLICE ? wave_first[gw] : gw;
     for (;;) {
@@ -84,7 +90,11 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
         const i64 g = p.g_base + lg;
         if (!SHARED_K) {
             const double *kr = p.rates + (i64)p.rate_stride * inst;
-            CWC_LOAD_K(kr);
+            if (FORM == CWC_FORM_PERSIST) {
+                CWC_LOAD_K_FREE(kr);
+            } else {
+                CWC_LOAD_K(kr);
+            }
         }
         double t = 0.0, t_next = 0.0;
         u64 e = 0, e0 = 0, dig = 0xcbf29ce484222325ull;

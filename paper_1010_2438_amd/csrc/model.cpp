@@ -998,7 +998,17 @@ std::string codegen_wave(const Flat &f)
     w.begin("CWC_DECL_K");
     for (int r = 0; r < NR; ++r) w.line("double k" + I(r) + " = 0.0;");
     w.end();
+    // The rates are the same in every lane (one trajectory per wavefront),
+    // but in scalar registers they crowd out the kernel's other uniform
+    // values and spill to lanes of a VGPR (a lane read per use); kept in
+    // VGPRs instead (CWC_KEEP), they fit beside the state.
     w.begin("CWC_LOAD_K(ptr)");
+    for (int r = 0; r < f.n_rules; ++r)
+        w.line("k" + I(r) + " = (ptr)[" + I(r) + "]; CWC_KEEP(k" + I(r) + ");");
+    w.end();
+    // the queue-draining form reloads them per trajectory and holds more
+    // state: there the compiler's own placement keeps two wavefronts per SIMD
+    w.begin("CWC_LOAD_K_FREE(ptr)");
     for (int r = 0; r < f.n_rules; ++r) w.line("k" + I(r) + " = (ptr)[" + I(r) + "];");
     w.end();
     w.begin("CWC_DECL_STATE");
