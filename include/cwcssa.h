@@ -266,8 +266,10 @@ typedef struct {
  * with cwc_run_submit (plain or persistent form, one wavefront per
  * trajectory; lanes_per_replica 0 or 64; rate tables allowed, init_table
  * must be NULL, the initial term is the model's; want_traj keeps the
- * observables [K+1][C][G]) and cwc_run_fetch_term.  Streamed runs and the
- * server take fixed-tree models only.  Errors: CWC_E_INVALID (indices,
+ * observables [K+1][C][G]) and cwc_run_fetch_term, and in streamed runs
+ * and the server (time-sliced, each trajectory's term checkpointed in
+ * device memory between slices; cwc_stream_fetch_term,
+ * cwc_server_fetch_term).  Errors: CWC_E_INVALID (indices,
  * rates, counts, regions beyond the pattern, non-preorder term),
  * CWC_E_UNSUPPORTED (max_comp > 64, order > 2), CWC_E_COMPILE. */
 cwc_status cwc_gmodel_create(cwc_ctx *ctx, const cwc_gmodel_desc *d,
@@ -509,6 +511,10 @@ cwc_status cwc_stream_fetch_counters(cwc_stream *s, int64_t *events,
                                      double *t_final, int32_t *n_recorded,
                                      int32_t *final_counts,
                                      int dst_is_device);
+/* General models: each trajectory's final term, as cwc_run_fetch_term,
+ * once every window has been returned.  Errors: CWC_E_NOTREADY before,
+ * CWC_E_INVALID for a fixed-tree model. */
+cwc_status cwc_stream_fetch_term(cwc_stream *s, int32_t *dst, int dst_is_device);
 /* Waits for enqueued work and releases the stream's device memory. */
 void cwc_stream_destroy(cwc_stream *s);
 
@@ -601,6 +607,11 @@ cwc_status cwc_server_fetch_counters(cwc_server *s, uint64_t job, int64_t *event
                                      uint8_t *status, uint64_t *digest, double *t_final,
                                      int32_t *n_recorded, int32_t *final_counts,
                                      int dst_is_device);
+/* General models: a completed job's final terms, as cwc_run_fetch_term.
+ * Errors: as cwc_server_fetch_counters; CWC_E_INVALID for a fixed-tree
+ * model's job. */
+cwc_status cwc_server_fetch_term(cwc_server *s, uint64_t job, int32_t *dst,
+                                 int dst_is_device);
 /* Frees a completed job's device memory; its id becomes invalid. */
 cwc_status cwc_server_release(cwc_server *s, uint64_t job);
 /* Blocks until no job is queued or active, or timeout_s elapses

@@ -33,9 +33,10 @@ SYMBOLS = [
     "cwc_run_fetch_moments", "cwc_run_fetch_trajectories", "cwc_run_fetch_term",
     "cwc_run_fetch_counters", "cwc_run_destroy", "cwc_run_into",
     "cwc_stream_open", "cwc_stream_next", "cwc_stream_info", "cwc_stream_fetch_counters",
-    "cwc_stream_destroy", "cwc_server_create", "cwc_server_set_policy",
+    "cwc_stream_fetch_term", "cwc_stream_destroy", "cwc_server_create", "cwc_server_set_policy",
     "cwc_server_submit", "cwc_server_poll", "cwc_server_job_info",
-    "cwc_server_fetch_stats", "cwc_server_fetch_counters", "cwc_server_release",
+    "cwc_server_fetch_stats", "cwc_server_fetch_counters", "cwc_server_fetch_term",
+    "cwc_server_release",
     "cwc_server_wait_idle", "cwc_server_get_stats", "cwc_server_destroy",
     "cwc_autotune",
     "cwc_realign",
@@ -191,6 +192,7 @@ def load(path: str = LIB_PATH):
         "cwc_stream_next": [P, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P, ctypes.c_int],
         "cwc_stream_info": [P, ctypes.POINTER(cwc_stream_info_t)],
         "cwc_stream_fetch_counters": [P, P, P, P, P, P, P, ctypes.c_int],
+        "cwc_stream_fetch_term": [P, P, ctypes.c_int],
         "cwc_stats_finalize": [P, P, P, P, P, I64, I32, P, P, P],
         "cwc_stats_confidence": [P, P, I64, I32, ctypes.c_double, P],
         "cwc_realign": [P, P, I64, I32, ctypes.c_double, I32, I32, P],
@@ -203,6 +205,7 @@ def load(path: str = LIB_PATH):
         "cwc_server_job_info": [P, ctypes.c_uint64, ctypes.POINTER(cwc_job_info)],
         "cwc_server_fetch_stats": [P, ctypes.c_uint64, P, P, P, ctypes.c_int],
         "cwc_server_fetch_counters": [P, ctypes.c_uint64, P, P, P, P, P, P, ctypes.c_int],
+        "cwc_server_fetch_term": [P, ctypes.c_uint64, P, ctypes.c_int],
         "cwc_server_release": [P, ctypes.c_uint64],
         "cwc_server_wait_idle": [P, ctypes.c_double],
         "cwc_server_get_stats": [P, ctypes.POINTER(cwc_server_stats)],
@@ -687,6 +690,14 @@ class Stream:
                 return
             yield w
 
+    def term(self):
+        """General models: the final term [G][max_comp][alive, label, parent,
+        wrap NS, content NS], once every window has been returned."""
+        m = self.model
+        t = np.empty((self.G, m.max_comp, 3 + 2 * m.n_species), np.int32)
+        check(load().cwc_stream_fetch_term(self.h, t.ctypes.data, 0))
+        return t
+
     def info(self) -> Dict:
         i = cwc_stream_info_t()
         check(load().cwc_stream_info(self.h, ctypes.byref(i)))
@@ -745,6 +756,7 @@ class Server:
         self.h = h
         self.ctx = ctx
         self.shapes = {}
+        self.models = {}
 
     def set_policy(self, slice_samples: int = 0, predicted: bool = False):
         """cwc_server_set_policy: slices of `slice_samples` sample points (0:
@@ -757,6 +769,7 @@ class Server:
         check(load().cwc_server_submit(self.h, model.h, ctypes.byref(d), ctypes.byref(jid)))
         self.shapes[jid.value] = (run["n_instances"], run["replicas"], run["n_samples"],
                                   model.info["n_cells"])
+        self.models[jid.value] = model
         return jid.value
 
     def poll(self, max_n=4096):
@@ -795,9 +808,21 @@ class Server:
                                                         "final_counts")], 0))
         return out
 
+    def term(self, jid):
+        """General models: a completed job's final terms [G][max_comp][alive,
+        label, parent, wrap NS, content NS]."""
+        I, R, K1, C = self.shapes[jid]
+        m = self.models[jid]
+        # a fixed-tree job: the library refuses it before writing anything
+        shape = (I * R, m.max_comp, 3 + 2 * m.n_species) if hasattr(m, "max_comp") else (1,)
+        t = np.empty(shape, np.int32)
+        check(load().cwc_server_fetch_term(self.h, jid, t.ctypes.data, 0))
+        return t
+
     def release(self, jid):
         check(load().cwc_server_release(self.h, jid))
         self.shapes.pop(jid, None)
+        self.models.pop(jid, None)
 
     def server_stats(self):
         st = cwc_server_stats()

@@ -271,19 +271,33 @@ __device__ __forceinline__ void gen_observe(const GenLane &s, int *obs)
     }
 }
 
-template <bool PERSIST, bool SHARED_K>
-__device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p)
+#define G_FORM_PLAIN 0
+#define G_FORM_PERSIST 1
+#define G_FORM_SLICE 2
+
+// FORM: run to completion (plain: one trajectory per wavefront of the grid;
+// persistent: wavefronts claim trajectories from the queue) or time-sliced
+// (streamed runs and serving: wavefront w works on job wave_job[w],
+// trajectory wave_first[w], for at most `budget` draws and before the
+// slice's stop sample, resuming from and suspending to a checkpoint: the
+// term in final_term, the time, event count, digest and next sample in
+// ck_*).
+template <int FORM, bool SHARED_K>
+__device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p0, const cwc_kparams *jobs,
+                                             const int *wave_job, const long long *wave_first,
+                                             long long budget)
 {
     const double INF = __longlong_as_double(0x7FF0000000000000ll);
     const int lane = (int)__lane_id();
     const i64 gw = __builtin_amdgcn_readfirstlane(
         (int)(((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const cwc_kparams &p = FORM == G_FORM_SLICE ? jobs[wave_job[gw]] : p0;
     double k[G_NR > 0 ? G_NR : 1];
     if (SHARED_K) {
 #pragma unroll
         for (int r = 0; r < G_NR; ++r) k[r] = p.rates[r];
     }
-    i64 item = gw;
+    i64 item = FORM == G_FORM_SLICE ? wave_first[gw] : gw;
     for (;;) {
         if (item >= p.G) break;
         i64 lg = item;
@@ -299,23 +313,52 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p)
 #pragma unroll
             for (int r = 0; r < G_NR; ++r) k[r] = kr[r];
         }
-        // the initial term
+        const int cks = FORM == G_FORM_SLICE ? (int)p.ck_state[lg] : 0;
+        if (cks == 2) break;                          // already finished
         GenLane s;
-        const bool init_ = lane < G_NINIT;
-        const int il = init_ ? lane : 0;      // every table read in bounds
-        s.lab = init_ ? g_init_label[il] : -1;
-        s.par = init_ ? g_init_parent[il] : -1;
-#pragma unroll
-        for (int a = 0; a < G_NS; ++a) {
-            s.c[a] = init_ ? g_init_content[il * G_NS + a] : 0;
-            s.w[a] = init_ ? g_init_wrap[il * G_NS + a] : 0;
-        }
         double t = 0.0, t_next = 0.0;
         u64 e = 0, e0 = 0, dig = 0xcbf29ce484222325ull;
         i32 kn = 0;
+        if (cks == 1) {
+            // resume: the term and the scalars saved at the last suspension
+            const bool in_ = lane < G_MAXC;
+            const int *row = p.final_term + (lg * G_MAXC + (in_ ? lane : 0)) * (i64)G_W;
+            s.lab = in_ ? row[1] : -1;
+            s.par = in_ ? row[2] : -1;
+#pragma unroll
+            for (int a = 0; a < G_NS; ++a) {
+                s.w[a] = in_ ? row[3 + a] : 0;
+                s.c[a] = in_ ? row[3 + G_NS + a] : 0;
+            }
+            t = p.ck_t[lg];
+            e = p.ck_e[lg];
+            dig = p.ck_dig[lg];
+            kn = p.ck_kn[lg];
+            t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
+        } else {
+            // the initial term
+            const bool init_ = lane < G_NINIT;
+            const int il = init_ ? lane : 0;      // every table read in bounds
+            s.lab = init_ ? g_init_label[il] : -1;
+            s.par = init_ ? g_init_parent[il] : -1;
+#pragma unroll
+            for (int a = 0; a < G_NS; ++a) {
+                s.c[a] = init_ ? g_init_content[il * G_NS + a] : 0;
+                s.w[a] = init_ ? g_init_wrap[il * G_NS + a] : 0;
+            }
+        }
+        // the slice stops before this sample (streamed windows, sample
+        // slices); the run-to-completion forms never stop early
+        i32 kstop = 0x7FFFFFFF;
+        if (FORM == G_FORM_SLICE) {
+            kstop = p.k_stop;
+            if (p.k_slice > 0 && (long long)kn + p.k_slice < (long long)p.k_stop)
+                kstop = kn + p.k_slice;
+        }
         bool have_batch = false;
         double Eb = 0.0, Ub = 0.0;
         int st = CWC_ST_RUNNING;
+        long long n = 0;                    // draws in this slice
         int obs[G_NOBS];
 
 #define GEN_EMIT()                                                            \
@@ -340,6 +383,8 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p)
     } while (0)
 
         while (st == CWC_ST_RUNNING) {
+            if (FORM == G_FORM_SLICE && n == budget) break;
+            ++n;
             // ---- Match
             GenAbove u;
             gen_gather(s, u, lane);
@@ -365,12 +410,16 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p)
             }
             const int di = (int)(e - e0);
             if (a0 == 0.0) {
-                while (kn < p.K1) GEN_EMIT();
-                st = CWC_ST_ABSORBED;
+                while (kn < p.K1 && kn < kstop) GEN_EMIT();
+                st = kn < p.K1 ? CWC_ST_WINDOW : CWC_ST_ABSORBED;
                 break;
             }
             const double tn = t + cwc_rl(Eb, di) / a0;
-            while (t_next < tn) GEN_EMIT();
+            while (t_next < tn && kn < kstop) GEN_EMIT();
+            if (t_next < tn) {
+                st = CWC_ST_WINDOW;     // the slice's last sample is done
+                break;
+            }
             if (kn >= p.K1) {
                 st = CWC_ST_OK;
                 break;
@@ -412,6 +461,28 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p)
             }
         }
 #undef GEN_EMIT
+        if (FORM == G_FORM_SLICE && (st == CWC_ST_RUNNING || st == CWC_ST_WINDOW)) {
+            // ---- suspend: the term and the scalars back to the checkpoint
+            if (lane < G_MAXC) {
+                int *row = p.final_term + (lg * G_MAXC + lane) * (i64)G_W;
+                row[0] = s.lab >= 0 ? 1 : 0;
+                row[1] = s.lab;
+                row[2] = s.par;
+#pragma unroll
+                for (int a2 = 0; a2 < G_NS; ++a2) {
+                    row[3 + a2] = s.w[a2];
+                    row[3 + G_NS + a2] = s.c[a2];
+                }
+            }
+            if (lane == 0) {
+                p.ck_t[lg] = t;
+                p.ck_e[lg] = e;
+                p.ck_dig[lg] = dig;
+                p.ck_kn[lg] = kn;
+                p.ck_state[lg] = 1;
+            }
+            break;
+        }
         // ---- finish: observables, per-trajectory results, final term
         gen_observe(s, obs);
         if (lane == 0) {
@@ -424,6 +495,10 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p)
             p.status[lg] = (unsigned char)st;
             p.n_recorded[lg] = kn;
             if (p.rec_hist) atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);
+            if (FORM == G_FORM_SLICE) {
+                p.ck_state[lg] = 2;
+                atomicAdd(p.done_count, 1ull);
+            }
         }
         if (p.final_term && lane < G_MAXC) {
             int *row = p.final_term + (lg * G_MAXC + lane) * (i64)G_W;
@@ -436,7 +511,7 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p)
                 row[3 + G_NS + a2] = s.c[a2];
             }
         }
-        if (!PERSIST) break;
+        if (FORM != G_FORM_PERSIST) break;
         u64 nxt = 0;
         if (lane == 0) nxt = atomicAdd(p.cursor, 1ull);
         item = (i64)__shfl((long long)nxt, 0);
@@ -444,10 +519,22 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p)
 }
 
 extern "C" __global__ void __launch_bounds__(256)
-cwc_gen_plain_shared(cwc_kparams p) { cwc_gen_main<false, true>(p); }
+cwc_gen_plain_shared(cwc_kparams p)
+{ cwc_gen_main<G_FORM_PLAIN, true>(p, nullptr, nullptr, nullptr, 0); }
 extern "C" __global__ void __launch_bounds__(256)
-cwc_gen_plain_table(cwc_kparams p) { cwc_gen_main<false, false>(p); }
+cwc_gen_plain_table(cwc_kparams p)
+{ cwc_gen_main<G_FORM_PLAIN, false>(p, nullptr, nullptr, nullptr, 0); }
 extern "C" __global__ void __launch_bounds__(256)
-cwc_gen_persistent_shared(cwc_kparams p) { cwc_gen_main<true, true>(p); }
+cwc_gen_persistent_shared(cwc_kparams p)
+{ cwc_gen_main<G_FORM_PERSIST, true>(p, nullptr, nullptr, nullptr, 0); }
 extern "C" __global__ void __launch_bounds__(256)
-cwc_gen_persistent_table(cwc_kparams p) { cwc_gen_main<true, false>(p); }
+cwc_gen_persistent_table(cwc_kparams p)
+{ cwc_gen_main<G_FORM_PERSIST, false>(p, nullptr, nullptr, nullptr, 0); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_gen_slice_shared(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
+                     long long budget)
+{ cwc_gen_main<G_FORM_SLICE, true>(jobs[0], jobs, wave_job, wave_first, budget); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_gen_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
+                    long long budget)
+{ cwc_gen_main<G_FORM_SLICE, false>(jobs[0], jobs, wave_job, wave_first, budget); }

@@ -106,6 +106,7 @@ struct Job {
     bool shared_k = true;
     long long I = 0, R = 0, G = 0;
     int K1 = 0, C = 0, NR = 1;
+    long long term_ints = 0;          // general models: the terms [G][slots][row]
     cwc_run_desc d{};
     std::vector<double> rates;
     std::vector<int> init;
@@ -138,6 +139,7 @@ size_t job_bytes(const Job &j)
     b += rounded(G) * 2 + rounded(G * 4) * 2;                            // status ck_state, n_rec ck_kn
     b += rounded(mom * 8) * 5;                                           // s1 s2hi s2lo mean var
     b += rounded(I * (K1 + 1) * 8) + rounded(I * K1 * 8);                // hist, n
+    if (j.term_ints) b += rounded((size_t)j.term_ints * 4);              // terms (checkpoint)
     return b;
 }
 
@@ -236,7 +238,8 @@ bool reserve(cwc_server *s, Job *j)
               take(s, j, &kp.s2_hi32, mom) && take(s, j, &kp.s2_lo32, mom) &&
               take(s, j, &j->mean, mom) && take(s, j, &j->var, mom) &&
               take(s, j, &kp.rec_hist, j->I * (long long)(j->K1 + 1)) &&
-              take(s, j, &j->nk, j->I * (long long)j->K1);
+              take(s, j, &j->nk, j->I * (long long)j->K1) &&
+              (!j->term_ints || take(s, j, &kp.final_term, j->term_ints));
     if (!ok) {
         drop(s, j);
         return false;
@@ -650,16 +653,18 @@ cwc_status cwc_server_submit(cwc_server *s, const cwc_model *m, const cwc_run_de
 {
     if (!s || !m || !d || !job_id) return set_err(CWC_E_INVALID, "null argument");
     if (m->ctx != s->ctx) return set_err(CWC_E_INVALID, "model belongs to another context");
-    if (m->gen)
-        return set_err(CWC_E_UNSUPPORTED, "the server takes fixed-tree models (no time-sliced "
-                                          "kernel for general terms)");
     auto j = std::make_unique<Job>();
     cwc_status st = validate_run(m, d, &j->rates, &j->init);
     if (st != CWC_OK) return st;
+    // general models run one wavefront per trajectory (layout 2), their
+    // terms checkpointed in the job's term buffer between slices
     st = ensure_layout(const_cast<cwc_model *>(m), m->flat.layout);
     if (st != CWC_OK) return st;
     j->m = const_cast<cwc_model *>(m);
     j->layout = m->flat.layout;
+    if (m->gen)
+        j->term_ints = d->n_instances * d->replicas_per_instance * (long long)m->gen->max_comp *
+                       (3 + 2 * m->gen->n_species);
     j->d = *d;
     j->d.tuning = nullptr;
     j->I = d->n_instances;
@@ -759,6 +764,25 @@ cwc_status cwc_server_fetch_counters(cwc_server *s, uint64_t job, int64_t *event
         (st = copy_out(t_final, j->kp.t_final, G * 8, dv, a)) == CWC_OK &&
         (st = copy_out(n_recorded, j->kp.n_recorded, G * 4, dv, a)) == CWC_OK)
         st = copy_out(final_counts, j->kp.final_counts, G * j->C * 4, dv, a);
+    (void)hipStreamDestroy(a);
+    return st;
+}
+
+cwc_status cwc_server_fetch_term(cwc_server *s, uint64_t job, int32_t *dst, int dst_is_device)
+{
+    if (!s || !dst) return set_err(CWC_E_INVALID, "null argument");
+    cwc_status st = CWC_OK;
+    Job *j;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        j = find_done(s, job, &st);
+    }
+    if (!j) return st;
+    if (!j->term_ints) return set_err(CWC_E_INVALID, "not a general model: its term is fixed");
+    hipStream_t a;
+    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess)
+        return set_err(CWC_E_DEVICE, "stream");
+    st = copy_out(dst, j->kp.final_term, (size_t)j->term_ints * 4, dst_is_device, a);
     (void)hipStreamDestroy(a);
     return st;
 }

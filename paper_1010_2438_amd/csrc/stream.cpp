@@ -181,9 +181,6 @@ extern "C" cwc_status cwc_stream_open(cwc_ctx *ctx, const cwc_model *m, const cw
     if (window < 1) return set_err(CWC_E_INVALID, "window must be >= 1 sample point");
     if (d->want_traj)
         return set_err(CWC_E_UNSUPPORTED, "a streamed run keeps statistics only: want_traj must be 0");
-    if (m->gen)
-        return set_err(CWC_E_UNSUPPORTED, "streamed runs take fixed-tree models (no time-sliced "
-                                          "kernel for general terms)");
     std::vector<double> rates;
     std::vector<int> init;
     cwc_status st = validate_run(m, d, &rates, &init);
@@ -220,18 +217,32 @@ extern "C" cwc_status cwc_stream_open(cwc_ctx *ctx, const cwc_model *m, const cw
         }                                                                              \
     } while (0)
     // layout: the model's own; lane-layout models run two lanes per
-    // trajectory when they have two leaves, unless the tuning asks for one
+    // trajectory when they have two leaves, unless the tuning asks for one;
+    // general models one wavefront per trajectory
     s->layout = f.layout;
     int lanes = d->tuning ? d->tuning->lanes_per_replica : 0;
-    if (lanes == 64) s->layout = 1;
-    else if (lanes == 1 || lanes == 2) s->layout = 0;
-    else if (lanes != 0) {
+    if (m->gen) {
+        if (lanes != 0 && lanes != 64) {
+            free_stream(s);
+            return set_err(CWC_E_UNSUPPORTED, "a general model runs one wavefront per "
+                                              "trajectory (lanes_per_replica 0 or 64)");
+        }
+    } else if (lanes == 64) {
+        s->layout = 1;
+    } else if (lanes == 1 || lanes == 2) {
+        s->layout = 0;
+    } else if (lanes != 0) {
         free_stream(s);
         return set_err(CWC_E_UNSUPPORTED, "a streamed run takes lanes_per_replica 0, 1, 2 or 64");
     }
     STCHK(ensure_layout(const_cast<cwc_model *>(m), s->layout));
     const bool shared = !(d->rate_table && f.n_rules > 0);
-    if (s->layout == 1) {
+    if (s->layout == 2) {
+        s->group = 64;
+        s->per_wave = 1;
+        s->fn = m->fn[2][shared ? 4 : 5];
+        s->kernel = shared ? "cwc_gen_slice_shared" : "cwc_gen_slice_table";
+    } else if (s->layout == 1) {
         s->group = 64;
         s->per_wave = 1;
         s->fn = m->fn[1][shared ? 4 : 5];
@@ -276,6 +287,11 @@ extern "C" cwc_status cwc_stream_open(cwc_ctx *ctx, const cwc_model *m, const cw
     STCHK(take(s, &kp.ck_kn, G));
     STCHK(take(s, &kp.ck_state, G));
     STCHK(take(s, &kp.done_count, 1));
+    // general models: the term of each trajectory, its checkpoint while it
+    // runs and its final term once it has ended
+    if (m->gen)
+        STCHK(take(s, &kp.final_term,
+                   G * (long long)m->gen->max_comp * (3 + 2 * m->gen->n_species)));
     STCHK(take(s, &kp.s1, rows * C));
     STCHK(take(s, &kp.s2_hi32, rows * C));
     STCHK(take(s, &kp.s2_lo32, rows * C));
@@ -440,6 +456,22 @@ extern "C" cwc_status cwc_stream_fetch_counters(cwc_stream *s, int64_t *events, 
     if (t_final) HIPCHK(hipMemcpy(t_final, s->kp.t_final, G * 8, kind));
     if (n_recorded) HIPCHK(hipMemcpy(n_recorded, s->kp.n_recorded, G * 4, kind));
     if (final_counts) HIPCHK(hipMemcpy(final_counts, s->kp.final_counts, G * s->C * 4, kind));
+    return CWC_OK;
+}
+
+extern "C" cwc_status cwc_stream_fetch_term(cwc_stream *s, int32_t *dst, int dst_is_device)
+{
+    if (!s || !dst) return set_err(CWC_E_INVALID, "null argument");
+    if (!s->m->gen) return set_err(CWC_E_INVALID, "not a general model: its term is fixed");
+    if (s->next_window < s->n_windows)
+        return set_err(CWC_E_NOTREADY, "the stream has windows left (%d of %d returned)",
+                       s->next_window, s->n_windows);
+    HIPCHK(hipSetDevice(s->ctx->device));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const GFlat &g = *s->m->gen;
+    HIPCHK(hipMemcpy(dst, s->kp.final_term,
+                     (size_t)s->G * g.max_comp * (3 + 2 * g.n_species) * sizeof(int32_t),
+                     dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     return CWC_OK;
 }
 

@@ -126,10 +126,11 @@ def test_general_model_errors(ctx):
     assert e.value.code == -2
     with pytest.raises(CwcError):
         Run(ctx, gm, dict(run, init_table=np.zeros((1, gm.info["n_cells"]), np.int32)))
-    with pytest.raises(CwcError):
-        Stream(ctx, gm, run, 2)
+    with pytest.raises(CwcError) as e:
+        Stream(ctx, gm, run, 2, lanes_per_replica=2)          # one wavefront per trajectory
+    assert e.value.code == -2
     srv = Server(ctx, hbm_budget=8 << 20, max_active=2, slice_events=1024)
     with pytest.raises(CwcError):
-        srv.submit(gm, run)
+        srv.submit(gm, dict(run, init_table=np.zeros((1, gm.info["n_cells"]), np.int32)))
     srv.close()
     gm.close()

@@ -96,6 +96,70 @@ def test_alone_vs_mix(ctx, slice_samples, predicted):
     srv.close()
 
 
+@pytest.mark.parametrize("slice_samples,predicted", [(0, False), (4, True)])
+def test_general_jobs_in_mix(ctx, slice_samples, predicted):
+    """General models (compartments created, dissolved, deleted) served
+    beside a fixed-tree job: each job's counters, statistics and final terms
+    equal the job run alone, with the terms checkpointed between slices; one
+    job is also checked against the general oracle."""
+    from paper_1010_2438_amd import CwcError, GModel, Model, Run, Server
+    print("case serving general mix slice_samples", slice_samples, "predicted", predicted,
+          flush=True)
+    colony = W.cell_colony(n0=4, nutrient=300, max_comp=24)
+    tab = np.tile(np.array([r["k"] for r in colony["rules"]]), (3, 1)) * \
+        np.array([0.5, 1.0, 2.0])[:, None]
+    specs = [
+        (colony, W.make_run(seed=31, replicas=40, dt=0.5, n_samples=21)),
+        (W.cell_dissolution(release_wrap=True), W.make_run(seed=32, replicas=77, dt=0.25,
+                                                           n_samples=17)),
+        (colony, W.make_run(seed=33, n_instances=3, replicas=10, dt=0.5, n_samples=21,
+                            rate_table=tab)),
+        (W.nested_export(), W.make_run(seed=34, replicas=64, dt=0.25, n_samples=17,
+                                       max_events=300)),
+    ]
+    gms = {}
+    for m, _ in specs:
+        if repr(m) not in gms:
+            gms[repr(m)] = GModel(ctx, m)
+    alone = []
+    for m, run in specs:
+        r = Run(ctx, gms[repr(m)], run, mode="plain", want_digest=True)
+        r.wait()
+        g = r.counters()
+        g["stats"] = r.stats()
+        g["term"] = r.term()
+        r.close()
+        alone.append(g)
+    orc = oracle.gsimulate(specs[1][0], specs[1][1], want_term=True, threads=8)
+    for key in ("events", "status", "digest", "n_recorded", "final_counts"):
+        assert np.array_equal(alone[1][key], orc[key]), key
+    assert np.array_equal(alone[1]["term"], orc["term"])
+    lv = Model(ctx, W.lotka_volterra())
+    lv_run = W.make_run(seed=35, replicas=100, dt=0.05, n_samples=21)
+    srv = Server(ctx, hbm_budget=256 << 20, max_active=16, slice_events=97)
+    srv.set_policy(slice_samples, predicted)
+    ids = [srv.submit(gms[repr(m)], run, want_digest=True) for m, run in specs]
+    lv_id = srv.submit(lv, lv_run)
+    srv.wait_idle(300)
+    assert set(srv.poll()) == set(ids) | {lv_id}
+    for jid, g in zip(ids, alone):
+        c = srv.counters(jid)
+        for key in ("events", "status", "digest", "n_recorded", "final_counts"):
+            assert np.array_equal(c[key], g[key]), (jid, key)
+        assert same_float(c["t_final"], g["t_final"])
+        same_stats(srv.stats(jid), g["stats"])
+        assert np.array_equal(srv.term(jid), g["term"]), jid
+    assert max(srv.info(j)["n_ticks"] for j in ids) > 3     # really sliced
+    with pytest.raises(CwcError):
+        srv.term(lv_id)                                     # a fixed-tree job has no term
+    for j in ids + [lv_id]:
+        srv.release(j)
+    assert srv.server_stats()["pool_used"] == 0
+    srv.close()
+    for gm in gms.values():
+        gm.close()
+
+
 def test_admission_within_budget(ctx):
     """A pool that holds two jobs at a time: the client fetches and releases
     finished jobs, queued jobs are admitted FIFO as memory frees up, the pool

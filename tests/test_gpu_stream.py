@@ -135,6 +135,54 @@ def test_stream_confidence_bands_match_run(ctx):
     s.close()
 
 
+def check_gstream(ctx, m, run, window):
+    """A general model streamed: every window's rows and every trajectory's
+    counters and final term against the general oracle."""
+    from paper_1010_2438_amd import GModel, Stream
+    print("case general stream", m["name"], "window", window,
+          "G", run["n_instances"] * run["replicas"], "K1", run["n_samples"], flush=True)
+    orc = oracle.gsimulate(m, run, want_term=True, threads=8)
+    gm = GModel(ctx, m)
+    s = Stream(ctx, gm, run, window, want_digest=True)
+    assert s.info()["kernel"].startswith("cwc_gen_slice"), s.info()["kernel"]
+    K1, seen = run["n_samples"], 0
+    for k0, mean, var, n in s:
+        assert k0 == seen
+        rows = mean.shape[1]
+        assert np.array_equal(n, orc["n"][:, k0:k0 + rows].astype(np.int64)), k0
+        assert close_rel(mean, orc["mean"][:, k0:k0 + rows]), k0
+        assert close_rel(var, orc["var"][:, k0:k0 + rows]), k0
+        seen += rows
+    assert seen == K1
+    got = s.counters()
+    for key in RESULT_KEYS:
+        assert np.array_equal(got[key], orc[key]), key
+    assert same_float(got["t_final"], orc["t_final"])
+    assert np.array_equal(s.term(), orc["term"])
+    s.close()
+    gm.close()
+
+
+def test_stream_general_models(ctx):
+    """Compartments created, dissolved and deleted across window ends: the
+    term is checkpointed between windows; rate tables and the pool-full
+    OVERFLOW end trajectories mid-window."""
+    check_gstream(ctx, W.cell_colony(n0=3, nutrient=40, max_comp=16, k_up=0.2, k_div=0.4,
+                                     k_die=0.1),
+                  W.make_run(seed=21, replicas=150, dt=0.25, n_samples=37), window=5)
+    check_gstream(ctx, W.cell_dissolution(release_wrap=True),
+                  W.make_run(seed=22, replicas=97, dt=0.25, n_samples=17), window=3)
+    check_gstream(ctx, W.nested_export(), W.make_run(seed=23, replicas=64, dt=0.25, n_samples=17),
+                  window=16)
+    m = W.cell_colony(n0=4, nutrient=300, max_comp=24)
+    tab = np.tile(np.array([r["k"] for r in m["rules"]]), (4, 1)) * \
+        np.array([0.5, 1.0, 2.0, 3.0])[:, None]
+    check_gstream(ctx, m, W.make_run(seed=24, n_instances=4, replicas=20, dt=0.5, n_samples=21,
+                                     rate_table=tab), window=4)
+    check_gstream(ctx, W.cell_birth_death(lam=20.0, mu=0.1, n0=0, max_comp=5),
+                  W.make_run(seed=25, replicas=50, dt=0.1, n_samples=40), window=7)
+
+
 def test_stream_errors(ctx):
     from paper_1010_2438_amd import CwcError, Model, Stream
     m = W.birth_death()
