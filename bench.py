@@ -296,7 +296,8 @@ def chain_seconds_per_event(ctx, stream):
 
 
 def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=64,
-                slice_samples=0, predicted=False, chain_s_per_event=None):
+                slice_samples=0, predicted=False, chain_s_per_event=None, resident=False,
+                detail=False):
     """Replays the first n_jobs of the serving trace (Poisson arrivals, mixed
     configurations 0-3, 64..8192 replicas, t_end 5..100) against the
     continuous-batching server; arrival times are multiplied by time_scale.
@@ -317,7 +318,7 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
             mo[key] = Model(ctx, m)
     tab, _ = W.sweep_rate_table(models[1], 4096, 2)
     srv = Server(ctx, hbm_budget=budget, max_active=max_active, slice_events=slice_events)
-    srv.set_policy(slice_samples, predicted)
+    srv.set_policy(slice_samples, predicted, resident)
 
     def run_of(job):
         c = job["config"]
@@ -393,9 +394,15 @@ def serve_trace(ctx, n_jobs, time_scale, budget, slice_events=4096, max_active=6
            "offered_events_per_s": ev / max(span, 1e-9),
            "makespan_s": wall, "ticks": st["ticks"],
            "policy": {"slice_events": slice_events, "slice_samples": slice_samples,
-                      "order": "predicted" if predicted else "fifo"},
+                      "order": "resident" if resident else
+                      ("predicted" if predicted else "fifo")},
            "hbm_budget_bytes": st["pool_bytes"], "pool_peak_bytes": st["pool_peak"],
            "lotka_volterra_count_cap": {"cap": 100000, **overflow}}
+    if detail:
+        out["per_job"] = [{"config": trace[i]["config"], "replicas": trace[i]["replicas"],
+                           "t_submit": infos[j]["t_submit"], "t_admit": infos[j]["t_admit"],
+                           "t_done": infos[j]["t_done"], "longest": longest[j],
+                           "events": infos[j]["events"]} for i, j in enumerate(ids)]
     if chain_s_per_event:
         # no schedule finishes a job before its longest trajectory's events
         # have run one after another at the fastest per-event chain
@@ -658,10 +665,13 @@ def main():
         log("serving (sub-saturation, predicted)", pred)
         small = serve_trace(ctx, args.serve_jobs, scale, SERVE_SMALL_POOL, **SERVE_PREDICTED)
         log("serving (sub-saturation, predicted, small pool)", small)
-        best = min((sub, pred), key=lambda r: r["p99_latency_s"])
+        res = serve_trace(ctx, args.serve_jobs, scale, 16 << 30, resident=True)
+        log("serving (sub-saturation, resident kernels)", res)
+        best = min((sub, pred, res), key=lambda r: r["p99_latency_s"])
         serving = {"trace": "first %d jobs of %s" % (args.serve_jobs, W.CONFIG_NAMES[4]),
                    "at_trace_rate": sat, "sub_saturation": dict(sub, time_scale=scale),
                    "sub_saturation_predicted": dict(pred, time_scale=scale),
+                   "sub_saturation_resident": dict(res, time_scale=scale),
                    "sub_saturation_small_pool": dict(small, time_scale=scale),
                    "p50_latency_s": best["p50_latency_s"], "p99_latency_s": best["p99_latency_s"],
                    "p_latency_policy": best["policy"]}

@@ -588,13 +588,28 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
  * first (in arrival order), then the job whose predicted remaining time --
  * remaining slices (sample points left / slice_samples) times its mean
  * slice wall time so far -- is longest (FIFO while slice_samples is 0).
- * Results never depend on either setting.  Errors: CWC_E_INVALID. */
+ * CWC_SCHED_RESIDENT (paper Sec. 5.2: the farm's workers take instances
+ * from one stream of tasks as they become free): no slices; each model
+ * group (model, layout, rate-table use) has a queue of (job, trajectory)
+ * items in coherent host memory, published as jobs are admitted, and
+ * resident kernels of that group -- one per free device stream, launched
+ * when items wait unclaimed -- keep claiming items and running them to
+ * their end while new jobs arrive; a kernel's wavefront leaves after 2 ms
+ * without an item, and the kernel that completes a job's last item reports
+ * the job's id to the host.  slice_events and slice_samples do not apply;
+ * a job takes at most 2^18 items (wavefront-sized runs of trajectories).
+ * The switch to or from CWC_SCHED_RESIDENT needs a server with no queued
+ * or active job.  Results never depend on the policy.  Errors:
+ * CWC_E_INVALID. */
 #define CWC_SCHED_FIFO      0
 #define CWC_SCHED_PREDICTED 1
+#define CWC_SCHED_RESIDENT  2
 cwc_status cwc_server_set_policy(cwc_server *s, int32_t slice_samples, int32_t policy);
 /* Queues a job (never blocks).  Tables are copied.  mode and tuning of `d`
- * are ignored (the server's time-sliced form is used).  CWC_E_NOMEM if the
- * job alone exceeds the pool; CWC_E_INVALID as cwc_run_submit. */
+ * are ignored (the server's time-sliced or resident form is used).
+ * CWC_E_NOMEM if the job alone exceeds the pool; CWC_E_INVALID as
+ * cwc_run_submit; CWC_E_UNSUPPORTED for a resident-policy job of more than
+ * 2^18 items. */
 cwc_status cwc_server_submit(cwc_server *s, const cwc_model *m, const cwc_run_desc *d,
                              uint64_t *job_id);
 /* Ids of jobs completed since the last poll (each reported once). */

@@ -758,10 +758,13 @@ class Server:
         self.shapes = {}
         self.models = {}
 
-    def set_policy(self, slice_samples: int = 0, predicted: bool = False):
+    def set_policy(self, slice_samples: int = 0, predicted: bool = False,
+                   resident: bool = False):
         """cwc_server_set_policy: slices of `slice_samples` sample points (0:
-        draw-bounded only) and the predictive dispatch order."""
-        check(load().cwc_server_set_policy(self.h, int(slice_samples), 1 if predicted else 0))
+        draw-bounded only) and the predictive dispatch order; or resident
+        kernels draining per-model queues of (job, trajectory) items."""
+        policy = 2 if resident else (1 if predicted else 0)
+        check(load().cwc_server_set_policy(self.h, int(slice_samples), policy))
 
     def submit(self, model: Model, run: Dict, want_digest=False) -> int:
         d, _r, _i = _run_desc(run, want_digest)

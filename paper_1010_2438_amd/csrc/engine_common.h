@@ -25,6 +25,84 @@ typedef long long i64;
 // window); the trajectory resumes from its checkpoint in the next window
 #define CWC_ST_WINDOW (-2)
 
+// ------------------------------------------------- resident serving kernels
+// A resident kernel stays on the device while the host keeps publishing
+// (job, trajectory) items: each wavefront claims the next item, copies its
+// job's parameters, runs the item's trajectories to their end, counts them
+// toward the job and claims again, until the host asks it to stop or no
+// item has come for a while.
+
+// Claims the next item for the calling wavefront (lane 0 claims; the result
+// is the same in every lane).  False once the host has asked for a stop,
+// or when no item has been published for q.idle_ticks of wall-clock time.
+// The acquire load of the host's tail orders the item's words and
+// everything the host made visible before publishing it (the job's tables,
+// zeroed accumulators, its parameters) before this wavefront's next loads.
+__device__ __forceinline__ bool cwc_rq_claim(const cwc_rq &q, int &slot, i64 &first, i64 &job)
+{
+    i64 s = -1, f = 0, id = 0;
+    if (__lane_id() == 0) {
+        const u64 t0 = wall_clock64();
+        for (;;) {
+            if (__hip_atomic_load(q.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+            u64 h = __hip_atomic_load(q.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const i64 t = __hip_atomic_load(q.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            if ((i64)h < t) {
+                // another wavefront may take item h first: then try again
+                // at once (every failure is some wavefront's claim)
+                if (__hip_atomic_compare_exchange_strong(q.head, &h, h + 1ull, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)) {
+                    const i64 *it = q.items + CWC_RQ_ITEM * (i64)(h & (u64)q.mask);
+                    s = __hip_atomic_load(it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    f = __hip_atomic_load(it + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    id = __hip_atomic_load(it + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    break;
+                }
+                continue;
+            }
+            if ((i64)(wall_clock64() - t0) > q.idle_ticks) break;
+            __builtin_amdgcn_s_sleep(127);
+        }
+    }
+    s = __shfl(s, 0);
+    f = __shfl(f, 0);
+    id = __shfl(id, 0);
+    slot = (int)s;
+    first = f;
+    job = id;
+    return s >= 0;
+}
+
+// Copies a job's parameters into the wavefront's LDS copy with loads that
+// bypass the caches: a slot's parameters change between jobs while the
+// kernel runs.
+__device__ __forceinline__ void cwc_rq_params(cwc_kparams *dst, const cwc_kparams *src)
+{
+    constexpr int W = (int)(sizeof(cwc_kparams) / sizeof(u32));
+    const u32 *s = (const u32 *)src;
+    u32 *d = (u32 *)dst;
+    for (int i = (int)__lane_id(); i < W; i += 64)
+        d[i] = __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// After an item: its n finished trajectories count toward the job once
+// their results are visible device-wide (release); the wavefront whose
+// count completes the job publishes the job's id to the host.
+__device__ __forceinline__ void cwc_rq_finish(const cwc_rq &q, const cwc_kparams &p, int slot,
+                                              i64 job, u32 n)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (__lane_id() == 0 && n) {
+        const u64 old = __hip_atomic_fetch_add(p.done_count, (u64)n, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        if (old + n == (u64)p.G)
+            __hip_atomic_store(q.done + slot, job, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 // ------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
 // multiplies; the key advances by the Weyl constants between rounds.

@@ -274,30 +274,28 @@ __device__ __forceinline__ void gen_observe(const GenLane &s, int *obs)
 #define G_FORM_PLAIN 0
 #define G_FORM_PERSIST 1
 #define G_FORM_SLICE 2
+#define G_FORM_ITEM 3
 
 // FORM: run to completion (plain: one trajectory per wavefront of the grid;
-// persistent: wavefronts claim trajectories from the queue) or time-sliced
-// (streamed runs and serving: wavefront w works on job wave_job[w],
-// trajectory wave_first[w], for at most `budget` draws and before the
-// slice's stop sample, resuming from and suspending to a checkpoint: the
-// term in final_term, the time, event count, digest and next sample in
-// ck_*).
+// persistent: wavefronts claim trajectories from the queue), time-sliced
+// (streamed runs and serving: the wavefront works on trajectory item0 of
+// job p for at most `budget` draws and before the slice's stop sample,
+// resuming from and suspending to a checkpoint: the term in final_term,
+// the time, event count, digest and next sample in ck_*) or one item of a
+// resident kernel (as time-sliced, to the trajectory's end, counted toward
+// the job by the caller).
 template <int FORM, bool SHARED_K>
-__device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p0, const cwc_kparams *jobs,
-                                             const int *wave_job, const long long *wave_first,
-                                             long long budget)
+__device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p, i64 item0, long long budget)
 {
+    constexpr bool SLICED = FORM == G_FORM_SLICE || FORM == G_FORM_ITEM;
     const double INF = __longlong_as_double(0x7FF0000000000000ll);
     const int lane = (int)__lane_id();
-    const i64 gw = __builtin_amdgcn_readfirstlane(
-        (int)(((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-    const cwc_kparams &p = FORM == G_FORM_SLICE ? jobs[wave_job[gw]] : p0;
     double k[G_NR > 0 ? G_NR : 1];
     if (SHARED_K) {
 #pragma unroll
         for (int r = 0; r < G_NR; ++r) k[r] = p.rates[r];
     }
-    i64 item = FORM == G_FORM_SLICE ? wave_first[gw] : gw;
+    i64 item = item0;
     for (;;) {
         if (item >= p.G) break;
         i64 lg = item;
@@ -313,7 +311,7 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p0, const cwc_kp
 #pragma unroll
             for (int r = 0; r < G_NR; ++r) k[r] = kr[r];
         }
-        const int cks = FORM == G_FORM_SLICE ? (int)p.ck_state[lg] : 0;
+        const int cks = SLICED ? (int)p.ck_state[lg] : 0;
         if (cks == 2) break;                          // already finished
         GenLane s;
         double t = 0.0, t_next = 0.0;
@@ -350,7 +348,7 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p0, const cwc_kp
         // the slice stops before this sample (streamed windows, sample
         // slices); the run-to-completion forms never stop early
         i32 kstop = 0x7FFFFFFF;
-        if (FORM == G_FORM_SLICE) {
+        if (SLICED) {
             kstop = p.k_stop;
             if (p.k_slice > 0 && (long long)kn + p.k_slice < (long long)p.k_stop)
                 kstop = kn + p.k_slice;
@@ -383,7 +381,7 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p0, const cwc_kp
     } while (0)
 
         while (st == CWC_ST_RUNNING) {
-            if (FORM == G_FORM_SLICE && n == budget) break;
+            if (SLICED && n == budget) break;
             ++n;
             // ---- Match
             GenAbove u;
@@ -461,7 +459,7 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p0, const cwc_kp
             }
         }
 #undef GEN_EMIT
-        if (FORM == G_FORM_SLICE && (st == CWC_ST_RUNNING || st == CWC_ST_WINDOW)) {
+        if (SLICED && (st == CWC_ST_RUNNING || st == CWC_ST_WINDOW)) {
             // ---- suspend: the term and the scalars back to the checkpoint
             if (lane < G_MAXC) {
                 int *row = p.final_term + (lg * G_MAXC + lane) * (i64)G_W;
@@ -495,10 +493,8 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p0, const cwc_kp
             p.status[lg] = (unsigned char)st;
             p.n_recorded[lg] = kn;
             if (p.rec_hist) atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);
-            if (FORM == G_FORM_SLICE) {
-                p.ck_state[lg] = 2;
-                atomicAdd(p.done_count, 1ull);
-            }
+            if (SLICED) p.ck_state[lg] = 2;
+            if (FORM == G_FORM_SLICE) atomicAdd(p.done_count, 1ull);
         }
         if (p.final_term && lane < G_MAXC) {
             int *row = p.final_term + (lg * G_MAXC + lane) * (i64)G_W;
@@ -518,23 +514,52 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p0, const cwc_kp
     }
 }
 
+// Resident form: wavefronts claim items (job, trajectory) from the host's
+// queue and run each to its end, until the queue is closed or stays empty.
+template <bool SHARED_K>
+__device__ __forceinline__ void cwc_gen_resident(const cwc_kparams *jobs, const cwc_rq &q)
+{
+    __shared__ cwc_kparams rq_kp[4];                  // per wavefront of the block
+    cwc_kparams &jp = rq_kp[threadIdx.x >> 6];
+    int slot;
+    i64 first, job;
+    while (cwc_rq_claim(q, slot, first, job)) {
+        cwc_rq_params(&jp, jobs + slot);
+        cwc_gen_main<G_FORM_ITEM, SHARED_K>(jp, first, 0x7FFFFFFFFFFFFFFFll);
+        cwc_rq_finish(q, jp, slot, job, first < jp.G ? 1u : 0u);
+    }
+}
+
+__device__ __forceinline__ i64 gen_global_wave()
+{
+    return __builtin_amdgcn_readfirstlane((int)(((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+}
+
 extern "C" __global__ void __launch_bounds__(256)
-cwc_gen_plain_shared(cwc_kparams p)
-{ cwc_gen_main<G_FORM_PLAIN, true>(p, nullptr, nullptr, nullptr, 0); }
+cwc_gen_plain_shared(cwc_kparams p) { cwc_gen_main<G_FORM_PLAIN, true>(p, gen_global_wave(), 0); }
 extern "C" __global__ void __launch_bounds__(256)
-cwc_gen_plain_table(cwc_kparams p)
-{ cwc_gen_main<G_FORM_PLAIN, false>(p, nullptr, nullptr, nullptr, 0); }
+cwc_gen_plain_table(cwc_kparams p) { cwc_gen_main<G_FORM_PLAIN, false>(p, gen_global_wave(), 0); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_gen_persistent_shared(cwc_kparams p)
-{ cwc_gen_main<G_FORM_PERSIST, true>(p, nullptr, nullptr, nullptr, 0); }
+{ cwc_gen_main<G_FORM_PERSIST, true>(p, gen_global_wave(), 0); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_gen_persistent_table(cwc_kparams p)
-{ cwc_gen_main<G_FORM_PERSIST, false>(p, nullptr, nullptr, nullptr, 0); }
+{ cwc_gen_main<G_FORM_PERSIST, false>(p, gen_global_wave(), 0); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_gen_slice_shared(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
                      long long budget)
-{ cwc_gen_main<G_FORM_SLICE, true>(jobs[0], jobs, wave_job, wave_first, budget); }
+{
+    const i64 gw = gen_global_wave();
+    cwc_gen_main<G_FORM_SLICE, true>(jobs[wave_job[gw]], wave_first[gw], budget);
+}
 extern "C" __global__ void __launch_bounds__(256)
 cwc_gen_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
                     long long budget)
-{ cwc_gen_main<G_FORM_SLICE, false>(jobs[0], jobs, wave_job, wave_first, budget); }
+{
+    const i64 gw = gen_global_wave();
+    cwc_gen_main<G_FORM_SLICE, false>(jobs[wave_job[gw]], wave_first[gw], budget);
+}
+extern "C" __global__ void __launch_bounds__(256)
+cwc_gen_resident_shared(const cwc_kparams *jobs, cwc_rq q) { cwc_gen_resident<true>(jobs, q); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_gen_resident_table(const cwc_kparams *jobs, cwc_rq q) { cwc_gen_resident<false>(jobs, q); }

@@ -422,53 +422,83 @@ __device__ __forceinline__ void cwc_lane_main(const cwc_kparams &p)
 // `budget` draws, then either finishes or is suspended back to its
 // checkpoint.  The counter-based random stream makes the split invisible:
 // the trajectory is identical to an uninterrupted run.
-template <bool SHARED_K>
+// Resident form (RESIDENT): the wavefront claims items (job, first
+// trajectory) from the host's queue instead, runs each to its end and
+// counts it toward its job, until the queue is closed or stays empty.
+template <bool SHARED_K, bool RESIDENT>
 __device__ __forceinline__ void cwc_lane_slice(const cwc_kparams *jobs, const int *wave_job,
-                                               const long long *wave_first, long long budget)
+                                               const long long *wave_first, long long budget,
+                                               const cwc_rq &q)
 {
     const int w = (int)((blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6);
-    const cwc_kparams &p = jobs[wave_job[w]];
+    // the resident form's LDS layout takes the queue's accumulator depth,
+    // the same for every job of the kernel
+    cwc_kparams pr{};
+    pr.nslot = q.nslot;
+    pr.k_stop = 0x7FFFFFFF;
+    const cwc_kparams &p = RESIDENT ? pr : jobs[wave_job[w]];
     CWC_LANE_LOCALS;
-    if (SHARED_K) { CWC_LOAD_K(p.rates); }
-    const i64 my = wave_first[w] + (i64)(threadIdx.x & 63);
-    bool active = my < p.G && p.ck_state[my] != 2;
-    if (active) {
-        CWC_IDENT(my, SHARED_K);
-        if (p.ck_state[my] == 0) {
-            CWC_START();
-        } else {
-            { const i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_LOAD_COUNTS(ck_); }
-            t = p.ck_t[lg];
-            e = p.ck_e[lg];
-            dig = p.ck_dig[lg];
-            kn = p.ck_kn[lg];
-            t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
-            CWC_DRAW(e, E, U);
+    // one item: trajectories first + lane of job p; returns how many of
+    // them the item finished
+    auto item = [&](const cwc_kparams &p, i64 first, long long budget) -> u32 {
+        kstop = p.k_stop;
+        if (SHARED_K) { CWC_LOAD_K(p.rates); }
+        const i64 my = first + (i64)(threadIdx.x & 63);
+        bool active = my < p.G && p.ck_state[my] != 2;
+        if (active) {
+            CWC_IDENT(my, SHARED_K);
+            if (p.ck_state[my] == 0) {
+                CWC_START();
+            } else {
+                { const i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_LOAD_COUNTS(ck_); }
+                t = p.ck_t[lg];
+                e = p.ck_e[lg];
+                dig = p.ck_dig[lg];
+                kn = p.ck_kn[lg];
+                t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
+                CWC_DRAW(e, E, U);
+            }
+            CWC_SLICE_STOP();
         }
-        CWC_SLICE_STOP();
-    }
-    long long n = 0;
-    while (__any(active)) {
-        if (!active) continue;
-        int st = CWC_ST_RUNNING;
-        CWC_STEP(st);
-        ++n;
-        if (st != CWC_ST_RUNNING && st != CWC_ST_WINDOW) {
-            CWC_FINISH(st);
-            p.ck_state[lg] = 2;
-            atomicAdd(p.done_count, 1ull);
-            active = false;
-        } else if (st == CWC_ST_WINDOW || n == budget) {
-            { i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(ck_); }
-            p.ck_t[lg] = t;
-            p.ck_e[lg] = e;
-            p.ck_dig[lg] = dig;
-            p.ck_kn[lg] = kn;
-            p.ck_state[lg] = 1;
-            active = false;
+        bool fin = false;
+        long long n = 0;
+        while (__any(active)) {
+            if (!active) continue;
+            int st = CWC_ST_RUNNING;
+            CWC_STEP(st);
+            ++n;
+            if (st != CWC_ST_RUNNING && st != CWC_ST_WINDOW) {
+                CWC_FINISH(st);
+                p.ck_state[lg] = 2;
+                if (!RESIDENT) atomicAdd(p.done_count, 1ull);
+                fin = true;
+                active = false;
+            } else if (st == CWC_ST_WINDOW || n == budget) {
+                { i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(ck_); }
+                p.ck_t[lg] = t;
+                p.ck_e[lg] = e;
+                p.ck_dig[lg] = dig;
+                p.ck_kn[lg] = kn;
+                p.ck_state[lg] = 1;
+                active = false;
+            }
         }
+        cwc_acc_flush_all(p, acc);
+        return (u32)__popcll(__ballot(fin));
+    };
+    if (!RESIDENT) {
+        item(p, wave_first[w], budget);
+        return;
     }
-    cwc_acc_flush_all(p, acc);
+    __shared__ cwc_kparams rq_kp[4];                  // per wavefront of the block
+    cwc_kparams &jp = rq_kp[threadIdx.x >> 6];
+    int slot;
+    i64 first, job;
+    while (cwc_rq_claim(q, slot, first, job)) {
+        cwc_rq_params(&jp, jobs + slot);
+        const u32 n = item(jp, first, 0x7FFFFFFFFFFFFFFFll);
+        cwc_rq_finish(q, jp, slot, job, n);
+    }
 }
 
 extern "C" __global__ void __launch_bounds__(256)
@@ -481,10 +511,18 @@ extern "C" __global__ void __launch_bounds__(256)
 cwc_lane_persistent_table(cwc_kparams p) { cwc_lane_main<true, false>(p); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_lane_slice_shared(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
-                      long long budget) { cwc_lane_slice<true>(jobs, wave_job, wave_first, budget); }
+                      long long budget)
+{ cwc_lane_slice<true, false>(jobs, wave_job, wave_first, budget, cwc_rq{}); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_lane_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
-                     long long budget) { cwc_lane_slice<false>(jobs, wave_job, wave_first, budget); }
+                     long long budget)
+{ cwc_lane_slice<false, false>(jobs, wave_job, wave_first, budget, cwc_rq{}); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_lane_resident_shared(const cwc_kparams *jobs, cwc_rq q)
+{ cwc_lane_slice<true, true>(jobs, nullptr, nullptr, 0, q); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_lane_resident_table(const cwc_kparams *jobs, cwc_rq q)
+{ cwc_lane_slice<false, true>(jobs, nullptr, nullptr, 0, q); }
 
 #ifdef CWC_PAIR
 // ------------------------------------------------------------ pair layout
@@ -703,44 +741,52 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
 // checkpoint (or starts), runs at most `budget` draws, then finishes or is
 // suspended.  The slice starts at an even iteration, so lane 0 takes the
 // draw of the current event and lane 1 receives the next one from the
-// first even iteration's pair of draws.
-template <bool SHARED_K>
+// first even iteration's pair of draws.  Resident form (RESIDENT): items
+// claimed from the host's queue, each run to its end (as the lane form).
+template <bool SHARED_K, bool RESIDENT>
 __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const int *wave_job,
-                                               const long long *wave_first, long long budget)
+                                               const long long *wave_first, long long budget,
+                                               const cwc_rq &q)
 {
     const int w = (int)((blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6);
-    const cwc_kparams &p = jobs[wave_job[w]];
+    cwc_kparams pr{};
+    pr.nslot = q.nslot;
+    pr.k_stop = 0x7FFFFFFF;
+    const cwc_kparams &p = RESIDENT ? pr : jobs[wave_job[w]];
     CWC_LANE_LOCALS;
     CWC_PAIR_DECL;
     const int h_ = (int)(__lane_id() & 1u);
-    if (SHARED_K) { CWC_PAIR_LOAD_K(p.rates, h_); }
     double Eo = 0.0, Uo = 0.0;      // draw of the next odd-iteration event
-    const i64 my = wave_first[w] + (i64)((threadIdx.x & 63) >> 1);
-    bool active = my < p.G && p.ck_state[my] != 2;
-    if (active) {
-        lg = my;
-        inst = (i64)((u32)lg / (u32)p.R);
-        g = p.g_base + lg;
-        if (!SHARED_K) {
-            const double *kr_ = p.rates + (i64)p.rate_stride * inst;
-            CWC_PAIR_LOAD_K(kr_, h_);
+    auto item = [&](const cwc_kparams &p, i64 first, long long budget) -> u32 {
+        kstop = p.k_stop;
+        if (SHARED_K) { CWC_PAIR_LOAD_K(p.rates, h_); }
+        const i64 my = first + (i64)((threadIdx.x & 63) >> 1);
+        bool active = my < p.G && p.ck_state[my] != 2;
+        if (active) {
+            lg = my;
+            inst = (i64)((u32)lg / (u32)p.R);
+            g = p.g_base + lg;
+            if (!SHARED_K) {
+                const double *kr_ = p.rates + (i64)p.rate_stride * inst;
+                CWC_PAIR_LOAD_K(kr_, h_);
+            }
+            if (p.ck_state[my] == 0) {
+                { const i32 *ini_ = p.init + (i64)p.init_stride * inst; CWC_LOAD_COUNTS(ini_); }
+                t = 0.0; t_next = 0.0; e = 0; kn = 0;
+                dig = 0xcbf29ce484222325ull;
+            } else {
+                { const i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_LOAD_COUNTS(ck_); }
+                t = p.ck_t[lg];
+                e = p.ck_e[lg];
+                dig = p.ck_dig[lg];
+                kn = p.ck_kn[lg];
+                t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
+            }
+            CWC_DRAW(e, E, U);
+            CWC_SLICE_STOP();
         }
-        if (p.ck_state[my] == 0) {
-            { const i32 *ini_ = p.init + (i64)p.init_stride * inst; CWC_LOAD_COUNTS(ini_); }
-            t = 0.0; t_next = 0.0; e = 0; kn = 0;
-            dig = 0xcbf29ce484222325ull;
-        } else {
-            { const i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_LOAD_COUNTS(ck_); }
-            t = p.ck_t[lg];
-            e = p.ck_e[lg];
-            dig = p.ck_dig[lg];
-            kn = p.ck_kn[lg];
-            t_next = (kn < p.K1) ? (double)kn * p.dt : INF;
-        }
-        CWC_DRAW(e, E, U);
-        CWC_SLICE_STOP();
-    }
-    long long n = 0;
+        bool fin = false;
+        long long n = 0;
 #define CWC_PEMIT()                                                           \
     do {                                                                      \
         if (h_ == 0) {                                                        \
@@ -758,7 +804,8 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
             if (h_ == 0) {                                                    \
                 CWC_FINISH(st);                                               \
                 p.ck_state[lg] = 2;                                           \
-                atomicAdd(p.done_count, 1ull);                                \
+                if (!RESIDENT) atomicAdd(p.done_count, 1ull);                 \
+                fin = true;                                                   \
             }                                                                 \
             active = false;                                                   \
         } else if ((st) == CWC_ST_WINDOW || n == budget) {                    \
@@ -773,24 +820,39 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
             active = false;                                                   \
         }                                                                     \
     } while (0)
-    while (__any(active)) {
-        if (active) {
-            int st = CWC_ST_RUNNING;
-            ++n;
-            CWC_PAIR_STEP_BODY(st, true);
-            CWC_PSLICE_AFTER(st);
+        while (__any(active)) {
+            if (active) {
+                int st = CWC_ST_RUNNING;
+                ++n;
+                CWC_PAIR_STEP_BODY(st, true);
+                CWC_PSLICE_AFTER(st);
+            }
+            if (!__any(active)) break;
+            if (active) {
+                int st = CWC_ST_RUNNING;
+                ++n;
+                CWC_PAIR_STEP_BODY(st, false);
+                CWC_PSLICE_AFTER(st);
+            }
         }
-        if (!__any(active)) break;
-        if (active) {
-            int st = CWC_ST_RUNNING;
-            ++n;
-            CWC_PAIR_STEP_BODY(st, false);
-            CWC_PSLICE_AFTER(st);
-        }
-    }
 #undef CWC_PSLICE_AFTER
 #undef CWC_PEMIT
-    cwc_acc_flush_all(p, acc);
+        cwc_acc_flush_all(p, acc);
+        return (u32)__popcll(__ballot(fin));
+    };
+    if (!RESIDENT) {
+        item(p, wave_first[w], budget);
+        return;
+    }
+    __shared__ cwc_kparams rq_kp[4];                  // per wavefront of the block
+    cwc_kparams &jp = rq_kp[threadIdx.x >> 6];
+    int slot;
+    i64 first, job;
+    while (cwc_rq_claim(q, slot, first, job)) {
+        cwc_rq_params(&jp, jobs + slot);
+        const u32 n = item(jp, first, 0x7FFFFFFFFFFFFFFFll);
+        cwc_rq_finish(q, jp, slot, job, n);
+    }
 }
 
 extern "C" __global__ void __launch_bounds__(256)
@@ -803,10 +865,18 @@ extern "C" __global__ void __launch_bounds__(256)
 cwc_pair_persistent_table(cwc_kparams p) { cwc_pair_main<true, false>(p); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_pair_slice_shared(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
-                      long long budget) { cwc_pair_slice<true>(jobs, wave_job, wave_first, budget); }
+                      long long budget)
+{ cwc_pair_slice<true, false>(jobs, wave_job, wave_first, budget, cwc_rq{}); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_pair_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
-                     long long budget) { cwc_pair_slice<false>(jobs, wave_job, wave_first, budget); }
+                     long long budget)
+{ cwc_pair_slice<false, false>(jobs, wave_job, wave_first, budget, cwc_rq{}); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_pair_resident_shared(const cwc_kparams *jobs, cwc_rq q)
+{ cwc_pair_slice<true, true>(jobs, nullptr, nullptr, 0, q); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_pair_resident_table(const cwc_kparams *jobs, cwc_rq q)
+{ cwc_pair_slice<false, true>(jobs, nullptr, nullptr, 0, q); }
 #endif  // CWC_PAIR
 
 #ifdef CWC_QUAD

@@ -44,21 +44,21 @@ __device__ __forceinline__ void cwc_wave_emit(const cwc_kparams &p, const i32 *c
 #define CWC_FORM_PLAIN 0
 #define CWC_FORM_PERSIST 1
 #define CWC_FORM_SLICE 2
+#define CWC_FORM_ITEM 3
 
 // FORM: run to completion (plain: one trajectory per wavefront of the grid;
-// persistent: wavefronts claim trajectories from the queue) or time-sliced
-// (serving: wavefront w works on job wave_job[w], trajectory wave_first[w],
-// for at most `budget` draws, resuming from and suspending to a checkpoint).
+// persistent: wavefronts claim trajectories from the queue), time-sliced
+// (serving: the wavefront works on trajectory item0 of job p for at most
+// `budget` draws, resuming from and suspending to a checkpoint) or one
+// item of a resident kernel (as time-sliced, to the trajectory's end,
+// counted toward the job by the caller).
 template <int FORM, bool SHARED_K>
-__device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_kparams *jobs,
-                                              const int *wave_job, const long long *wave_first,
-                                              long long budget)
+__device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p, i64 item0, long long budget)
 {
+    constexpr bool SLICED = FORM == CWC_FORM_SLICE || FORM == CWC_FORM_ITEM;
     const double INF = __longlong_as_double(0x7FF0000000000000ll);
     const int lane = (int)__lane_id();
     const int wib = (int)(threadIdx.x >> 6);
-    const i64 gw = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;   // global wave
-    const cwc_kparams &p = FORM == CWC_FORM_SLICE ? jobs[wave_job[gw]] : p0;
     __shared__ i32 stage[4 * CWC_NCELL_LANE * 64];       // [wave][cell][lane]
     i32 *const col = stage + wib * (CWC_NCELL_LANE * 64) + lane;
     const int kind = cwc_kind[lane];          // -1: no compartment
@@ -76,7 +76,7 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
         }
     }
 
-    i64 item = FORM == CWC_FORM_SLICE ? wave_first[gw] : gw;
+    i64 item = item0;
     for (;;) {
         if (item >= p.G) break;
         // ---- begin (or resume) trajectory
@@ -99,7 +99,7 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
         double t = 0.0, t_next = 0.0;
         u64 e = 0, e0 = 0, dig = 0xcbf29ce484222325ull;
         i32 kn = 0;
-        const int cks = FORM == CWC_FORM_SLICE ? (int)p.ck_state[lg] : 0;
+        const int cks = SLICED ? (int)p.ck_state[lg] : 0;
         if (cks == 2) break;                          // already finished
         if (cks == 1) {
             const i32 *ck = p.ck_counts + lg * (i64)CWC_C;
@@ -115,7 +115,7 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
         }
         // a time slice of p.k_slice sample points ends before this sample
         i32 kstop = p.k_stop;
-        if (FORM == CWC_FORM_SLICE && p.k_slice > 0 &&
+        if (SLICED && p.k_slice > 0 &&
             (long long)kn + p.k_slice < (long long)p.k_stop)
             kstop = kn + p.k_slice;
         bool have_batch = false;
@@ -138,7 +138,7 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
     } while (0)
 
         while (st == CWC_ST_RUNNING) {
-            if (FORM == CWC_FORM_SLICE && n == budget) break;
+            if (SLICED && n == budget) break;
             ++n;
             // ---- Match: leaves, subtree, butterfly over compartment blocks
             CWC_LEAVES(kind);
@@ -250,10 +250,8 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
             p.status[lg] = (unsigned char)st;
             p.n_recorded[lg] = kn;
             if (p.rec_hist) atomicAdd(p.rec_hist + inst * (i64)(p.K1 + 1) + kn, 1ull);
-            if (FORM == CWC_FORM_SLICE) {
-                p.ck_state[lg] = 2;
-                atomicAdd(p.done_count, 1ull);
-            }
+            if (SLICED) p.ck_state[lg] = 2;
+            if (FORM == CWC_FORM_SLICE) atomicAdd(p.done_count, 1ull);
         }
         if (FORM != CWC_FORM_PERSIST) break;
         u64 nxt = 0;
@@ -262,23 +260,54 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p0, const cwc_k
     }
 }
 
+// Resident form: wavefronts claim items (job, trajectory) from the host's
+// queue and run each to its end, until the queue is closed or stays empty.
+template <bool SHARED_K>
+__device__ __forceinline__ void cwc_wave_resident(const cwc_kparams *jobs, const cwc_rq &q)
+{
+    __shared__ cwc_kparams rq_kp[4];                  // per wavefront of the block
+    cwc_kparams &jp = rq_kp[threadIdx.x >> 6];
+    int slot;
+    i64 first, job;
+    while (cwc_rq_claim(q, slot, first, job)) {
+        cwc_rq_params(&jp, jobs + slot);
+        cwc_wave_main<CWC_FORM_ITEM, SHARED_K>(jp, first, 0x7FFFFFFFFFFFFFFFll);
+        cwc_rq_finish(q, jp, slot, job, first < jp.G ? 1u : 0u);
+    }
+}
+
+__device__ __forceinline__ i64 cwc_global_wave()
+{
+    return ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+}
+
 extern "C" __global__ void __launch_bounds__(256)
 cwc_wave_plain_shared(cwc_kparams p)
-{ cwc_wave_main<CWC_FORM_PLAIN, true>(p, nullptr, nullptr, nullptr, 0); }
+{ cwc_wave_main<CWC_FORM_PLAIN, true>(p, cwc_global_wave(), 0); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_wave_plain_table(cwc_kparams p)
-{ cwc_wave_main<CWC_FORM_PLAIN, false>(p, nullptr, nullptr, nullptr, 0); }
+{ cwc_wave_main<CWC_FORM_PLAIN, false>(p, cwc_global_wave(), 0); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_wave_persistent_shared(cwc_kparams p)
-{ cwc_wave_main<CWC_FORM_PERSIST, true>(p, nullptr, nullptr, nullptr, 0); }
+{ cwc_wave_main<CWC_FORM_PERSIST, true>(p, cwc_global_wave(), 0); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_wave_persistent_table(cwc_kparams p)
-{ cwc_wave_main<CWC_FORM_PERSIST, false>(p, nullptr, nullptr, nullptr, 0); }
+{ cwc_wave_main<CWC_FORM_PERSIST, false>(p, cwc_global_wave(), 0); }
 extern "C" __global__ void __launch_bounds__(256)
 cwc_wave_slice_shared(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
                       long long budget)
-{ cwc_wave_main<CWC_FORM_SLICE, true>(jobs[0], jobs, wave_job, wave_first, budget); }
+{
+    const i64 gw = cwc_global_wave();
+    cwc_wave_main<CWC_FORM_SLICE, true>(jobs[wave_job[gw]], wave_first[gw], budget);
+}
 extern "C" __global__ void __launch_bounds__(256)
 cwc_wave_slice_table(const cwc_kparams *jobs, const int *wave_job, const long long *wave_first,
                      long long budget)
-{ cwc_wave_main<CWC_FORM_SLICE, false>(jobs[0], jobs, wave_job, wave_first, budget); }
+{
+    const i64 gw = cwc_global_wave();
+    cwc_wave_main<CWC_FORM_SLICE, false>(jobs[wave_job[gw]], wave_first[gw], budget);
+}
+extern "C" __global__ void __launch_bounds__(256)
+cwc_wave_resident_shared(const cwc_kparams *jobs, cwc_rq q) { cwc_wave_resident<true>(jobs, q); }
+extern "C" __global__ void __launch_bounds__(256)
+cwc_wave_resident_table(const cwc_kparams *jobs, cwc_rq q) { cwc_wave_resident<false>(jobs, q); }

@@ -62,4 +62,21 @@ struct cwc_kparams {
     unsigned long long *done_count;  // trajectories finished so far
 };
 
+// Resident serving kernels: the queue of (job, trajectory) items that the
+// host publishes while the kernel runs, passed by value beside the job
+// table.  Items are CWC_RQ_ITEM words: job slot, first trajectory, job id,
+// unused.
+#define CWC_RQ_ITEM 4
+struct cwc_rq {
+    unsigned long long *head;   // device memory: items claimed so far
+    const long long *tail;      // coherent host memory: items published
+    const long long *items;     // coherent host memory: ring [mask + 1][CWC_RQ_ITEM]
+    const int *stop;            // coherent host memory: nonzero = claim nothing more
+    long long *done;            // coherent host memory [slots]: id of the job whose
+                                // last item has finished, by job slot
+    long long mask;             // ring entries - 1 (a power of two minus one)
+    long long idle_ticks;       // wall-clock ticks a wavefront waits for an item
+    int nslot;                  // lane layout: accumulator rows per wavefront
+};
+
 #endif

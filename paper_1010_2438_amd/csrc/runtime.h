@@ -48,13 +48,13 @@ struct cwc_model {
     int fits[3] = {0, 0, 0};            // layouts the model fits (lane, wave, general)
     std::string source[3];              // per layout, generated on demand
     hipModule_t module[3] = {nullptr, nullptr, nullptr};
-    hipFunction_t fn[3][6] = {};        // [layout][plain/persistent/slice x shared/table]
-                                        // (the general engine has no slice form)
+    hipFunction_t fn[3][8] = {};        // [layout][plain/persistent/slice/resident x
+                                        // shared/table]
     std::shared_ptr<cwc::GFlat> gen;    // general models (layout 2): the term and rules
     hipFunction_t quad_fn[4] = {};      // lane module's quad kernels (plain/persistent x
                                         // shared/table); null with fewer than four leaves
-    hipFunction_t pair_fn[6] = {};      // lane module's pair kernels (plain/persistent/
-                                        // slice x shared/table); null with one leaf
+    hipFunction_t pair_fn[8] = {};      // lane module's pair kernels (plain/persistent/
+                                        // slice/resident x shared/table); null with one leaf
     double *d_k = nullptr;              // device copies of the model's kinetic
     int *d_init = nullptr;              // constants and initial counts
     std::mutex mu;

@@ -107,6 +107,8 @@ struct Job {
     long long I = 0, R = 0, G = 0;
     int K1 = 0, C = 0, NR = 1;
     long long term_ints = 0;          // general models: the terms [G][slots][row]
+    int group = -1;                   // resident mode: the job's queue
+    long long items = 0;              // resident mode: items published for the job
     cwc_run_desc d{};
     std::vector<double> rates;
     std::vector<int> init;
@@ -148,6 +150,31 @@ double now_s(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Resident mode: the item queue of one model group (model, layout,
+// rate-table use).  Items are published into a ring in coherent host
+// memory and claimed by the group's resident kernels through a device
+// counter.
+constexpr long long kRingItems = 1ll << 18;
+struct RGroup {
+    cwc_model *m = nullptr;
+    int layout = 0;
+    bool shared_k = true;
+    bool pair = false;
+    hipFunction_t fn = nullptr;
+    long long per_wave = 64;               // trajectories per item
+    int wpb = 4;                           // wavefronts per block
+    unsigned lds = 0;
+    long long *h_items = nullptr;          // [kRingItems][CWC_RQ_ITEM], coherent host memory
+    long long *h_tail = nullptr;           // [1] items published, coherent host memory
+    long long *dv_items = nullptr;         // the kernels' addresses of the two
+    long long *dv_tail = nullptr;
+    unsigned long long *d_head = nullptr;  // [1] items claimed (device)
+    long long published = 0;
+    long long claimed = 0;                 // last value read back
+    long long done_items = 0;              // items of completed jobs
+    double t_unclaimed = -1.0;             // since when items have waited unclaimed
+};
+
 }  // namespace
 
 struct cwc_server {
@@ -183,6 +210,17 @@ struct cwc_server {
     std::vector<long long> h_wave_first[kStreams];
     hipEvent_t ev_slice[kStreams] = {};           // end of each stream's slice
     double t_slice[kStreams] = {};                 // launch time of each stream's slice
+    // resident mode (scheduler thread only, after creation): one item queue
+    // per model group; flags shared with the kernels in coherent host memory
+    std::vector<std::unique_ptr<RGroup>> groups;
+    int rkern[kStreams] = {-1, -1, -1, -1};       // group of each stream's resident kernel
+    long long rwaves[kStreams] = {};               // its wavefronts
+    int *h_stop = nullptr;                         // [1] close every queue
+    long long *h_done = nullptr;                   // [max_active] completed job ids by slot
+    int *dv_stop = nullptr;                        // the kernels' addresses of the two
+    long long *dv_done = nullptr;
+    long long idle_ticks = 0;                      // wall-clock ticks of 2 ms
+    std::vector<long long> h_head;                 // read-back buffer for claim counters
 };
 
 namespace {
@@ -384,6 +422,94 @@ bool finish_job(cwc_server *s, Job *j)
 // wavefronts per SIMD, so one model's jobs can occupy several streams.
 long long slice_wave_cap(const cwc_server *s) { return (long long)s->ctx->n_cu * 4; }
 
+// ---- resident mode
+
+// The queue of the job's model group, created on first use (scheduler
+// thread).  Lane-layout models run two lanes per trajectory where they have
+// two leaves (the shorter chain per event), else one.
+int group_of(cwc_server *s, Job *j)
+{
+    for (size_t i = 0; i < s->groups.size(); ++i) {
+        const RGroup &g = *s->groups[i];
+        if (g.m == j->m && g.layout == j->layout && g.shared_k == j->shared_k) return (int)i;
+    }
+    auto g = std::make_unique<RGroup>();
+    g->m = j->m;
+    g->layout = j->layout;
+    g->shared_k = j->shared_k;
+    g->pair = j->layout == 0 && j->m->pair_fn[6] != nullptr;
+    const int k = j->shared_k ? 6 : 7;
+    g->fn = g->pair ? j->m->pair_fn[k] : j->m->fn[j->layout][k];
+    g->per_wave = j->layout == 0 ? (g->pair ? 32 : 64) : 1;
+    g->wpb = 4;
+    while (j->layout == 0 && g->wpb > 1 &&
+           cwc_lane_lds_bytes(j->m->flat.n_cells, g->wpb, kDefaultSampleSlots) > s->ctx->max_lds)
+        g->wpb /= 2;
+    g->lds = j->layout == 0
+                 ? (unsigned)cwc_lane_lds_bytes(j->m->flat.n_cells, g->wpb, kDefaultSampleSlots)
+                 : 0u;
+    if (hipHostMalloc((void **)&g->h_items, kRingItems * CWC_RQ_ITEM * sizeof(long long),
+                      hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&g->h_tail, sizeof(long long), hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&g->dv_items, g->h_items, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&g->dv_tail, g->h_tail, 0) != hipSuccess ||
+        hipMalloc((void **)&g->d_head, sizeof(unsigned long long)) != hipSuccess ||
+        hipMemsetAsync(g->d_head, 0, sizeof(unsigned long long), s->aux) != hipSuccess ||
+        hipStreamSynchronize(s->aux) != hipSuccess) {
+        if (g->h_items) (void)hipHostFree(g->h_items);
+        if (g->h_tail) (void)hipHostFree(g->h_tail);
+        if (g->d_head) (void)hipFree(g->d_head);
+        return -1;
+    }
+    __atomic_store_n(g->h_tail, 0ll, __ATOMIC_RELEASE);
+    s->groups.push_back(std::move(g));
+    return (int)s->groups.size() - 1;
+}
+
+// Items of one admitted job: its trajectories in wavefront-sized runs,
+// written into the ring before the tail that publishes them (release: a
+// kernel that reads the tail sees the items and the job's tables).
+void publish_items(cwc_server *s, Job *j)
+{
+    RGroup &g = *s->groups[j->group];
+    long long t = g.published;
+    for (long long f = 0; f < j->G; f += g.per_wave, ++t) {
+        long long *it = g.h_items + CWC_RQ_ITEM * (t & (kRingItems - 1));
+        it[0] = j->slot;
+        it[1] = f;
+        it[2] = (long long)j->id;
+        it[3] = 0;
+    }
+    j->items = t - g.published;
+    g.published = t;
+    __atomic_store_n(g.h_tail, t, __ATOMIC_RELEASE);
+}
+
+// Launches a resident kernel of group gi with `waves` wavefronts on stream
+// si (which has nothing in flight).
+bool launch_resident(cwc_server *s, int si, int gi, long long waves)
+{
+    RGroup &g = *s->groups[gi];
+    const long long blocks = (waves + g.wpb - 1) / g.wpb;
+    cwc_rq q{};
+    q.head = g.d_head;
+    q.tail = g.dv_tail;
+    q.items = g.dv_items;
+    q.stop = s->dv_stop;
+    q.done = s->dv_done;
+    q.mask = kRingItems - 1;
+    q.idle_ticks = s->idle_ticks;
+    q.nslot = kDefaultSampleSlots;
+    void *args[] = {&s->d_jobs, &q};
+    SCHK(hipModuleLaunchKernel(g.fn, (unsigned)blocks, 1, 1, 64 * g.wpb, 1, 1, g.lds,
+                               s->streams[si], args, nullptr));
+    SCHK(hipEventRecord(s->ev_slice[si], s->streams[si]));
+    s->rkern[si] = gi;
+    s->rwaves[si] = blocks * g.wpb;
+    return true;
+}
+
 void scheduler(cwc_server *s)
 {
     if (hipSetDevice(s->ctx->device) != hipSuccess) {
@@ -395,12 +521,16 @@ void scheduler(cwc_server *s)
     std::vector<Job *> admitted;
     std::vector<Job *> inflight[kStreams];       // jobs of each stream's slice
     std::vector<Job *> ready;                    // admitted, not in a slice
+    std::vector<Job *> unpublished;              // resident: admitted, items not yet published
+    std::vector<Job *> published;                // resident: items published, not finished
     bool ok = true;
     bool stopping = false;
     double t_last = now_s(s->t0);
     for (;;) {
-        bool busy = false;
-        for (int i = 0; i < kStreams; ++i) busy = busy || !inflight[i].empty();
+        bool kernels = false;                    // slices or resident kernels in flight
+        for (int i = 0; i < kStreams; ++i) kernels = kernels || !inflight[i].empty() || s->rkern[i] >= 0;
+        const bool busy = kernels || !published.empty() || !unpublished.empty();
+        int policy = CWC_SCHED_FIFO;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             const double t = now_s(s->t0);
@@ -410,28 +540,33 @@ void scheduler(cwc_server *s)
                 s->cv.wait(lk, [&] { return s->stop || !s->queue.empty() || !ready.empty(); });
             t_last = now_s(s->t0);
             stopping = s->stop;
-            if (stopping && !busy) return;
+            policy = s->policy;
+            if (stopping && !kernels) return;
             if (stopping) {
-                // drain the slices in flight, start nothing new
+                // drain what is in flight, start nothing new; resident
+                // kernels leave once their current items end
+                __atomic_store_n(s->h_stop, 1, __ATOMIC_RELEASE);
             } else if (!s->error.empty() || !ok) {
-                if (!busy) {
+                if (!kernels) {
                     s->idle_cv.notify_all();
                     s->cv.wait(lk, [&] { return s->stop; });
                     return;
                 }
+                __atomic_store_n(s->h_stop, 1, __ATOMIC_RELEASE);
             } else {
                 // admission: FIFO, while a slot and pool memory are free
                 while (!s->queue.empty() && !s->free_slots.empty()) {
                     Job *j = s->jobs[s->queue.front()].get();
                     if (!reserve(s, j)) break;
                     j->slot = s->free_slots.back();
-                    j->k_slice = s->slice_samples;
+                    j->k_slice = policy == CWC_SCHED_RESIDENT ? 0 : s->slice_samples;
                     s->free_slots.pop_back();
                     s->queue.pop_front();
                     admitted.push_back(j);
                 }
             }
         }
+        const bool resident = policy == CWC_SCHED_RESIDENT;
         for (Job *j : admitted)
             if (ok) ok = init_job(s, j, j->slot);
         if (!admitted.empty()) {
@@ -440,13 +575,64 @@ void scheduler(cwc_server *s)
                 j->state = CWC_JOB_ACTIVE;
                 j->t_admit = now_s(s->t0);
                 s->active.push_back(j);
-                ready.push_back(j);
+                (resident ? unpublished : ready).push_back(j);
             }
             admitted.clear();
         }
-        // completions
         std::vector<Job *> finished;
         bool progressed = false;
+        if (resident && ok && !stopping) {
+            // publish admitted jobs' items in admission order while the
+            // ring has room beyond the items not yet claimed
+            size_t n_pub = 0;
+            for (Job *j : unpublished) {
+                if (j->group < 0) j->group = group_of(s, j);
+                if (j->group < 0) {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    fail_locked(s, "resident queue setup failed");
+                    ok = false;
+                    break;
+                }
+                RGroup &g = *s->groups[j->group];
+                const long long need = (j->G + g.per_wave - 1) / g.per_wave;
+                if (g.published + need - g.claimed > kRingItems) break;
+                publish_items(s, j);
+                published.push_back(j);
+                ++n_pub;
+                progressed = true;
+            }
+            unpublished.erase(unpublished.begin(), unpublished.begin() + n_pub);
+            // completions: the kernel that finished a job's last item wrote
+            // its id into the job's slot
+            for (size_t i = 0; ok && i < published.size();) {
+                Job *j = published[i];
+                if (__atomic_load_n(s->h_done + j->slot, __ATOMIC_ACQUIRE) == (long long)j->id) {
+                    if (!finish_job(s, j)) {
+                        ok = false;
+                        break;
+                    }
+                    s->groups[j->group]->done_items += j->items;
+                    finished.push_back(j);
+                    published.erase(published.begin() + i);
+                    progressed = true;
+                } else {
+                    ++i;
+                }
+            }
+        }
+        // streams whose work has ended
+        for (int i = 0; i < kStreams; ++i) {
+            if (s->rkern[i] < 0) continue;
+            const hipError_t q = hipEventQuery(s->ev_slice[i]);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                fail_locked(s, "a resident kernel failed");
+                ok = false;
+            }
+            s->rkern[i] = -1;
+            progressed = true;
+        }
         for (int i = 0; i < kStreams; ++i) {
             if (inflight[i].empty()) continue;
             const hipError_t q = hipEventQuery(s->ev_slice[i]);
@@ -496,6 +682,49 @@ void scheduler(cwc_server *s)
                 s->stats.events += j->events;
             }
         }
+        if (resident && ok && !stopping) {
+            // resident kernels: a group whose items wait unclaimed gets a
+            // kernel on a free stream, at once if it has none running, else
+            // once its items have waited a millisecond (its kernels' waves
+            // are all busy); the claim counters are read back for this
+            const double now = now_s(s->t0);
+            for (size_t gi = 0; ok && gi < s->groups.size(); ++gi) {
+                RGroup &g = *s->groups[gi];
+                if (g.published == g.claimed) continue;
+                if (hipMemcpyAsync(&s->h_head[0], g.d_head, 8, hipMemcpyDeviceToHost, s->aux) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(s->aux) != hipSuccess) {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    fail_locked(s, "claim counter read-back failed");
+                    ok = false;
+                    break;
+                }
+                g.claimed = std::max(g.claimed, std::min(s->h_head[0], g.published));
+                const long long waiting = g.published - g.claimed;
+                if (waiting == 0) {
+                    g.t_unclaimed = -1.0;
+                    continue;
+                }
+                if (g.t_unclaimed < 0) g.t_unclaimed = now;
+                int running = 0, free_si = -1;
+                for (int i = 0; i < kStreams; ++i) {
+                    running += s->rkern[i] == (int)gi;
+                    if (free_si < 0 && s->rkern[i] < 0 && inflight[i].empty()) free_si = i;
+                }
+                if (free_si < 0 || (running > 0 && now - g.t_unclaimed < 1e-3)) continue;
+                // a full share of the device, so items published while the
+                // kernel runs find idle wavefronts
+                const long long waves = slice_wave_cap(s);
+                if (!launch_resident(s, free_si, (int)gi, waves)) {
+                    ok = false;
+                    break;
+                }
+                g.t_unclaimed = now;
+                progressed = true;
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->stats.ticks += 1;
+            }
+        }
         // launches: an idle stream takes the group of the first ready job:
         // the oldest (FIFO), or under the predictive policy (paper Sec. 5.2
         // schema ii: heuristics from the instances' history) jobs without a
@@ -503,11 +732,6 @@ void scheduler(cwc_server *s)
         // result, a long one its history), then the job with the longest
         // predicted remaining time: its remaining slices times its mean slice
         // wall time so far
-        int policy = CWC_SCHED_FIFO;
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            policy = s->policy;
-        }
         if (policy == CWC_SCHED_PREDICTED && ready.size() > 1) {
             auto predicted = [](const Job *j) {
                 if (j->n_ticks == 0 || j->k_slice <= 0) return -1.0;
@@ -522,7 +746,7 @@ void scheduler(cwc_server *s)
             });
         }
         for (int i = 0; ok && !stopping && i < kStreams && !ready.empty(); ++i) {
-            if (!inflight[i].empty()) continue;
+            if (!inflight[i].empty() || s->rkern[i] >= 0) continue;
             const Job *lead = ready.front();
             std::vector<Job *> take_jobs, rest;
             long long waves = 0;
@@ -557,11 +781,11 @@ void scheduler(cwc_server *s)
             if (!ok) s->idle_cv.notify_all();
         }
         if (!progressed) {
-            // slices in flight and none finished: poll again shortly; nothing
+            // work in flight and none finished: poll again shortly; nothing
             // in flight and nothing admissible (the pool is held by finished,
             // unreleased jobs): sleep until a submission or release
-            bool any = false;
-            for (int i = 0; i < kStreams; ++i) any = any || !inflight[i].empty();
+            bool any = !published.empty() || !unpublished.empty();
+            for (int i = 0; i < kStreams; ++i) any = any || !inflight[i].empty() || s->rkern[i] >= 0;
             std::unique_lock<std::mutex> lk(s->mu);
             if (any)
                 s->cv.wait_for(lk, std::chrono::microseconds(200));
@@ -622,10 +846,34 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
     for (int i = 0; ok && i < kStreams; ++i)
         ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&s->ev_slice[i], hipEventDisableTiming) == hipSuccess;
+    // resident mode's flags in coherent host memory; a resident wavefront
+    // gives up waiting for items after 2 ms of the device's wall clock
+    int khz = 0;
+    ok = ok &&
+         hipHostMalloc((void **)&s->h_stop, sizeof(int), hipHostMallocCoherent) == hipSuccess &&
+         hipHostMalloc((void **)&s->h_done, sizeof(long long) * max_active,
+                       hipHostMallocCoherent) == hipSuccess &&
+         hipHostGetDevicePointer((void **)&s->dv_stop, s->h_stop, 0) == hipSuccess &&
+         hipHostGetDevicePointer((void **)&s->dv_done, s->h_done, 0) == hipSuccess &&
+         hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) == hipSuccess &&
+         khz > 0;
     if (!ok) {
+        for (int i = 0; i < kStreams; ++i) {
+            if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
+            if (s->ev_slice[i]) (void)hipEventDestroy(s->ev_slice[i]);
+        }
+        if (s->aux) (void)hipStreamDestroy(s->aux);
+        if (s->d_jobs) (void)hipFree(s->d_jobs);
+        if (s->d_done) (void)hipFree(s->d_done);
+        if (s->h_stop) (void)hipHostFree(s->h_stop);
+        if (s->h_done) (void)hipHostFree(s->h_done);
         ctx->release(s->pool_mem);
         return set_err(CWC_E_DEVICE, "server device setup failed");
     }
+    *s->h_stop = 0;
+    for (int i = 0; i < max_active; ++i) s->h_done[i] = 0;
+    s->idle_ticks = 10ll * khz;
+    s->h_head.assign(1, 0);
     for (int i = max_active - 1; i >= 0; --i) s->free_slots.push_back(i);
     s->stats.pool_bytes = (int64_t)s->pool.bytes;
     s->t0 = std::chrono::steady_clock::now();
@@ -640,9 +888,13 @@ cwc_status cwc_server_set_policy(cwc_server *s, int32_t slice_samples, int32_t p
 {
     if (!s) return set_err(CWC_E_INVALID, "null server");
     if (slice_samples < 0) return set_err(CWC_E_INVALID, "slice_samples must be >= 0");
-    if (policy != CWC_SCHED_FIFO && policy != CWC_SCHED_PREDICTED)
+    if (policy != CWC_SCHED_FIFO && policy != CWC_SCHED_PREDICTED && policy != CWC_SCHED_RESIDENT)
         return set_err(CWC_E_INVALID, "unknown scheduling policy %d", policy);
     std::lock_guard<std::mutex> lk(s->mu);
+    if ((policy == CWC_SCHED_RESIDENT) != (s->policy == CWC_SCHED_RESIDENT) &&
+        (!s->queue.empty() || !s->active.empty()))
+        return set_err(CWC_E_INVALID, "switching to or from the resident policy needs a server "
+                                      "with no queued or active job");
     s->slice_samples = slice_samples;
     s->policy = policy;
     return CWC_OK;
@@ -678,6 +930,10 @@ cwc_status cwc_server_submit(cwc_server *s, const cwc_model *m, const cwc_run_de
         return set_err(CWC_E_NOMEM, "job needs %zu bytes, the server pool has %zu", job_bytes(*j),
                        s->pool.bytes);
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->policy == CWC_SCHED_RESIDENT && j->G > kRingItems * (j->layout == 0 ? 32 : 1))
+        return set_err(CWC_E_UNSUPPORTED, "a resident-policy job takes at most %lld items (%lld "
+                                          "trajectories)", kRingItems,
+                       kRingItems * (j->layout == 0 ? 32 : 1));
     if (!s->error.empty()) return set_err(CWC_E_DEVICE, "server failed: %s", s->error.c_str());
     j->id = s->next_id++;
     j->t_submit = now_s(s->t0);
@@ -844,6 +1100,13 @@ void cwc_server_destroy(cwc_server *s)
     if (s->aux) (void)hipStreamDestroy(s->aux);
     if (s->d_jobs) (void)hipFree(s->d_jobs);
     if (s->d_done) (void)hipFree(s->d_done);
+    for (auto &g : s->groups) {
+        (void)hipHostFree(g->h_items);
+        (void)hipHostFree(g->h_tail);
+        (void)hipFree(g->d_head);
+    }
+    if (s->h_stop) (void)hipHostFree(s->h_stop);
+    if (s->h_done) (void)hipHostFree(s->h_done);
     cwc_ctx *ctx = s->ctx;
     ctx->release(s->pool_mem);
     delete s;

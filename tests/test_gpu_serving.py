@@ -47,13 +47,17 @@ def same_stats(a, b):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("slice_samples,predicted", [(0, False), (3, True), (5, False)])
-def test_alone_vs_mix(ctx, slice_samples, predicted):
+@pytest.mark.parametrize("slice_samples,predicted,resident",
+                         [(0, False, False), (3, True, False), (5, False, False),
+                          (0, False, True)])
+def test_alone_vs_mix(ctx, slice_samples, predicted, resident):
     """Every job of the mix equals the job run alone, with slices bounded by
-    draws only, and with slices of a few sample points (constant simulation
-    time) under the predictive and the FIFO dispatch order."""
+    draws only, with slices of a few sample points (constant simulation
+    time) under the predictive and the FIFO dispatch order, and with
+    resident kernels draining per-model queues of items."""
     from paper_1010_2438_amd import Model, Server
-    print("case serving mix slice_samples", slice_samples, "predicted", predicted, flush=True)
+    print("case serving mix slice_samples", slice_samples, "predicted", predicted,
+          "resident", resident, flush=True)
     specs = job_specs()
     models = {}
     for m, _ in specs:
@@ -68,7 +72,7 @@ def test_alone_vs_mix(ctx, slice_samples, predicted):
     compare_trajectories(alone[0], orc)
     # the mix: every job admitted at once, sliced every 997 draws
     srv = Server(ctx, hbm_budget=256 << 20, max_active=16, slice_events=997)
-    srv.set_policy(slice_samples, predicted)
+    srv.set_policy(slice_samples, predicted, resident)
     ids = [srv.submit(models[repr(m)], run, want_digest=True) for m, run in specs]
     srv.wait_idle(300)
     done = set(srv.poll())
@@ -82,7 +86,8 @@ def test_alone_vs_mix(ctx, slice_samples, predicted):
         assert same_float(c["t_final"], g["t_final"])
         same_stats(srv.stats(jid), (g["mean"], g["var"], g["n"]))
         assert info["events"] == int(g["events"].sum())
-    assert max(srv.info(j)["n_ticks"] for j in ids) > 3     # really sliced
+    if not resident:
+        assert max(srv.info(j)["n_ticks"] for j in ids) > 3     # really sliced
     if slice_samples:
         # a job of K+1 sample points needs at least ceil((K+1) / slice) slices
         for jid, (m, run) in zip(ids, specs):
@@ -96,15 +101,16 @@ def test_alone_vs_mix(ctx, slice_samples, predicted):
     srv.close()
 
 
-@pytest.mark.parametrize("slice_samples,predicted", [(0, False), (4, True)])
-def test_general_jobs_in_mix(ctx, slice_samples, predicted):
+@pytest.mark.parametrize("slice_samples,predicted,resident",
+                         [(0, False, False), (4, True, False), (0, False, True)])
+def test_general_jobs_in_mix(ctx, slice_samples, predicted, resident):
     """General models (compartments created, dissolved, deleted) served
     beside a fixed-tree job: each job's counters, statistics and final terms
     equal the job run alone, with the terms checkpointed between slices; one
     job is also checked against the general oracle."""
     from paper_1010_2438_amd import CwcError, GModel, Model, Run, Server
     print("case serving general mix slice_samples", slice_samples, "predicted", predicted,
-          flush=True)
+          "resident", resident, flush=True)
     colony = W.cell_colony(n0=4, nutrient=300, max_comp=24)
     tab = np.tile(np.array([r["k"] for r in colony["rules"]]), (3, 1)) * \
         np.array([0.5, 1.0, 2.0])[:, None]
@@ -137,7 +143,7 @@ def test_general_jobs_in_mix(ctx, slice_samples, predicted):
     lv = Model(ctx, W.lotka_volterra())
     lv_run = W.make_run(seed=35, replicas=100, dt=0.05, n_samples=21)
     srv = Server(ctx, hbm_budget=256 << 20, max_active=16, slice_events=97)
-    srv.set_policy(slice_samples, predicted)
+    srv.set_policy(slice_samples, predicted, resident)
     ids = [srv.submit(gms[repr(m)], run, want_digest=True) for m, run in specs]
     lv_id = srv.submit(lv, lv_run)
     srv.wait_idle(300)
@@ -149,7 +155,8 @@ def test_general_jobs_in_mix(ctx, slice_samples, predicted):
         assert same_float(c["t_final"], g["t_final"])
         same_stats(srv.stats(jid), g["stats"])
         assert np.array_equal(srv.term(jid), g["term"]), jid
-    assert max(srv.info(j)["n_ticks"] for j in ids) > 3     # really sliced
+    if not resident:
+        assert max(srv.info(j)["n_ticks"] for j in ids) > 3     # really sliced
     with pytest.raises(CwcError):
         srv.term(lv_id)                                     # a fixed-tree job has no term
     for j in ids + [lv_id]:
@@ -160,16 +167,20 @@ def test_general_jobs_in_mix(ctx, slice_samples, predicted):
         gm.close()
 
 
-def test_admission_within_budget(ctx):
+@pytest.mark.parametrize("resident", [False, True])
+def test_admission_within_budget(ctx, resident):
     """A pool that holds two jobs at a time: the client fetches and releases
     finished jobs, queued jobs are admitted FIFO as memory frees up, the pool
-    never overflows, and results match a solo run."""
+    never overflows, and results match a solo run (resident: the job slots
+    and pool memory of released jobs are reused while the kernels stay)."""
     import time
     from paper_1010_2438_amd import Model, Server
+    print("case serving admission resident", resident, flush=True)
     m = W.gene_regulation(1)
     mo = Model(ctx, m)
     runs = [W.make_run(seed=100 + i, replicas=20000, dt=0.5, n_samples=11) for i in range(6)]
     srv = Server(ctx, hbm_budget=10 << 20, max_active=8, slice_events=2048)
+    srv.set_policy(0, False, resident)
     ids = [srv.submit(mo, r) for r in runs]
     kept, infos = {}, {}
     t0 = time.time()
@@ -192,6 +203,41 @@ def test_admission_within_budget(ctx):
     solo = gpu_run(ctx, mo, runs[4], mode="plain", want_traj=False)
     assert np.array_equal(kept["final_counts"], solo["final_counts"])
     assert np.array_equal(kept["events"], solo["events"])
+    srv.close()
+
+
+def test_resident_slot_reuse_and_policy_switch(ctx):
+    """Resident kernels with one job slot: every job reuses the slot (and
+    the parameters the kernels copy from it) while the kernels may stay on
+    the device; each result equals the job run alone.  The policy can change
+    to or from resident only while no job is queued or active."""
+    import time
+    from paper_1010_2438_amd import CwcError, Model, Server
+    print("case serving resident slot reuse", flush=True)
+    m = W.lotka_volterra()
+    mo = Model(ctx, m)
+    runs = [W.make_run(seed=200 + i, replicas=64 * (i + 1), dt=0.05, n_samples=21,
+                       count_cap=100000) for i in range(5)]
+    srv = Server(ctx, hbm_budget=64 << 20, max_active=1, slice_events=4096)
+    srv.set_policy(0, False, True)
+    ids = [srv.submit(mo, r, want_digest=True) for r in runs]
+    with pytest.raises(CwcError):
+        srv.set_policy(0, False, False)            # jobs queued: no switch
+    got, t0 = {}, time.time()
+    while len(got) < len(ids) and time.time() - t0 < 120:
+        for j in srv.poll():
+            got[j] = (srv.counters(j), srv.stats(j))
+            srv.release(j)
+        time.sleep(0.002)
+    assert set(got) == set(ids)
+    for jid, run in zip(ids, runs):
+        g = gpu_run(ctx, mo, run, mode="plain", want_traj=False, want_digest=True)
+        c, st = got[jid]
+        for key in ("events", "status", "digest", "n_recorded", "final_counts"):
+            assert np.array_equal(c[key], g[key]), (jid, key)
+        assert same_float(c["t_final"], g["t_final"])
+        same_stats(st, (g["mean"], g["var"], g["n"]))
+    srv.set_policy(0, False, False)                # idle: the switch is allowed
     srv.close()
 
 
