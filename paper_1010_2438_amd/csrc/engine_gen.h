@@ -407,14 +407,16 @@ __device__ __forceinline__ void cwc_gen_main(const cwc_kparams &p, i64 item0, lo
                 Ub = cwc_u_open1(x2, x3);
             }
             const int di = (int)(e - e0);
+            // (the stop sample exists in the sliced forms only: the
+            // run-to-completion forms keep the loops without it)
             if (a0 == 0.0) {
-                while (kn < p.K1 && kn < kstop) GEN_EMIT();
+                while (kn < p.K1 && (!SLICED || kn < kstop)) GEN_EMIT();
                 st = kn < p.K1 ? CWC_ST_WINDOW : CWC_ST_ABSORBED;
                 break;
             }
             const double tn = t + cwc_rl(Eb, di) / a0;
-            while (t_next < tn && kn < kstop) GEN_EMIT();
-            if (t_next < tn) {
+            while (t_next < tn && (!SLICED || kn < kstop)) GEN_EMIT();
+            if (SLICED && t_next < tn) {
                 st = CWC_ST_WINDOW;     // the slice's last sample is done
                 break;
             }

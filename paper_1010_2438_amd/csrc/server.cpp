@@ -42,6 +42,10 @@ using namespace cwc;
 namespace {
 
 constexpr int kStreams = 4;
+// resident mode: streams for resident kernels, created on first use; every
+// stream should have a hardware queue of its own (GPU_MAX_HW_QUEUES), since
+// a resident kernel holds its queue until it leaves
+constexpr int kRStreams = 8;
 // launches of at most this many trajectories use two lanes per trajectory
 constexpr long long kPairSliceMax = 32768;
 
@@ -213,8 +217,9 @@ struct cwc_server {
     // resident mode (scheduler thread only, after creation): one item queue
     // per model group; flags shared with the kernels in coherent host memory
     std::vector<std::unique_ptr<RGroup>> groups;
-    int rkern[kStreams] = {-1, -1, -1, -1};       // group of each stream's resident kernel
-    long long rwaves[kStreams] = {};               // its wavefronts
+    hipStream_t rstreams[kRStreams] = {};          // resident kernels' streams
+    hipEvent_t ev_res[kRStreams] = {};             // end of each stream's kernel
+    int rkern[kRStreams] = {-1, -1, -1, -1, -1, -1, -1, -1};  // group of each stream's kernel
     int *h_stop = nullptr;                         // [1] close every queue
     long long *h_done = nullptr;                   // [max_active] completed job ids by slot
     int *dv_stop = nullptr;                        // the kernels' addresses of the two
@@ -502,11 +507,14 @@ bool launch_resident(cwc_server *s, int si, int gi, long long waves)
     q.idle_ticks = s->idle_ticks;
     q.nslot = kDefaultSampleSlots;
     void *args[] = {&s->d_jobs, &q};
+    if (!s->rstreams[si]) {
+        SCHK(hipStreamCreateWithFlags(&s->rstreams[si], hipStreamNonBlocking));
+        SCHK(hipEventCreateWithFlags(&s->ev_res[si], hipEventDisableTiming));
+    }
     SCHK(hipModuleLaunchKernel(g.fn, (unsigned)blocks, 1, 1, 64 * g.wpb, 1, 1, g.lds,
-                               s->streams[si], args, nullptr));
-    SCHK(hipEventRecord(s->ev_slice[si], s->streams[si]));
+                               s->rstreams[si], args, nullptr));
+    SCHK(hipEventRecord(s->ev_res[si], s->rstreams[si]));
     s->rkern[si] = gi;
-    s->rwaves[si] = blocks * g.wpb;
     return true;
 }
 
@@ -528,7 +536,8 @@ void scheduler(cwc_server *s)
     double t_last = now_s(s->t0);
     for (;;) {
         bool kernels = false;                    // slices or resident kernels in flight
-        for (int i = 0; i < kStreams; ++i) kernels = kernels || !inflight[i].empty() || s->rkern[i] >= 0;
+        for (int i = 0; i < kStreams; ++i) kernels = kernels || !inflight[i].empty();
+        for (int i = 0; i < kRStreams; ++i) kernels = kernels || s->rkern[i] >= 0;
         const bool busy = kernels || !published.empty() || !unpublished.empty();
         int policy = CWC_SCHED_FIFO;
         {
@@ -620,10 +629,10 @@ void scheduler(cwc_server *s)
                 }
             }
         }
-        // streams whose work has ended
-        for (int i = 0; i < kStreams; ++i) {
+        // resident kernels that have ended
+        for (int i = 0; i < kRStreams; ++i) {
             if (s->rkern[i] < 0) continue;
-            const hipError_t q = hipEventQuery(s->ev_slice[i]);
+            const hipError_t q = hipEventQuery(s->ev_res[i]);
             if (q == hipErrorNotReady) continue;
             if (q != hipSuccess) {
                 std::lock_guard<std::mutex> lk(s->mu);
@@ -685,8 +694,8 @@ void scheduler(cwc_server *s)
         if (resident && ok && !stopping) {
             // resident kernels: a group whose items wait unclaimed gets a
             // kernel on a free stream, at once if it has none running, else
-            // once its items have waited a millisecond (its kernels' waves
-            // are all busy); the claim counters are read back for this
+            // once its items have waited 0.2 ms (its kernels' wavefronts are
+            // all busy or gone); the claim counters are read back for this
             const double now = now_s(s->t0);
             for (size_t gi = 0; ok && gi < s->groups.size(); ++gi) {
                 RGroup &g = *s->groups[gi];
@@ -707,14 +716,12 @@ void scheduler(cwc_server *s)
                 }
                 if (g.t_unclaimed < 0) g.t_unclaimed = now;
                 int running = 0, free_si = -1;
-                for (int i = 0; i < kStreams; ++i) {
+                for (int i = 0; i < kRStreams; ++i) {
                     running += s->rkern[i] == (int)gi;
-                    if (free_si < 0 && s->rkern[i] < 0 && inflight[i].empty()) free_si = i;
+                    if (free_si < 0 && s->rkern[i] < 0) free_si = i;
                 }
-                if (free_si < 0 || (running > 0 && now - g.t_unclaimed < 1e-3)) continue;
-                // a full share of the device, so items published while the
-                // kernel runs find idle wavefronts
-                const long long waves = slice_wave_cap(s);
+                if (free_si < 0 || (running > 0 && now - g.t_unclaimed < 2e-4)) continue;
+                const long long waves = std::min(waiting, slice_wave_cap(s));
                 if (!launch_resident(s, free_si, (int)gi, waves)) {
                     ok = false;
                     break;
@@ -746,7 +753,7 @@ void scheduler(cwc_server *s)
             });
         }
         for (int i = 0; ok && !stopping && i < kStreams && !ready.empty(); ++i) {
-            if (!inflight[i].empty() || s->rkern[i] >= 0) continue;
+            if (!inflight[i].empty()) continue;
             const Job *lead = ready.front();
             std::vector<Job *> take_jobs, rest;
             long long waves = 0;
@@ -785,7 +792,8 @@ void scheduler(cwc_server *s)
             // in flight and nothing admissible (the pool is held by finished,
             // unreleased jobs): sleep until a submission or release
             bool any = !published.empty() || !unpublished.empty();
-            for (int i = 0; i < kStreams; ++i) any = any || !inflight[i].empty() || s->rkern[i] >= 0;
+            for (int i = 0; i < kStreams; ++i) any = any || !inflight[i].empty();
+            for (int i = 0; i < kRStreams; ++i) any = any || s->rkern[i] >= 0;
             std::unique_lock<std::mutex> lk(s->mu);
             if (any)
                 s->cv.wait_for(lk, std::chrono::microseconds(200));
@@ -872,7 +880,7 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
     }
     *s->h_stop = 0;
     for (int i = 0; i < max_active; ++i) s->h_done[i] = 0;
-    s->idle_ticks = 10ll * khz;
+    s->idle_ticks = 2ll * khz;
     s->h_head.assign(1, 0);
     for (int i = max_active - 1; i >= 0; --i) s->free_slots.push_back(i);
     s->stats.pool_bytes = (int64_t)s->pool.bytes;
@@ -1096,6 +1104,13 @@ void cwc_server_destroy(cwc_server *s)
         if (s->d_wave_job[i]) (void)hipFree(s->d_wave_job[i]);
         if (s->d_wave_first[i]) (void)hipFree(s->d_wave_first[i]);
         if (s->ev_slice[i]) (void)hipEventDestroy(s->ev_slice[i]);
+    }
+    for (int i = 0; i < kRStreams; ++i) {
+        if (s->rstreams[i]) {
+            (void)hipStreamSynchronize(s->rstreams[i]);
+            (void)hipStreamDestroy(s->rstreams[i]);
+        }
+        if (s->ev_res[i]) (void)hipEventDestroy(s->ev_res[i]);
     }
     if (s->aux) (void)hipStreamDestroy(s->aux);
     if (s->d_jobs) (void)hipFree(s->d_jobs);
