@@ -112,7 +112,6 @@ struct Job {
     int K1 = 0, C = 0, NR = 1;
     long long term_ints = 0;          // general models: the terms [G][slots][row]
     int group = -1;                   // resident mode: the job's queue
-    long long items = 0;              // resident mode: items published for the job
     cwc_run_desc d{};
     std::vector<double> rates;
     std::vector<int> init;
@@ -175,7 +174,6 @@ struct RGroup {
     unsigned long long *d_head = nullptr;  // [1] items claimed (device)
     long long published = 0;
     long long claimed = 0;                 // last value read back
-    long long done_items = 0;              // items of completed jobs
     double t_unclaimed = -1.0;             // since when items have waited unclaimed
 };
 
@@ -486,7 +484,6 @@ void publish_items(cwc_server *s, Job *j)
         it[2] = (long long)j->id;
         it[3] = 0;
     }
-    j->items = t - g.published;
     g.published = t;
     __atomic_store_n(g.h_tail, t, __ATOMIC_RELEASE);
 }
@@ -620,7 +617,6 @@ void scheduler(cwc_server *s)
                         ok = false;
                         break;
                     }
-                    s->groups[j->group]->done_items += j->items;
                     finished.push_back(j);
                     published.erase(published.begin() + i);
                     progressed = true;
