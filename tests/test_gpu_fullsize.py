@@ -6,7 +6,8 @@ counts, events, statuses, fired-leaf digests, final times, every recorded
 sample), checks every sample of every trajectory against the model's
 conservation laws and every moment against the exact integer sums of the
 fetched samples, and runs the benchmark's other launches of the same
-workload against the first, bit for bit, trajectory by trajectory."""
+workload against the first, bit for bit, trajectory by trajectory; the
+general-term colony is compared in full with the general oracle."""
 import numpy as np
 import pytest
 
@@ -140,3 +141,34 @@ def test_multi_compartment_full_size_benchmark_launch(ctx):
     ids = np.linspace(0, R - 1, 128).astype(np.int64)
     compare_trajectories(g, oracle_ids(m, run, ids), g_index=ids)
     check_moments_and_laws(m, g, 1, R, K1)
+
+
+def test_cell_colony_full_size_benchmark_launch(ctx):
+    """The general-term cell colony (compartments created and deleted at run
+    time; 2048 replicas, t_end 100, 201 samples) in the benchmark's
+    persistent launch (one wavefront per trajectory, block 256, 8 requested
+    waves per SIMD: the queue-free general kernel): every trajectory against
+    the general oracle bit for bit (events, statuses, fired-leaf digests,
+    final times, final observables, whole final terms) and the exact
+    moments equal."""
+    from bench import general_workload
+    from paper_1010_2438_amd import GModel, Run
+    from tests.gpu_common import RESULT_KEYS, compare_stats, same_float
+    m, run = general_workload()
+    gm = GModel(ctx, m)
+    print("case cell colony full size, persistent general", flush=True)
+    r = Run(ctx, gm, run, mode="persistent", tuning=LAUNCH[5], want_digest=True)
+    assert r.kernel_name() == "cwc_gen_plain_shared"
+    r.wait()
+    g = r.counters()
+    g["s1"], g["s2_hi32"], g["s2_lo32"], _ = r.moments()
+    g["mean"], g["var"], g["n"] = r.stats()
+    g["term"] = r.term()
+    r.close()
+    gm.close()
+    orc = oracle.gsimulate(m, run, want_term=True, threads=16)
+    for key in RESULT_KEYS:
+        assert np.array_equal(g[key], orc[key]), key
+    assert same_float(g["t_final"], orc["t_final"])
+    assert np.array_equal(g["term"], orc["term"])
+    compare_stats(g, orc)
