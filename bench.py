@@ -32,12 +32,6 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# More hardware queues than HIP's default of four (read when HIP starts):
-# the serving replay keeps up to five streams busy at once (four slice
-# streams and the per-job set-up and finalisation stream), and streams that
-# share a hardware queue run one after another.  A setting in the
-# environment wins.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "SSA events/sec on 1 GPU (batched persistent vs plain launch); p99 job latency"
 PEAK_VALU_SLOTS = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock = 3.93e13/s

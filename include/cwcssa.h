@@ -596,9 +596,8 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
  * launched when items wait unclaimed -- keep claiming items and running
  * them to their end while new jobs arrive; a kernel's wavefront leaves
  * after 2 ms without an item, and the kernel that completes a job's last
- * item reports the job's id to the host.  A resident kernel holds its
- * stream's hardware queue while it runs: give the process at least 16
- * (GPU_MAX_HW_QUEUES) so that the streams do not share them.  slice_events and slice_samples do not apply;
+ * item reports the job's id to the host.  (Every stream of the server,
+ * slice and resident, has a hardware queue of its own.)  slice_events and slice_samples do not apply;
  * a job takes at most 2^18 items (wavefront-sized runs of trajectories).
  * The switch to or from CWC_SCHED_RESIDENT needs a server with no queued
  * or active job.  Results never depend on the policy.  Errors:

@@ -42,9 +42,9 @@ using namespace cwc;
 namespace {
 
 constexpr int kStreams = 4;
-// resident mode: streams for resident kernels, created on first use; every
-// stream should have a hardware queue of its own (GPU_MAX_HW_QUEUES), since
-// a resident kernel holds its queue until it leaves
+// resident mode: streams for resident kernels, created on first use (each,
+// like every stream of the server, with a hardware queue of its own, since
+// a resident kernel holds its queue until it leaves)
 constexpr int kRStreams = 8;
 // launches of at most this many trajectories use two lanes per trajectory
 constexpr long long kPairSliceMax = 32768;
@@ -421,6 +421,18 @@ bool finish_job(cwc_server *s, Job *j)
     return true;
 }
 
+// A stream with a hardware queue of its own: created with a compute-unit
+// mask (every unit of the device), which the runtime serves from a queue of
+// its own instead of one shared round-robin with the process's other
+// streams, so a long kernel on one of the server's streams (a resident
+// kernel, a long slice) never holds up the others' work behind it.
+bool own_queue_stream(cwc_ctx *ctx, hipStream_t *st)
+{
+    std::vector<uint32_t> mask((size_t)(ctx->n_cu + 31) / 32, 0u);
+    for (int c = 0; c < ctx->n_cu; ++c) mask[c / 32] |= 1u << (c % 32);
+    return hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data()) == hipSuccess;
+}
+
 // Wavefronts one slice launch may cover: about half the device at two
 // wavefronts per SIMD, so one model's jobs can occupy several streams.
 long long slice_wave_cap(const cwc_server *s) { return (long long)s->ctx->n_cu * 4; }
@@ -505,7 +517,11 @@ bool launch_resident(cwc_server *s, int si, int gi, long long waves)
     q.nslot = kDefaultSampleSlots;
     void *args[] = {&s->d_jobs, &q};
     if (!s->rstreams[si]) {
-        SCHK(hipStreamCreateWithFlags(&s->rstreams[si], hipStreamNonBlocking));
+        if (!own_queue_stream(s->ctx, &s->rstreams[si])) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            fail_locked(s, "resident stream creation failed");
+            return false;
+        }
         SCHK(hipEventCreateWithFlags(&s->ev_res[si], hipEventDisableTiming));
     }
     SCHK(hipModuleLaunchKernel(g.fn, (unsigned)blocks, 1, 1, 64 * g.wpb, 1, 1, g.lds,
@@ -846,9 +862,9 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
     s->pool.init(s->pool_mem, hbm_budget);
     bool ok = hipMalloc(&s->d_jobs, sizeof(cwc_kparams) * max_active) == hipSuccess &&
               hipMalloc(&s->d_done, 8 * max_active) == hipSuccess &&
-              hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) == hipSuccess;
+              own_queue_stream(ctx, &s->aux);
     for (int i = 0; ok && i < kStreams; ++i)
-        ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess &&
+        ok = own_queue_stream(ctx, &s->streams[i]) &&
              hipEventCreateWithFlags(&s->ev_slice[i], hipEventDisableTiming) == hipSuccess;
     // resident mode's flags in coherent host memory; a resident wavefront
     // gives up waiting for items after 2 ms of the device's wall clock
