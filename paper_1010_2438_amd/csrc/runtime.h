@@ -136,5 +136,11 @@ cwc_status compile_source(const std::string &src, const std::string &arch,
                           std::vector<char> *code);
 std::string model_source(const Flat &f, int layout);
 std::string gmodel_source(const GFlat &g);
+// A non-blocking stream with a hardware queue of its own (created with a
+// compute-unit mask covering the whole device, which the runtime serves
+// from a queue of its own instead of one shared round-robin with the
+// process's other streams): work on it never waits behind a long kernel
+// on another stream.
+bool own_queue_stream(cwc_ctx *ctx, hipStream_t *st);
 }  // namespace cwc
 #endif

@@ -205,6 +205,8 @@ struct cwc_server {
     unsigned long long *d_done = nullptr;    // [max_active]
     hipStream_t streams[kStreams] = {};
     hipStream_t aux = nullptr;
+    hipStream_t fetch = nullptr;             // result copies of client calls
+    std::mutex fetch_mu;                     // one client copy at a time on it
     int *d_wave_job[kStreams] = {};
     long long *d_wave_first[kStreams] = {};
     size_t wave_cap[kStreams] = {};
@@ -419,18 +421,6 @@ bool finish_job(cwc_server *s, Job *j)
     for (long long v : ev) tot += v;
     j->events = tot;
     return true;
-}
-
-// A stream with a hardware queue of its own: created with a compute-unit
-// mask (every unit of the device), which the runtime serves from a queue of
-// its own instead of one shared round-robin with the process's other
-// streams, so a long kernel on one of the server's streams (a resident
-// kernel, a long slice) never holds up the others' work behind it.
-bool own_queue_stream(cwc_ctx *ctx, hipStream_t *st)
-{
-    std::vector<uint32_t> mask((size_t)(ctx->n_cu + 31) / 32, 0u);
-    for (int c = 0; c < ctx->n_cu; ++c) mask[c / 32] |= 1u << (c % 32);
-    return hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data()) == hipSuccess;
 }
 
 // Wavefronts one slice launch may cover: about half the device at two
@@ -862,7 +852,7 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
     s->pool.init(s->pool_mem, hbm_budget);
     bool ok = hipMalloc(&s->d_jobs, sizeof(cwc_kparams) * max_active) == hipSuccess &&
               hipMalloc(&s->d_done, 8 * max_active) == hipSuccess &&
-              own_queue_stream(ctx, &s->aux);
+              own_queue_stream(ctx, &s->aux) && own_queue_stream(ctx, &s->fetch);
     for (int i = 0; ok && i < kStreams; ++i)
         ok = own_queue_stream(ctx, &s->streams[i]) &&
              hipEventCreateWithFlags(&s->ev_slice[i], hipEventDisableTiming) == hipSuccess;
@@ -883,6 +873,7 @@ cwc_status cwc_server_create(cwc_ctx *ctx, size_t hbm_budget, int32_t max_active
             if (s->ev_slice[i]) (void)hipEventDestroy(s->ev_slice[i]);
         }
         if (s->aux) (void)hipStreamDestroy(s->aux);
+        if (s->fetch) (void)hipStreamDestroy(s->fetch);
         if (s->d_jobs) (void)hipFree(s->d_jobs);
         if (s->d_done) (void)hipFree(s->d_done);
         if (s->h_stop) (void)hipHostFree(s->h_stop);
@@ -1006,13 +997,11 @@ cwc_status cwc_server_fetch_stats(cwc_server *s, uint64_t job, double *mean, dou
     }
     if (!j) return st;
     const size_t mom = (size_t)j->I * j->K1 * j->C;
-    hipStream_t a;
-    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess)
-        return set_err(CWC_E_DEVICE, "stream");
+    std::lock_guard<std::mutex> fk(s->fetch_mu);
+    hipStream_t a = s->fetch;
     if ((st = copy_out(mean, j->mean, mom * 8, dst_is_device, a)) == CWC_OK &&
         (st = copy_out(var, j->var, mom * 8, dst_is_device, a)) == CWC_OK)
         st = copy_out(n, j->nk, (size_t)j->I * j->K1 * 8, dst_is_device, a);
-    (void)hipStreamDestroy(a);
     return st;
 }
 
@@ -1030,9 +1019,8 @@ cwc_status cwc_server_fetch_counters(cwc_server *s, uint64_t job, int64_t *event
     }
     if (!j) return st;
     const size_t G = (size_t)j->G;
-    hipStream_t a;
-    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess)
-        return set_err(CWC_E_DEVICE, "stream");
+    std::lock_guard<std::mutex> fk(s->fetch_mu);
+    hipStream_t a = s->fetch;
     int dv = dst_is_device;
     if ((st = copy_out(events, j->kp.events, G * 8, dv, a)) == CWC_OK &&
         (st = copy_out(status, j->kp.status, G, dv, a)) == CWC_OK &&
@@ -1040,7 +1028,6 @@ cwc_status cwc_server_fetch_counters(cwc_server *s, uint64_t job, int64_t *event
         (st = copy_out(t_final, j->kp.t_final, G * 8, dv, a)) == CWC_OK &&
         (st = copy_out(n_recorded, j->kp.n_recorded, G * 4, dv, a)) == CWC_OK)
         st = copy_out(final_counts, j->kp.final_counts, G * j->C * 4, dv, a);
-    (void)hipStreamDestroy(a);
     return st;
 }
 
@@ -1055,11 +1042,9 @@ cwc_status cwc_server_fetch_term(cwc_server *s, uint64_t job, int32_t *dst, int 
     }
     if (!j) return st;
     if (!j->term_ints) return set_err(CWC_E_INVALID, "not a general model: its term is fixed");
-    hipStream_t a;
-    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess)
-        return set_err(CWC_E_DEVICE, "stream");
+    std::lock_guard<std::mutex> fk(s->fetch_mu);
+    hipStream_t a = s->fetch;
     st = copy_out(dst, j->kp.final_term, (size_t)j->term_ints * 4, dst_is_device, a);
-    (void)hipStreamDestroy(a);
     return st;
 }
 
@@ -1125,6 +1110,7 @@ void cwc_server_destroy(cwc_server *s)
         if (s->ev_res[i]) (void)hipEventDestroy(s->ev_res[i]);
     }
     if (s->aux) (void)hipStreamDestroy(s->aux);
+    if (s->fetch) (void)hipStreamDestroy(s->fetch);
     if (s->d_jobs) (void)hipFree(s->d_jobs);
     if (s->d_done) (void)hipFree(s->d_done);
     for (auto &g : s->groups) {

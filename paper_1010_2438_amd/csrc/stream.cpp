@@ -309,7 +309,11 @@ extern "C" cwc_status cwc_stream_open(cwc_ctx *ctx, const cwc_model *m, const cw
     SHIP(hipHostMalloc((void **)&s->h_kp, 2 * sizeof(cwc_kparams), hipHostMallocDefault));
     SHIP(hipEventCreate(&s->ev_start));
     SHIP(hipEventCreate(&s->ev_sim));
-    SHIP(hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking));
+    // the window copies must not queue behind the next window's kernel
+    if (!own_queue_stream(ctx, &s->copy)) {
+        free_stream(s);
+        return set_err(CWC_E_DEVICE, "copy stream creation failed");
+    }
 
     kp.seed = d->seed;
     kp.G = G;
