@@ -140,7 +140,8 @@ std::string gmodel_source(const GFlat &g);
 // compute-unit mask covering the whole device, which the runtime serves
 // from a queue of its own instead of one shared round-robin with the
 // process's other streams): work on it never waits behind a long kernel
-// on another stream.
+// on another stream.  Falls back to an ordinary non-blocking stream where
+// the runtime has no masked streams.
 bool own_queue_stream(cwc_ctx *ctx, hipStream_t *st);
 }  // namespace cwc
 #endif
