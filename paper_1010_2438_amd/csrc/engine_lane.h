@@ -15,6 +15,13 @@
 //                                      whether a count exceeds the cap
 //   CWC_UNDO() / CWC_REDO()            take that change back / apply it again
 //   CWC_STAGE(ptr, stride)             counts -> ptr[c * stride]
+// and, for the two-lane (pair) layout, over the slots z<k> a lane keeps:
+//   CWC_PAIR_STATE / CWC_PAIR_DECL / CWC_PAIR_SETUP   slots; rates K<i>
+//                                      and half tree q<i>; change table
+//   CWC_PAIR_LOAD_COUNTS(ptr, h) / CWC_PAIR_STORE_COUNTS(ptr, h)
+//   CWC_PAIR_STAGE(col0, h)            the lane's cells -> col0[c * 64]
+//   CWC_PAIR_TREE(h) / CWC_PAIR_HALF / CWC_PAIR_DESCEND(x, j)
+//   CWC_PAIR_APPLY_MX(j, mx) / CWC_PAIR_UNDO() / CWC_PAIR_REDO()
 //
 // One event (paper Sec. 2.3, Match / Resolve / Update):
 //   Resolve  - one Philox4x32-10 block keyed by the run seed at counter
@@ -182,7 +189,7 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
 // or the event cap is reached -- in which case the slow path takes it
 // back and handles the event in the order the direct method defines.
 
-#define CWC_LANE_LOCALS                                                       \
+#define CWC_GROUP_LOCALS                                                      \
     const double INF = __longlong_as_double(0x7FF0000000000000ll);            \
     /* dynamic LDS (sized by the host): per wavefront a staging area      \
        [cell][lane] i32, then per wavefront the accumulator cache: nslot   \
@@ -209,8 +216,12 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
     i32 kn = 0;                     /* next sample index */                   \
     i32 kstop = p.k_stop;           /* suspend before recording this one */   \
     double E = 0.0, U = 0.0;        /* draw e: -ln(u_tau), u_sel */           \
-    CWC_DT_SETUP;                   /* per-leaf change table -> LDS */        \
     (void)INF;
+// the lane and quad layouts' locals: the group locals and the per-leaf
+// change table in LDS
+#define CWC_LANE_LOCALS                                                       \
+    CWC_GROUP_LOCALS;                                                         \
+    CWC_DT_SETUP
 
 // time-sliced kernels: a slice of p.k_slice sample points (constant
 // simulation time) ends before the trajectory records sample kn + k_slice
@@ -307,6 +318,11 @@ __device__ __forceinline__ void cwc_acc_flush_all(const cwc_kparams &p, const cw
 #define CWC_FINISH(st)                                                        \
     do {                                                                      \
         { i32 *fc_ = p.final_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(fc_); } \
+        CWC_FINISH_REST(st);                                                  \
+    } while (0)
+// the per-trajectory results other than the final counts
+#define CWC_FINISH_REST(st)                                                   \
+    do {                                                                      \
         p.events[lg] = (i64)e;                                                \
         p.t_final[lg] = t;                                                    \
         p.digest[lg] = p.want_digest ? dig : 0ull;                            \
@@ -557,6 +573,7 @@ __device__ __forceinline__ double cwc_pair_dpp(double v)
 }
 #define CWC_PAIR_LO 0xA0
 #define CWC_PAIR_HI 0xF5
+#define CWC_PAIR_SWAP 0xB1
 
 // Both lanes take the pair's two fresh draws: lane 1's (the next event,
 // an odd iteration) into Eo/Uo, lane 0's (the one after, an even
@@ -569,12 +586,37 @@ __device__ __forceinline__ double cwc_pair_dpp(double v)
         U = cwc_pair_dpp<CWC_PAIR_LO>(UN);                                    \
     } while (0)
 
+// Locals of the pair kernels: the group locals, the lane's count slots,
+// the lane's rates and half tree, and its change table in LDS.
+#define CWC_PAIR_LOCALS                                                       \
+    CWC_GROUP_LOCALS;                                                         \
+    CWC_PAIR_STATE;                                                           \
+    CWC_PAIR_DECL;                                                            \
+    CWC_PAIR_SETUP
+
+// Both lanes write the counts they keep into lane 0's staging column, in
+// place for lane 0 to record the sample.
+#define CWC_PAIR_STAGE_ALL()                                                  \
+    do {                                                                      \
+        i32 *c0_ = col - h_;                                                  \
+        CWC_PAIR_STAGE(c0_, h_);                                              \
+        cwc_lds_order();                                                      \
+    } while (0)
+
+// terminal outputs: each lane writes the counts it keeps, lane 0 the rest
+#define CWC_PAIR_FINISH(st)                                                   \
+    do {                                                                      \
+        { i32 *fc_ = p.final_counts + lg * (i64)CWC_C;                        \
+          CWC_PAIR_STORE_COUNTS(fc_, h_); }                                   \
+        if (h_ == 0) CWC_FINISH_REST(st);                                     \
+    } while (0)
+
 // One step of a pair (the locals of the pair kernels, CWC_PEMIT and h_ in
 // scope): the event of this iteration -- its draw is E/U at an even
 // iteration, Eo/Uo at an odd one, the same in both lanes -- and, at an
 // even iteration, the next two draws (lane 1: e+1, lane 0: e+2).  The root
 // is lane 0's half plus lane 1's, in that order in both lanes.
-#define CWC_PAIR_STEP_BODY(st, EVEN)                                                   \
+#define CWC_PAIR_STEP_BODY(st, EVEN)                                          \
     do {                                                                      \
         CWC_PAIR_TREE(h_);                                                    \
         const double s_ = CWC_PAIR_HALF;                                      \
@@ -590,7 +632,9 @@ __device__ __forceinline__ double cwc_pair_dpp(double v)
         const int j0_ = cwc_pair_dpp_i<CWC_PAIR_LO>(jl_);                     \
         const int j1_ = cwc_pair_dpp_i<CWC_PAIR_HI>(jl_);                     \
         const i32 j_ = b0_ ? CWC_PB + j1_ : j0_;                              \
-        CWC_APPLY(j_, p.cap, ovf_);                                           \
+        CWC_PAIR_APPLY_MX(j_, mxl_);                                          \
+        const unsigned mxo_ = (unsigned)cwc_pair_dpp_i<CWC_PAIR_SWAP>((int)mxl_); \
+        const bool ovf_ = (mxl_ > mxo_ ? mxl_ : mxo_) > p.cap;                \
         double En_ = 0.0, Un_ = 0.0;                                          \
         if (EVEN) {                                                           \
             const u64 d1_ = e + 2ull - (u64)h_;                               \
@@ -603,11 +647,11 @@ __device__ __forceinline__ double cwc_pair_dpp(double v)
             if (EVEN) CWC_PAIR_SPREAD(En_, Un_);                              \
             if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
         } else if (a0_ == 0.0) {                                              \
-            CWC_UNDO();                                                       \
+            CWC_PAIR_UNDO();                                                  \
             while (kn < p.K1 && kn < kstop) CWC_PEMIT();                   \
             (st) = kn < p.K1 ? CWC_ST_WINDOW : CWC_ST_ABSORBED;               \
         } else {                                                              \
-            CWC_UNDO();                                                       \
+            CWC_PAIR_UNDO();                                                  \
             while (t_next < tn_ && kn < kstop) CWC_PEMIT();                \
             if (t_next < tn_) {                                               \
                 (st) = CWC_ST_WINDOW;                                         \
@@ -616,7 +660,7 @@ __device__ __forceinline__ double cwc_pair_dpp(double v)
             } else if (ovf_) {                                                \
                 (st) = CWC_ST_OVERFLOW;                                       \
             } else {                                                          \
-                CWC_REDO();                                                   \
+                CWC_PAIR_REDO();                                              \
                 t = tn_; e = e + 1;                                           \
                 if (EVEN) CWC_PAIR_SPREAD(En_, Un_);                          \
                 if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
@@ -628,8 +672,7 @@ __device__ __forceinline__ double cwc_pair_dpp(double v)
 template <bool PERSIST, bool SHARED_K>
 __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
 {
-    CWC_LANE_LOCALS;
-    CWC_PAIR_DECL;
+    CWC_PAIR_LOCALS;
     const int h_ = (int)(__lane_id() & 1u);
     if (SHARED_K) { CWC_PAIR_LOAD_K(p.rates, h_); }
     u32 it = 0;                     // wavefront iteration (parity: whose draw)
@@ -655,7 +698,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
             CWC_PAIR_LOAD_K(kr_, h_);                                         \
         }                                                                     \
         { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
-          CWC_LOAD_COUNTS(ini_); }                                            \
+          CWC_PAIR_LOAD_COUNTS(ini_, h_); }                                   \
         t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
         dig = 0xcbf29ce484222325ull;                                          \
         if (it & 1u) {                                                        \
@@ -672,9 +715,9 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
     // sample kn of the current state (lane 0 of the pair records it)
 #define CWC_PEMIT()                                                           \
     do {                                                                      \
+        CWC_PAIR_STAGE_ALL();                                                 \
         if (h_ == 0) {                                                        \
-            i32 *tr_ = CWC_TRAJ_AT(p, lg, kn); \
-            CWC_STAGE(col, 64);                                               \
+            i32 *tr_ = CWC_TRAJ_AT(p, lg, kn);                                \
             cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
         }                                                                     \
         kn += 1;                                                              \
@@ -714,7 +757,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
             int st = CWC_ST_RUNNING;
             CWC_PAIR_STEP_BODY(st, true);
             if (st != CWC_ST_RUNNING) {
-                if (h_ == 0) CWC_FINISH(st);
+                CWC_PAIR_FINISH(st);
                 active = false;
             }
         }
@@ -724,7 +767,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
             int st = CWC_ST_RUNNING;
             CWC_PAIR_STEP_BODY(st, false);
             if (st != CWC_ST_RUNNING) {
-                if (h_ == 0) CWC_FINISH(st);
+                CWC_PAIR_FINISH(st);
                 active = false;
             }
         }
@@ -753,8 +796,7 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
     pr.nslot = q.nslot;
     pr.k_stop = 0x7FFFFFFF;
     const cwc_kparams &p = RESIDENT ? pr : jobs[wave_job[w]];
-    CWC_LANE_LOCALS;
-    CWC_PAIR_DECL;
+    CWC_PAIR_LOCALS;
     const int h_ = (int)(__lane_id() & 1u);
     double Eo = 0.0, Uo = 0.0;      // draw of the next odd-iteration event
     auto item = [&](const cwc_kparams &p, i64 first, long long budget) -> u32 {
@@ -771,11 +813,11 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
                 CWC_PAIR_LOAD_K(kr_, h_);
             }
             if (p.ck_state[my] == 0) {
-                { const i32 *ini_ = p.init + (i64)p.init_stride * inst; CWC_LOAD_COUNTS(ini_); }
+                { const i32 *ini_ = p.init + (i64)p.init_stride * inst; CWC_PAIR_LOAD_COUNTS(ini_, h_); }
                 t = 0.0; t_next = 0.0; e = 0; kn = 0;
                 dig = 0xcbf29ce484222325ull;
             } else {
-                { const i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_LOAD_COUNTS(ck_); }
+                { const i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_PAIR_LOAD_COUNTS(ck_, h_); }
                 t = p.ck_t[lg];
                 e = p.ck_e[lg];
                 dig = p.ck_dig[lg];
@@ -789,9 +831,9 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
         long long n = 0;
 #define CWC_PEMIT()                                                           \
     do {                                                                      \
+        CWC_PAIR_STAGE_ALL();                                                 \
         if (h_ == 0) {                                                        \
-            i32 *tr_ = CWC_TRAJ_AT(p, lg, kn); \
-            CWC_STAGE(col, 64);                                               \
+            i32 *tr_ = CWC_TRAJ_AT(p, lg, kn);                                \
             cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
         }                                                                     \
         kn += 1;                                                              \
@@ -801,16 +843,19 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
 #define CWC_PSLICE_AFTER(st)                                                  \
     do {                                                                      \
         if ((st) != CWC_ST_RUNNING && (st) != CWC_ST_WINDOW) {                \
+            { i32 *fc_ = p.final_counts + lg * (i64)CWC_C;                    \
+              CWC_PAIR_STORE_COUNTS(fc_, h_); }                               \
             if (h_ == 0) {                                                    \
-                CWC_FINISH(st);                                               \
+                CWC_FINISH_REST(st);                                          \
                 p.ck_state[lg] = 2;                                           \
                 if (!RESIDENT) atomicAdd(p.done_count, 1ull);                 \
                 fin = true;                                                   \
             }                                                                 \
             active = false;                                                   \
         } else if ((st) == CWC_ST_WINDOW || n == budget) {                    \
+            { i32 *ck_ = p.ck_counts + lg * (i64)CWC_C;                       \
+              CWC_PAIR_STORE_COUNTS(ck_, h_); }                               \
             if (h_ == 0) {                                                    \
-                { i32 *ck_ = p.ck_counts + lg * (i64)CWC_C; CWC_STORE_COUNTS(ck_); } \
                 p.ck_t[lg] = t;                                               \
                 p.ck_e[lg] = e;                                               \
                 p.ck_dig[lg] = dig;                                           \

@@ -551,7 +551,9 @@ std::string codegen_lane(const Flat &f)
     // added modulo 2^32, so an undo restores them exactly.  A rule only
     // fires with enough reactants, so no count goes below zero and the cap
     // test over the cells that can grow is one compare of their maximum.
-    w.begin("CWC_APPLY(j, cap, ovf)");
+    // CWC_APPLY_MX leaves the largest count that can grow in `mx` (the
+    // pair layout takes the cap test across its two lanes).
+    w.begin("CWC_APPLY_MX(j, mx)");
     w.line("const unsigned js_ = (unsigned)(j);");
     if (n_words == 1) {
         w.line("const unsigned dw0_ = cwc_dtab[js_];");
@@ -562,7 +564,7 @@ std::string codegen_lane(const Flat &f)
         w.line("const uint4 dq_ = cwc_dtab[js_];");
         w.line("const unsigned dw0_ = dq_.x, dw1_ = dq_.y, dw2_ = dq_.z, dw3_ = dq_.w;");
     }
-    w.line("unsigned mx_ = 0u;");
+    w.line("unsigned mx = 0u;");
     for (int c = 0; c < C; ++c) {
         if (per_cell[c].empty()) continue;
         bool pos = false;
@@ -612,8 +614,11 @@ std::string codegen_lane(const Flat &f)
         w.line("const unsigned d" + I(c) + "_ = " + e + ";");
         w.line("n" + I(c) + " = (int)((unsigned)n" + I(c) + " + d" + I(c) + "_);");
         w.line("CWC_KEEP(n" + I(c) + ");");
-        if (pos) w.line("mx_ = mx_ > (unsigned)n" + I(c) + " ? mx_ : (unsigned)n" + I(c) + ";");
+        if (pos) w.line("mx = mx > (unsigned)n" + I(c) + " ? mx : (unsigned)n" + I(c) + ";");
     }
+    w.end();
+    w.begin("CWC_APPLY(j, cap, ovf)");
+    w.line("CWC_APPLY_MX(j, mx_)");
     w.line("const bool ovf = mx_ > (cap);");
     w.end();
     w.begin("CWC_UNDO()");
@@ -666,6 +671,19 @@ std::string codegen_lane(const Flat &f)
     // operations as the lane layout's leaf (k * h with h = product of the
     // binomial factors), so the tree has the same bits; an empty side has
     // rate 0 and gives +0, which leaves every sum unchanged.
+    //
+    // Counts per lane: a lane keeps only the counts its half of the tree
+    // reads, and the cells no half reads are shared out between the two
+    // lanes, so an event's update and the tree's conversions touch about
+    // half of the cells in each lane.  Register z<k> (slot k) holds cell
+    // cell_of[h][k] in lane h; the left and the right reactant of the same
+    // leaf position are put in the same slot wherever the cells allow it,
+    // so their factor needs no select.  A cell read by both halves is kept
+    // by both lanes (lane 0 writes it out).  Each lane updates its slots
+    // from its own rows of a per-slot change table (lane h: rows h*P + j,
+    // byte layout).  When that table does not fit its LDS budget, both
+    // lanes keep every cell (slot k = cell k, the lane layout's counts,
+    // table and update).
     if (P >= 2) {
         const int B = P / 2;
         int DB = 0;
@@ -675,6 +693,146 @@ std::string codegen_lane(const Flat &f)
         for (int i = 0; i < B; ++i) hz[B + i] = (f.leaf_slot[i] < 0) && (f.leaf_slot[B + i] < 0);
         for (int i = B - 1; i >= 1; --i) hz[i] = hz[2 * i] && hz[2 * i + 1];
         auto hv = [&](int i) -> std::string { return hz[i] ? std::string("0.0") : "q" + I(i); };
+
+        // net change of each cell at each leaf
+        std::vector<std::vector<long long>> dcl(C, std::vector<long long>(P, 0));
+        for (int c = 0; c < C; ++c)
+            for (auto &ld : per_cell[c]) dcl[c][ld.first] += ld.second;
+        std::vector<char> changes(C, 0);
+        for (int c = 0; c < C; ++c) changes[c] = !per_cell[c].empty();
+
+        // factors at leaf position i: left from lane 0, right from lane 1
+        // (two two-cell factors of the right side may be swapped: the
+        // product is the same either way)
+        std::vector<std::pair<Fac, Fac>> facL(B), facR(B);
+        for (int i = 0; i < B; ++i) {
+            facL[i] = factors(f.leaf_slot[i]);
+            facR[i] = factors(f.leaf_slot[B + i]);
+        }
+        auto is_cell = [](const Fac &a) { return a.kind == 'n' || a.kind == 'd'; };
+
+        // --- slot maps
+        std::vector<int> slot_of[2] = {std::vector<int>(C, -1), std::vector<int>(C, -1)};
+        std::vector<int> cell_of[2];
+        auto free_at = [&](int h, int k) { return k >= (int)cell_of[h].size() || cell_of[h][k] < 0; };
+        auto take = [&](int h, int c, int k) {
+            if ((int)cell_of[h].size() <= k) cell_of[h].resize(k + 1, -1);
+            cell_of[h][k] = c;
+            slot_of[h][c] = k;
+        };
+        // would cells a (lane 0) and b (lane 1) end up in one slot
+        auto alignable = [&](int a, int b) {
+            const int ka = slot_of[0][a], kb = slot_of[1][b];
+            if (ka >= 0 && kb >= 0) return ka == kb;
+            if (ka >= 0) return free_at(1, ka);
+            if (kb >= 0) return free_at(0, kb);
+            return true;
+        };
+        auto align = [&](const Fac &l, const Fac &r) {
+            if (!(l.kind == r.kind && is_cell(l))) return;
+            const int a = l.cell, b = r.cell;
+            const int ka = slot_of[0][a], kb = slot_of[1][b];
+            if (ka >= 0 && kb >= 0) return;
+            if (ka >= 0) { if (free_at(1, ka)) take(1, b, ka); return; }
+            if (kb >= 0) { if (free_at(0, kb)) take(0, a, kb); return; }
+            int k = 0;
+            while (!free_at(0, k) || !free_at(1, k)) ++k;
+            take(0, a, k);
+            take(1, b, k);
+        };
+        auto misaligned = [&](const Fac &l, const Fac &r) {
+            if (l.kind != r.kind) return 1;
+            if (!is_cell(l)) return 0;
+            return alignable(l.cell, r.cell) ? 0 : 1;
+        };
+        for (int i = 0; i < B; ++i) {
+            if (f.leaf_slot[i] < 0 || f.leaf_slot[B + i] < 0) continue;
+            const std::pair<Fac, Fac> L = facL[i], R = facR[i], Rs{R.second, R.first};
+            if (is_cell(R.first) && is_cell(R.second) &&
+                misaligned(L.first, Rs.first) + misaligned(L.second, Rs.second) <
+                    misaligned(L.first, R.first) + misaligned(L.second, R.second))
+                facR[i] = Rs;
+            align(facL[i].first, facR[i].first);
+            align(facL[i].second, facR[i].second);
+        }
+        // the rest of each half's reactants, then the cells no half reads
+        auto first_free = [&](int h) { int k = 0; while (!free_at(h, k)) ++k; return k; };
+        for (int h = 0; h < 2; ++h)
+            for (int i = 0; i < B; ++i)
+                for (const Fac &a : {(h ? facR : facL)[i].first, (h ? facR : facL)[i].second})
+                    if (is_cell(a) && slot_of[h][a.cell] < 0) take(h, a.cell, first_free(h));
+        auto held = [&](int h, bool changing) {
+            int n = 0;
+            for (int c = 0; c < C; ++c) n += slot_of[h][c] >= 0 && (!changing || changes[c]);
+            return n;
+        };
+        for (int c = 0; c < C; ++c) {
+            if (slot_of[0][c] >= 0 || slot_of[1][c] >= 0) continue;
+            const int h = changes[c] ? (held(1, true) < held(0, true) ? 1 : 0)
+                                     : (held(1, false) < held(0, false) ? 1 : 0);
+            take(h, c, first_free(h));
+        }
+        int S = (int)std::max(cell_of[0].size(), cell_of[1].size());
+        for (int h = 0; h < 2; ++h) cell_of[h].resize(S, -1);
+
+        // --- per-slot change table, byte layout (as the lane layout's)
+        std::vector<Field> sf(S);
+        std::vector<char> spos(S, 0);
+        bool split = true;
+        int pw = 0;
+        {
+            int used[4] = {0, 0, 0, 0};
+            for (int k = 0; k < S && split; ++k) {
+                long long lo = 0, hi = 0;
+                for (int h = 0; h < 2; ++h) {
+                    const int c = cell_of[h][k];
+                    if (c < 0) continue;
+                    for (int j = 0; j < P; ++j) {
+                        lo = std::min(lo, dcl[c][j]);
+                        hi = std::max(hi, dcl[c][j]);
+                    }
+                }
+                if (lo == 0 && hi == 0) continue;   // no field: never changes
+                spos[k] = hi > 0;
+                Field &fd = sf[k];
+                fd.sgn = lo < 0;
+                const bool b8 = fd.sgn ? (lo >= -128 && hi <= 127) : hi <= 255;
+                const bool b16 = fd.sgn ? (lo >= -32768 && hi <= 32767) : hi <= 65535;
+                if (!b16) { split = false; break; }
+                fd.width = b8 ? 8 : 16;
+                for (int wd = 0; wd < 4 && fd.word < 0; ++wd) {
+                    const int off = (used[wd] + fd.width - 1) / fd.width * fd.width;
+                    if (off + fd.width <= 32) {
+                        fd.word = wd;
+                        fd.off = off;
+                        used[wd] = off + fd.width;
+                        pw = std::max(pw, wd + 1);
+                    }
+                }
+                if (fd.word < 0) split = false;
+            }
+            if (pw == 3) pw = 4;
+            if ((size_t)2 * (size_t)P * (size_t)pw * 4u > kPairStaticLdsBytes) split = false;
+        }
+        if (!split) {
+            // every cell in both lanes, slot k = cell k
+            S = C;
+            for (int h = 0; h < 2; ++h) {
+                cell_of[h].assign(C, -1);
+                for (int c = 0; c < C; ++c) { cell_of[h][c] = c; slot_of[h][c] = c; }
+            }
+        }
+        o << "#define CWC_PAIR_SPLIT " << (split ? 1 : 0) << "\n";
+        // the slot's register: z<k> of the per-lane state, or the lane
+        // layout's count n<k>
+        auto sv = [&](int k) { return (split ? "z" : "n") + I(k); };
+        // the cells lane h writes out: those it holds that lane 0 does not
+        // hold, and for lane 0 all it holds
+        auto owns = [&](int h, int k) {
+            const int c = cell_of[h][k];
+            return c >= 0 && (h == 0 || slot_of[0][c] < 0);
+        };
+
         w.begin("CWC_PAIR_DECL");
         for (int i = 0; i < B; ++i)
             if (!hz[B + i]) w.line("double K" + I(i) + " = 0.0;");
@@ -691,35 +849,182 @@ std::string codegen_lane(const Flat &f)
             w.line("K" + I(i) + " = (h) ? " + Rs + " : " + Ls + ";");
         }
         w.end();
-        // the lane's factor: h selects the right or the left slot's.  Two
-        // integer-valued factors (a count or one) are selected as integers
-        // and converted once (the conversion is exact either way).
-        auto fsel = [&](const Fac &l, const Fac &r) -> std::string {
-            if (l == r) return fexpr(l);
+
+        // per-lane state: declare, load from a count row, write the lane's
+        // cells to a count row or to a staging column (stride 64), and (for
+        // the host tests) write every cell the lane holds
+        w.begin("CWC_PAIR_STATE");
+        if (split)
+            for (int k = 0; k < S; ++k) w.line("int z" + I(k) + " = 0;");
+        w.end();
+        w.begin("CWC_PAIR_LOAD_COUNTS(ptr, h)");
+        if (split) {
+            for (int k = 0; k < S; ++k) {
+                const int c0 = cell_of[0][k], c1 = cell_of[1][k];
+                const std::string l0 = c0 < 0 ? "0" : "(ptr)[" + I(c0) + "]";
+                const std::string l1 = c1 < 0 ? "0" : "(ptr)[" + I(c1) + "]";
+                w.line("z" + I(k) + " = (h) ? " + l1 + " : " + l0 + ";");
+            }
+        } else {
+            w.line("CWC_LOAD_COUNTS(ptr);");
+        }
+        w.end();
+        auto store_lines = [&](const std::string &dst, const std::string &stride, bool all) {
+            if (!split) {
+                w.line(all ? "{" : "if (!(h)) {");
+                for (int c = 0; c < C; ++c)
+                    w.line("(" + dst + ")[" + I(c) + stride + "] = n" + I(c) + ";");
+                w.line("}");
+                return;
+            }
+            for (int h = 0; h < 2; ++h) {
+                w.line(h ? "} else {" : "if (!(h)) {");
+                for (int k = 0; k < S; ++k)
+                    if (all ? cell_of[h][k] >= 0 : owns(h, k))
+                        w.line("(" + dst + ")[" + I(cell_of[h][k]) + stride + "] = z" + I(k) + ";");
+            }
+            w.line("}");
+        };
+        w.begin("CWC_PAIR_STORE_COUNTS(ptr, h)");
+        store_lines("ptr", "", false);
+        w.end();
+        w.begin("CWC_PAIR_STAGE(col0, h)");
+        store_lines("col0", " * 64", false);
+        w.end();
+        w.begin("CWC_PAIR_HELD(ptr, h)");
+        store_lines("ptr", "", true);
+        w.end();
+
+        // update: CWC_PAIR_APPLY_MX adds the change of leaf j to the lane's
+        // slots and leaves the largest count that can grow in `mx`;
+        // CWC_PAIR_UNDO / CWC_PAIR_REDO take it back and apply it again
+        if (!split) {
+            o << "#define CWC_PAIR_SETUP CWC_DT_SETUP\n";
+            o << "#define CWC_PAIR_APPLY_MX(j, mx) CWC_APPLY_MX(j, mx)\n";
+            o << "#define CWC_PAIR_UNDO() CWC_UNDO()\n";
+            o << "#define CWC_PAIR_REDO() CWC_REDO()\n";
+        } else {
+            const char *ty = pw == 1 ? "unsigned int" : pw == 2 ? "uint2" : "uint4";
+            if (pw > 0) {
+                o << "__constant__ unsigned int cwc_ptab_g[" << 2 * P * pw << "] = {";
+                for (int h = 0; h < 2; ++h)
+                    for (int j = 0; j < P; ++j) {
+                        unsigned long long wv[4] = {0, 0, 0, 0};
+                        for (int k = 0; k < S; ++k) {
+                            const int c = cell_of[h][k];
+                            if (sf[k].word < 0 || c < 0) continue;
+                            const unsigned long long bv =
+                                (unsigned long long)dcl[c][j] & ((1ull << sf[k].width) - 1ull);
+                            wv[sf[k].word] |= bv << sf[k].off;
+                        }
+                        for (int q = 0; q < pw; ++q) {
+                            char b[32];
+                            std::snprintf(b, sizeof b, "%s0x%llxu", (h || j || q) ? ", " : "", wv[q]);
+                            o << b;
+                        }
+                    }
+                o << "};\n";
+                // the block's copy in LDS; cwc_ptab_h = this lane's rows
+                w.begin("CWC_PAIR_SETUP");
+                w.line(std::string("__shared__ ") + ty + " cwc_ptab[" + I(2 * P) + "];");
+                w.line("for (int i_ = (int)threadIdx.x; i_ < " + I(2 * P * pw) +
+                       "; i_ += (int)blockDim.x) ((unsigned int *)cwc_ptab)[i_] = cwc_ptab_g[i_];");
+                w.line("__syncthreads();");
+                w.line(std::string("const ") + ty + " *const cwc_ptab_h = cwc_ptab + ((threadIdx.x & 1u) ? " +
+                       I(P) + " : 0);");
+                w.end();
+            } else {
+                o << "#define CWC_PAIR_SETUP\n";
+            }
+            w.begin("CWC_PAIR_APPLY_MX(j, mx)");
+            if (pw == 1) {
+                w.line("const unsigned dw0_ = cwc_ptab_h[(unsigned)(j)];");
+            } else if (pw == 2) {
+                w.line("const uint2 dq_ = cwc_ptab_h[(unsigned)(j)];");
+                w.line("const unsigned dw0_ = dq_.x, dw1_ = dq_.y;");
+            } else if (pw == 4) {
+                w.line("const uint4 dq_ = cwc_ptab_h[(unsigned)(j)];");
+                w.line("const unsigned dw0_ = dq_.x, dw1_ = dq_.y, dw2_ = dq_.z, dw3_ = dq_.w;");
+            }
+            w.line("unsigned mx = 0u;");
+            for (int k = 0; k < S; ++k) {
+                const Field &fd = sf[k];
+                if (fd.word < 0) continue;
+                const std::string wv = "dw" + I(fd.word) + "_";
+                const std::string sh = fd.off ? "(" + wv + " >> " + I(fd.off) + ")" : wv;
+                const std::string e =
+                    fd.sgn ? std::string("(unsigned)(int)(") + (fd.width == 8 ? "signed char" : "short") + ")" + sh
+                           : std::string("(unsigned)(") + (fd.width == 8 ? "unsigned char" : "unsigned short") +
+                                 ")" + sh;
+                w.line("const unsigned d" + I(k) + "_ = " + e + ";");
+                w.line("z" + I(k) + " = (int)((unsigned)z" + I(k) + " + d" + I(k) + "_);");
+                w.line("CWC_KEEP(z" + I(k) + ");");
+                if (spos[k]) w.line("mx = mx > (unsigned)z" + I(k) + " ? mx : (unsigned)z" + I(k) + ";");
+            }
+            w.end();
+            w.begin("CWC_PAIR_UNDO()");
+            for (int k = 0; k < S; ++k)
+                if (sf[k].word >= 0) w.line("z" + I(k) + " = (int)((unsigned)z" + I(k) + " - d" + I(k) + "_);");
+            w.end();
+            w.begin("CWC_PAIR_REDO()");
+            for (int k = 0; k < S; ++k)
+                if (sf[k].word >= 0) w.line("z" + I(k) + " = (int)((unsigned)z" + I(k) + " + d" + I(k) + "_);");
+            w.end();
+        }
+
+        // --- the lane's half tree.  A factor is taken from the slot of its
+        // cell in the lane; where the two sides' factors differ (kind or
+        // slot) h selects, two integer-valued ones as integers converted
+        // once (the conversion is exact either way).
+        struct SF {
+            char kind;
+            int slot;
+            bool operator==(const SF &o) const { return kind == o.kind && slot == o.slot; }
+        };
+        auto sfac = [&](int h, const Fac &a) -> SF {
+            return SF{a.kind, is_cell(a) ? slot_of[h][a.cell] : -1};
+        };
+        auto sexpr = [&](const SF &a) -> std::string {
+            switch (a.kind) {
+            case 'n': return "y" + I(a.slot) + "_";
+            case 'd': return "(y" + I(a.slot) + "_ * w" + I(a.slot) + "_)";
+            case 'h': return "0.5";
+            default: return "1.0";
+            }
+        };
+        auto ssel = [&](const SF &l, const SF &r) -> std::string {
+            if (l == r) return sexpr(l);
             const bool li = l.kind == 'n' || l.kind == '1', ri = r.kind == 'n' || r.kind == '1';
             if (li && ri) {
-                auto iexpr = [&](const Fac &a) { return a.kind == 'n' ? "n" + I(a.cell) : std::string("1"); };
+                auto iexpr = [&](const SF &a) { return a.kind == 'n' ? sv(a.slot) : std::string("1"); };
                 return "(double)((h) ? " + iexpr(r) + " : " + iexpr(l) + ")";
             }
-            return "((h) ? " + fexpr(r) + " : " + fexpr(l) + ")";
+            return "((h) ? " + sexpr(r) + " : " + sexpr(l) + ")";
         };
+        std::vector<char> s_need_d(S, 0);
+        for (int i = 0; i < B; ++i)
+            for (int h = 0; h < 2; ++h)
+                for (const Fac &a : {(h ? facR : facL)[i].first, (h ? facR : facL)[i].second})
+                    if (a.kind == 'd') s_need_d[slot_of[h][a.cell]] = 1;
         w.begin("CWC_PAIR_TREE(h)");
         w.line("{");
-        for (int c = 0; c < C; ++c) {
-            if (need_c[c]) w.line("const double c" + I(c) + "_ = (double)n" + I(c) + ";");
-            if (need_d[c])
-                w.line("const double m" + I(c) + "_ = (double)(n" + I(c) + " > 0 ? n" + I(c) + " - 1 : 0);");
+        for (int k = 0; k < S; ++k) {
+            w.line("const double y" + I(k) + "_ = (double)" + sv(k) + ";");
+            if (s_need_d[k])
+                w.line("const double w" + I(k) + "_ = (double)(" + sv(k) + " > 0 ? " + sv(k) + " - 1 : 0);");
         }
         for (int i = 0; i < B; ++i) {
             if (hz[B + i]) continue;
             const int sl = f.leaf_slot[i], sr = f.leaf_slot[B + i];
-            auto L = factors(sl), R = factors(sr);
             // an empty side has rate +0: any finite factor gives +0 there,
-            // so the other side's factors are used unselected
+            // so the other side's factors (at their slots) are used unselected
+            std::pair<SF, SF> L{SF{'1', -1}, SF{'1', -1}}, R = L;
+            if (sl >= 0) L = {sfac(0, facL[i].first), sfac(0, facL[i].second)};
+            if (sr >= 0) R = {sfac(1, facR[i].first), sfac(1, facR[i].second)};
             if (sl < 0) L = R;
             if (sr < 0) R = L;
-            const std::string F1 = fsel(L.first, R.first);
-            const std::string F2 = fsel(L.second, R.second);
+            const std::string F1 = ssel(L.first, R.first);
+            const std::string F2 = ssel(L.second, R.second);
             std::string H;
             if (F2 == "1.0") H = F1;
             else H = "(" + F1 + " * " + F2 + ")";

@@ -71,8 +71,12 @@ inline size_t cwc_lane_lds_bytes(int n_cells, int waves, int nslot)
                             2 * (size_t)nslot * (size_t)n_cells * 8);
 }
 constexpr int kDefaultSampleSlots = 16;
-// static LDS of a lane-layout kernel: the per-leaf change table
-constexpr size_t kLaneStaticLds = kLaneStaticLdsBytes;
+// static LDS of a lane-group kernel: the per-leaf (lane layout) or
+// per-lane (pair layout) change table, and in the resident kernels the
+// copies of the job parameters of a block's four wavefronts
+constexpr size_t kLaneStaticLds =
+    (kPairStaticLdsBytes > kLaneStaticLdsBytes ? kPairStaticLdsBytes : kLaneStaticLdsBytes) +
+    4 * sizeof(cwc_kparams);
 // Compiles and loads the model's device code for `layout` if needed.
 cwc_status ensure_layout(cwc_model *m, int layout);
 // Directory of the compiled-code cache and the tuning table (created).

@@ -92,7 +92,8 @@ def applied_changes(model):
                 % (P * dtw))
     code = HARNESS % {
         "table": "#define CWC_DT_W %d\n%s" % (dtw, table),
-        "apply": macro(src, "CWC_APPLY(j, cap, ovf)"), "lds": lds, "copy": copy, "P": P,
+        "apply": macro(src, "CWC_APPLY_MX(j, mx)") + macro(src, "CWC_APPLY(j, cap, ovf)"),
+        "lds": lds, "copy": copy, "P": P,
         "base": BASE,
         "decl": "\n".join("            int n%d = %d;" % (c, BASE) for c in range(C)),
         "print": "\n".join('                std::printf(" %%d", n%d - %d);' % (c, BASE)
@@ -159,7 +160,7 @@ def test_layouts_covered():
     from paper_1010_2438_amd import cwc_codegen
     seen = set()
     for name, mk in MODELS.items():
-        body = macro(cwc_codegen(mk()), "CWC_APPLY(j, cap, ovf)")
+        body = macro(cwc_codegen(mk()), "CWC_APPLY_MX(j, mx)")
         for key, pat in (("s8", "(signed char)"), ("u8", "(unsigned char)"),
                          ("s16", "(short)"), ("u16", "(unsigned short)"),
                          ("sbfe", "amdgcn_sbfe"), ("ubfe", "amdgcn_ubfe(dw"),
@@ -168,6 +169,167 @@ def test_layouts_covered():
             if pat in body:
                 seen.add(key)
     assert seen == {"s8", "u8", "s16", "u16", "sbfe", "ubfe", "mask32", "mask64", "w4"}
+
+
+PAIR_APPLY_HARNESS = r"""
+#include <cstdio>
+typedef unsigned int u32;
+typedef int i32;
+struct uint2 { unsigned x, y; };
+struct uint4 { unsigned x, y, z, w; };
+#define __constant__
+#define CWC_KEEP(v) ((void)0)
+static inline int host_sbfe(int v, unsigned off, unsigned w) {
+    return (int)((unsigned)v << (32u - off - w)) >> (32u - w);
+}
+static inline unsigned host_ubfe(unsigned v, unsigned off, unsigned w) {
+    return (v >> off) & (w >= 32u ? 0xFFFFFFFFu : ((1u << w) - 1u));
+}
+#define __builtin_amdgcn_sbfe(v, o, w) host_sbfe((v), (o), (w))
+#define __builtin_amdgcn_ubfe(v, o, w) host_ubfe((v), (o), (w))
+%(tables)s
+%(macros)s
+static void show(const char *tag, int h, int j, const int *v) {
+    std::printf("%%s %%d %%d", tag, h, j);
+    for (int c = 0; c < %(C)d; ++c) std::printf(" %%d", v[c]);
+    std::printf("\n");
+}
+int main() {
+%(copy)s
+    for (int pass = 0; pass < 2; ++pass) {
+        int N[%(C)d];
+        for (int c = 0; c < %(C)d; ++c) N[c] = %(base)d + (pass ? 0 : 7 * c);
+        for (int j = 0; j < %(P)d; ++j) {
+            int own[%(C)d];
+            for (int c = 0; c < %(C)d; ++c) own[c] = -1;
+            unsigned mxs[2];
+            for (int h = 0; h < 2; ++h) {
+%(ndecl)s
+                CWC_PAIR_STATE;
+                CWC_PAIR_LOAD_COUNTS(N, h);
+%(tabh)s
+                CWC_PAIR_APPLY_MX(j, mx_);
+                mxs[h] = mx_;
+                int held[%(C)d];
+                for (int c = 0; c < %(C)d; ++c) held[c] = -1;
+                CWC_PAIR_HELD(held, h);
+                if (!pass) show("H", h, j, held);
+                CWC_PAIR_STORE_COUNTS(own, h);
+                CWC_PAIR_UNDO();
+                for (int c = 0; c < %(C)d; ++c) held[c] = -1;
+                CWC_PAIR_HELD(held, h);
+                if (!pass) show("U", h, j, held);
+                CWC_PAIR_REDO();
+                for (int c = 0; c < %(C)d; ++c) held[c] = -1;
+                CWC_PAIR_HELD(held, h);
+                if (!pass) show("R", h, j, held);
+            }
+            if (!pass) show("O", 0, j, own);
+            else std::printf("M %%d %%u\n", j, mxs[0] > mxs[1] ? mxs[0] : mxs[1]);
+        }
+    }
+    return 0;
+}
+"""
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+@pytest.mark.parametrize("name", sorted(MODELS))
+def test_generated_pair_change_table(name):
+    """The pair layout's per-lane counts (Sec. 2.1 update, split over two
+    lanes): for every leaf, each lane's slots take the oracle's net change
+    of the cells they hold, undo and redo restore and re-apply it exactly,
+    the two lanes' written rows together give every cell's new count, and
+    the larger of the two lanes' growth maxima exceeds the state exactly
+    when the leaf raises some count.  Covers both the per-lane table and
+    the fallback where both lanes keep every cell."""
+    from paper_1010_2438_amd import cwc_codegen
+    model = MODELS[name]()
+    src = cwc_codegen(model)
+    C = int(re.search(r"#define CWC_C (\d+)", src).group(1))
+    P = int(re.search(r"#define CWC_P (\d+)", src).group(1))
+    if "#define CWC_PAIR_SPLIT" not in src:
+        pytest.skip("a single leaf: no pair layout")
+    split = int(re.search(r"#define CWC_PAIR_SPLIT (\d+)", src).group(1))
+    dtw = int(re.search(r"#define CWC_DT_W (\d+)", src).group(1))
+    tables, copy, tabh = [], [], ""
+    if dtw:
+        tables.append(re.search(r"__constant__ unsigned int cwc_dtab_g\[\d+\] = \{[^}]*\};", src).group(0))
+        ty = re.search(r"__shared__ (\w[\w ]*?) cwc_dtab\[", src).group(1)
+        tables.append("static %s cwc_dtab[%d];" % (ty, P))
+        copy.append("    for (int i = 0; i < %d; ++i) ((unsigned *)cwc_dtab)[i] = cwc_dtab_g[i];"
+                    % (P * dtw))
+    m = re.search(r"__constant__ unsigned int cwc_ptab_g\[(\d+)\] = \{[^}]*\};", src)
+    if split and m:
+        tables.append(m.group(0))
+        ty = re.search(r"__shared__ (\w[\w ]*?) cwc_ptab\[", src).group(1)
+        tables.append("static %s cwc_ptab[%d];" % (ty, 2 * P))
+        copy.append("    for (int i = 0; i < %s; ++i) ((unsigned *)cwc_ptab)[i] = cwc_ptab_g[i];"
+                    % m.group(1))
+        tabh = "                const %s *cwc_ptab_h = cwc_ptab + (h ? %d : 0);" % (ty, P)
+    heads = ["CWC_LOAD_COUNTS(ptr)", "CWC_STORE_COUNTS(ptr)", "CWC_APPLY_MX(j, mx)",
+             "CWC_UNDO()", "CWC_REDO()", "CWC_PAIR_STATE", "CWC_PAIR_LOAD_COUNTS(ptr, h)",
+             "CWC_PAIR_STORE_COUNTS(ptr, h)", "CWC_PAIR_HELD(ptr, h)"]
+    macros = "".join(macro(src, hd) for hd in heads)
+    for hd in ("CWC_PAIR_APPLY_MX(", "CWC_PAIR_UNDO(", "CWC_PAIR_REDO("):
+        # one-line aliases of the lane macros, or multi-line macros
+        i = src.index("#define " + hd)
+        eol = src.index("\n", i)
+        macros += src[i:eol + 1] if not src[:eol].endswith("\\") else \
+            src[i:src.index("/* end */", i)] + "/* end */\n"
+    code = PAIR_APPLY_HARNESS % {
+        "tables": "\n".join(tables), "macros": macros, "copy": "\n".join(copy), "C": C, "P": P,
+        "base": BASE, "tabh": tabh,
+        "ndecl": "\n".join("                int n%d = 0; (void)n%d;" % (c, c) for c in range(C))}
+    d = tempfile.mkdtemp(prefix="cwc_papply_")
+    try:
+        with open(os.path.join(d, "t.cpp"), "w") as f:
+            f.write(code)
+        subprocess.check_call(["g++", "-O1", "-w", "-o", os.path.join(d, "t"),
+                               os.path.join(d, "t.cpp")])
+        out = subprocess.check_output([os.path.join(d, "t")], text=True)
+    finally:
+        shutil.rmtree(d)
+    flat = oracle.FlatModel(model)
+    N = [BASE + 7 * c for c in range(C)]
+    rows = {}
+    for line in out.splitlines():
+        f = line.split()
+        rows[(f[0], int(f[1]), int(f[2]))] = [int(x) for x in f[3:]]
+    n_held = [0, 0]
+    for leaf in range(P):
+        want = [0] * C
+        for k in range(int(flat.leaf_ndelta[leaf])):
+            cell, v = (int(x) for x in flat.leaf_delta[leaf, k])
+            want[cell] += v
+        new = [N[c] + want[c] for c in range(C)]
+        assert rows[("O", 0, leaf)] == new, "leaf %d: written rows" % leaf
+        for h in range(2):
+            held = rows[("H", h, leaf)]
+            kept = [c for c in range(C) if held[c] != -1]
+            n_held[h] = len(kept)
+            assert all(held[c] == new[c] for c in kept), ("apply", leaf, h)
+            assert rows[("R", h, leaf)] == held, ("redo", leaf, h)
+            assert all(rows[("U", h, leaf)][c] == N[c] for c in kept), ("undo", leaf, h)
+            assert all(rows[("U", h, leaf)][c] == -1 for c in range(C) if c not in kept)
+    mx = {int(f[1]): int(f[2]) for f in (l.split() for l in out.splitlines()) if f[0] == "M"}
+    for leaf in range(P):
+        want = [0] * C
+        for k in range(int(flat.leaf_ndelta[leaf])):
+            cell, v = (int(x) for x in flat.leaf_delta[leaf, k])
+            want[cell] += v
+        assert (mx[leaf] > BASE) == any(v > 0 for v in want), "leaf %d: growth" % leaf
+    if split:
+        # the split leaves each lane with fewer cells than the model has
+        assert max(n_held) < C
+
+
+def test_pair_split_covered():
+    """The models above reach both pair-layout state forms."""
+    from paper_1010_2438_amd import cwc_codegen
+    seen = {int(m.group(1)) for m in (re.search(r"#define CWC_PAIR_SPLIT (\d+)", cwc_codegen(mk()))
+                                      for mk in MODELS.values()) if m}
+    assert seen == {0, 1}
 
 
 DESCENT_HARNESS = r"""
@@ -365,6 +527,8 @@ QUAD_TREE_PART = r"""
 
 PAIR_TREE_PART = r"""
         for (int h = 0; h < 2; ++h) {
+            CWC_PAIR_STATE;
+            CWC_PAIR_LOAD_COUNTS(N, h);
             CWC_PAIR_DECL;
             CWC_PAIR_LOAD_K(KR, h);
             CWC_PAIR_TREE(h);
@@ -396,7 +560,8 @@ def test_generated_trees(name):
     macros = macro(src, "CWC_TREE")
     qnames = set()
     if pair:
-        for head in ("CWC_PAIR_DECL", "CWC_PAIR_LOAD_K(ptr, h)", "CWC_PAIR_TREE(h)"):
+        for head in ("CWC_LOAD_COUNTS(ptr)", "CWC_PAIR_STATE", "CWC_PAIR_LOAD_COUNTS(ptr, h)",
+                     "CWC_PAIR_DECL", "CWC_PAIR_LOAD_K(ptr, h)", "CWC_PAIR_TREE(h)"):
             macros += macro(src, head)
         # the half tree declares only the nodes that can be non-zero
         qnames = set(re.findall(r"double (q\d+) = ", macro(src, "CWC_PAIR_DECL")))
