@@ -15,7 +15,8 @@
 //                                      whether a count exceeds the cap
 //   CWC_UNDO() / CWC_REDO()            take that change back / apply it again
 //   CWC_STAGE(ptr, stride)             counts -> ptr[c * stride]
-// and, for the two-lane (pair) layout, over the slots z<k> a lane keeps:
+// and, for the two-lane (pair) layout, over the slots z<k> a lane keeps
+// (the four-lane quad layout's CWC_QUAD_* likewise, with CWC_QUAD_PART):
 //   CWC_PAIR_STATE / CWC_PAIR_DECL / CWC_PAIR_SETUP   slots; rates K<i>
 //                                      and half tree q<i>; change table
 //   CWC_PAIR_LOAD_COUNTS(ptr, h) / CWC_PAIR_STORE_COUNTS(ptr, h)
@@ -594,20 +595,22 @@ __device__ __forceinline__ double cwc_pair_dpp(double v)
     CWC_PAIR_DECL;                                                            \
     CWC_PAIR_SETUP
 
-// Both lanes write the counts they keep into lane 0's staging column, in
-// place for lane 0 to record the sample.
-#define CWC_PAIR_STAGE_ALL()                                                  \
+// Every lane of a group (pair or quad; STAGE its staging macro) writes the
+// counts it keeps into the group's lane 0's staging column, in place for
+// lane 0 to record the sample.
+#define CWC_GROUP_STAGE_ALL(STAGE)                                            \
     do {                                                                      \
         i32 *c0_ = col - h_;                                                  \
-        CWC_PAIR_STAGE(c0_, h_);                                              \
+        STAGE(c0_, h_);                                                       \
         cwc_lds_order();                                                      \
     } while (0)
 
-// terminal outputs: each lane writes the counts it keeps, lane 0 the rest
-#define CWC_PAIR_FINISH(st)                                                   \
+// terminal outputs: each lane of a group writes the counts it keeps
+// (STORE its count-row macro), lane 0 the rest
+#define CWC_GROUP_FINISH(st, STORE)                                           \
     do {                                                                      \
         { i32 *fc_ = p.final_counts + lg * (i64)CWC_C;                        \
-          CWC_PAIR_STORE_COUNTS(fc_, h_); }                                   \
+          STORE(fc_, h_); }                                                   \
         if (h_ == 0) CWC_FINISH_REST(st);                                     \
     } while (0)
 
@@ -715,7 +718,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
     // sample kn of the current state (lane 0 of the pair records it)
 #define CWC_PEMIT()                                                           \
     do {                                                                      \
-        CWC_PAIR_STAGE_ALL();                                                 \
+        CWC_GROUP_STAGE_ALL(CWC_PAIR_STAGE);                                                 \
         if (h_ == 0) {                                                        \
             i32 *tr_ = CWC_TRAJ_AT(p, lg, kn);                                \
             cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
@@ -757,7 +760,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
             int st = CWC_ST_RUNNING;
             CWC_PAIR_STEP_BODY(st, true);
             if (st != CWC_ST_RUNNING) {
-                CWC_PAIR_FINISH(st);
+                CWC_GROUP_FINISH(st, CWC_PAIR_STORE_COUNTS);
                 active = false;
             }
         }
@@ -767,7 +770,7 @@ __device__ __forceinline__ void cwc_pair_main(const cwc_kparams &p)
             int st = CWC_ST_RUNNING;
             CWC_PAIR_STEP_BODY(st, false);
             if (st != CWC_ST_RUNNING) {
-                CWC_PAIR_FINISH(st);
+                CWC_GROUP_FINISH(st, CWC_PAIR_STORE_COUNTS);
                 active = false;
             }
         }
@@ -831,7 +834,7 @@ __device__ __forceinline__ void cwc_pair_slice(const cwc_kparams *jobs, const in
         long long n = 0;
 #define CWC_PEMIT()                                                           \
     do {                                                                      \
-        CWC_PAIR_STAGE_ALL();                                                 \
+        CWC_GROUP_STAGE_ALL(CWC_PAIR_STAGE);                                                 \
         if (h_ == 0) {                                                        \
             i32 *tr_ = CWC_TRAJ_AT(p, lg, kn);                                \
             cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
@@ -927,12 +930,14 @@ cwc_pair_resident_table(const cwc_kparams *jobs, cwc_rq q)
 #ifdef CWC_QUAD
 // ------------------------------------------------------------ quad layout
 // Four lanes per trajectory (lane bits h = lane & 3): lane h holds quarter h
-// of the propensity tree (leaves [h*B, (h+1)*B)), all four hold the counts.
+// of the propensity tree (leaves [h*B, (h+1)*B)) and the counts that quarter
+// reads (the generated per-lane slots, as the pair layout's).
 // Per event: each lane builds its quarter; every lane reads the four
 // quarter sums (DPP broadcasts of lanes 0..3 of the quad) and forms the two
 // halves and the root in the canonical order; all take the two top
 // decisions, each descends its own quarter and the leaf index is read from
-// the lane holding the chosen quarter; all apply the change.  Draws: at
+// the lane holding the chosen quarter; each lane applies the change to its
+// slots, and the cap test takes the largest growth of the four lanes.  Draws: at
 // iterations of phase 0 (it % 4 == 0) lane k draws e + 1 + ((k + 3) % 4)
 // and the four draws are spread at once, so the events of phases 1, 2, 3
 // and the next phase 0 find theirs in E1..E3 and E0.  Every quad of a
@@ -943,6 +948,8 @@ cwc_pair_resident_table(const cwc_kparams *jobs, cwc_rq q)
 #define CWC_QL1 0x55
 #define CWC_QL2 0xAA
 #define CWC_QL3 0xFF
+#define CWC_QSWAP1 0xB1
+#define CWC_QSWAP2 0x4E
 
 #define CWC_QUAD_SPREAD(EN, UN)                                               \
     do {                                                                      \
@@ -983,7 +990,11 @@ cwc_pair_resident_table(const cwc_kparams *jobs, cwc_rq q)
         const int j3_ = cwc_pair_dpp_i<CWC_QL3>(jl_);                         \
         const i32 jq_ = b0_ ? (b1_ ? j3_ : j2_) : (b1_ ? j1_ : j0_);          \
         const i32 j_ = ((b0_ ? 2 : 0) + (b1_ ? 1 : 0)) * CWC_QB + jq_;         \
-        CWC_APPLY(j_, p.cap, ovf_);                                           \
+        CWC_QUAD_APPLY_MX(j_, mxl_);                                          \
+        const unsigned mx1_ = (unsigned)cwc_pair_dpp_i<CWC_QSWAP1>((int)mxl_); \
+        const unsigned mx2_ = mxl_ > mx1_ ? mxl_ : mx1_;                      \
+        const unsigned mx3_ = (unsigned)cwc_pair_dpp_i<CWC_QSWAP2>((int)mx2_); \
+        const bool ovf_ = (mx2_ > mx3_ ? mx2_ : mx3_) > p.cap;                \
         double En_ = 0.0, Un_ = 0.0;                                          \
         if ((PH) == 0) {                                                      \
             const u64 d1_ = e + 1ull + (u64)((h_ + 3) & 3);                   \
@@ -996,18 +1007,18 @@ cwc_pair_resident_table(const cwc_kparams *jobs, cwc_rq q)
             if ((PH) == 0) CWC_QUAD_SPREAD(En_, Un_);                         \
             if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
         } else if (a0_ == 0.0) {                                              \
-            CWC_UNDO();                                                       \
+            CWC_QUAD_UNDO();                                                  \
             while (kn < p.K1) CWC_QEMIT();                                    \
             (st) = CWC_ST_ABSORBED;                                           \
         } else {                                                              \
-            CWC_UNDO();                                                       \
+            CWC_QUAD_UNDO();                                                  \
             while (t_next < tn_) CWC_QEMIT();                                 \
             if (kn >= p.K1) {                                                 \
                 (st) = CWC_ST_OK;                                             \
             } else if (ovf_) {                                                \
                 (st) = CWC_ST_OVERFLOW;                                       \
             } else {                                                          \
-                CWC_REDO();                                                   \
+                CWC_QUAD_REDO();                                              \
                 t = tn_; e = e + 1;                                           \
                 if ((PH) == 0) CWC_QUAD_SPREAD(En_, Un_);                     \
                 if (p.want_digest) dig = (dig ^ (u64)(u32)j_) * 0x100000001b3ull; \
@@ -1019,8 +1030,10 @@ cwc_pair_resident_table(const cwc_kparams *jobs, cwc_rq q)
 template <bool PERSIST, bool SHARED_K>
 __device__ __forceinline__ void cwc_quad_main(const cwc_kparams &p)
 {
-    CWC_LANE_LOCALS;
+    CWC_GROUP_LOCALS;
+    CWC_QUAD_STATE;
     CWC_QUAD_DECL;
+    CWC_QUAD_SETUP;
     const int h_ = (int)(__lane_id() & 3u);
     if (SHARED_K) { CWC_QUAD_LOAD_K(p.rates, h_); }
     u32 it = 0;                     // wavefront iteration (phase it % 4)
@@ -1047,7 +1060,7 @@ __device__ __forceinline__ void cwc_quad_main(const cwc_kparams &p)
             CWC_QUAD_LOAD_K(kr_, h_);                                         \
         }                                                                     \
         { const i32 *ini_ = p.init + (i64)p.init_stride * inst;               \
-          CWC_LOAD_COUNTS(ini_); }                                            \
+          CWC_QUAD_LOAD_COUNTS(ini_, h_); }                                   \
         t = 0.0; t_next = 0.0; e = 0; kn = 0;                                 \
         dig = 0xcbf29ce484222325ull;                                          \
         {                                                                     \
@@ -1062,9 +1075,9 @@ __device__ __forceinline__ void cwc_quad_main(const cwc_kparams &p)
     // sample kn of the current state (lane 0 of the quad records it)
 #define CWC_QEMIT()                                                           \
     do {                                                                      \
+        CWC_GROUP_STAGE_ALL(CWC_QUAD_STAGE);                                  \
         if (h_ == 0) {                                                        \
-            i32 *tr_ = CWC_TRAJ_AT(p, lg, kn); \
-            CWC_STAGE(col, 64);                                               \
+            i32 *tr_ = CWC_TRAJ_AT(p, lg, kn);                                \
             cwc_emit_moments(p, acc, col, inst, kn, tr_);                     \
         }                                                                     \
         kn += 1;                                                              \
@@ -1104,7 +1117,7 @@ __device__ __forceinline__ void cwc_quad_main(const cwc_kparams &p)
         int st = CWC_ST_RUNNING;                                              \
         CWC_QUAD_STEP_BODY(st, PH);                                           \
         if (st != CWC_ST_RUNNING) {                                           \
-            if (h_ == 0) CWC_FINISH(st);                                      \
+            CWC_GROUP_FINISH(st, CWC_QUAD_STORE_COUNTS);                      \
             active = false;                                                   \
         }                                                                     \
     }                                                                         \

@@ -653,12 +653,397 @@ std::string codegen_lane(const Flat &f)
         if (sl.n_react == 2) return {Fac{'n', sl.react_cell[0]}, Fac{'n', sl.react_cell[1]}};
         return {one, one};
     };
-    auto fexpr = [&](const Fac &a) -> std::string {
+
+    // --- per-lane counts of a lane group (the pair and quad layouts below).
+    // Lane h of a group of G lanes builds leaf positions i = 0..B-1, the
+    // leaves h*B + i of the canonical tree (B = P/G), and keeps only the
+    // counts those leaves read, in registers z0..z(S-1) ("slots"): slot k
+    // holds cell cell_of[h][k] in lane h, or nothing.  The reactant cells
+    // the G lanes read at the same leaf position are put in one slot
+    // wherever the cells already placed allow it (a lane's two two-cell
+    // factors may be swapped, the product being the same), so the factor is
+    // that slot in every lane with no select.  Cells no lane reads are
+    // shared out (a changing cell to the lane holding the fewest changing
+    // cells, a constant one to the lane holding the fewest cells), so every
+    // cell lives in some lane; a cell kept by several lanes is written out
+    // by the lowest of them.  Each lane updates its slots from its own rows
+    // of a per-slot change table (lane h: rows h*P + j, byte layout).  When
+    // that table does not fit its LDS budget, every lane keeps every cell
+    // (slot k = cell k: the lane layout's counts, table and update).
+    std::vector<std::vector<long long>> dcl(C, std::vector<long long>(P, 0));
+    for (int c = 0; c < C; ++c)
+        for (auto &ld : per_cell[c]) dcl[c][ld.first] += ld.second;
+    std::vector<char> changes(C, 0);
+    for (int c = 0; c < C; ++c) changes[c] = !per_cell[c].empty();
+    auto is_cell = [](const Fac &a) { return a.kind == 'n' || a.kind == 'd'; };
+    struct GroupMaps {
+        int G = 0, B = 0, S = 0, pw = 0;
+        bool split = true;
+        std::vector<std::vector<int>> slot_of, cell_of;      // [G][C], [G][S]
+        std::vector<std::vector<std::pair<Fac, Fac>>> fac;   // [G][B] (after swaps)
+        std::vector<Field> sf;                               // [S]
+        std::vector<char> spos;                              // [S]: can grow
+    };
+    auto group_maps = [&](int G) -> GroupMaps {
+        GroupMaps m;
+        m.G = G;
+        m.B = P / G;
+        const int B = m.B;
+        m.slot_of.assign(G, std::vector<int>(C, -1));
+        m.cell_of.assign(G, std::vector<int>());
+        m.fac.assign(G, std::vector<std::pair<Fac, Fac>>(B));
+        for (int h = 0; h < G; ++h)
+            for (int i = 0; i < B; ++i) m.fac[h][i] = factors(f.leaf_slot[h * B + i]);
+        auto free_at = [&](int h, int k) { return k >= (int)m.cell_of[h].size() || m.cell_of[h][k] < 0; };
+        auto take = [&](int h, int c, int k) {
+            if ((int)m.cell_of[h].size() <= k) m.cell_of[h].resize(k + 1, -1);
+            m.cell_of[h][k] = c;
+            m.slot_of[h][c] = k;
+        };
+        // would cell a of lane ha and cell b of lane hb end up in one slot
+        auto alignable = [&](int ha, int a, int hb, int b) {
+            const int ka = m.slot_of[ha][a], kb = m.slot_of[hb][b];
+            if (ka >= 0 && kb >= 0) return ka == kb;
+            if (ka >= 0) return free_at(hb, ka);
+            if (kb >= 0) return free_at(ha, kb);
+            return true;
+        };
+        auto misaligned = [&](int ha, const Fac &l, int hb, const Fac &r) {
+            if (l.kind != r.kind) return 1;
+            if (!is_cell(l)) return 0;
+            return alignable(ha, l.cell, hb, r.cell) ? 0 : 1;
+        };
+        // put the members' cells, (lane, cell), in one slot where possible:
+        // the slot of the first member already placed, else the lowest slot
+        // free in every member's lane
+        auto align = [&](const std::vector<std::pair<int, int>> &mem) {
+            int k = -1;
+            for (auto &hc : mem)
+                if (k < 0 && m.slot_of[hc.first][hc.second] >= 0) k = m.slot_of[hc.first][hc.second];
+            if (k < 0) {
+                k = 0;
+                for (;;) {
+                    bool ok = true;
+                    for (auto &hc : mem) ok = ok && free_at(hc.first, k);
+                    if (ok) break;
+                    ++k;
+                }
+            }
+            for (auto &hc : mem)
+                if (m.slot_of[hc.first][hc.second] < 0 && free_at(hc.first, k)) take(hc.first, hc.second, k);
+        };
+        for (int i = 0; i < B; ++i) {
+            int ref = -1, present = 0;
+            for (int h = 0; h < G; ++h)
+                if (f.leaf_slot[h * B + i] >= 0) {
+                    ++present;
+                    if (ref < 0) ref = h;
+                }
+            if (present < 2) continue;
+            const std::pair<Fac, Fac> Rf = m.fac[ref][i];
+            for (int h = ref + 1; h < G; ++h) {
+                if (f.leaf_slot[h * B + i] < 0) continue;
+                const std::pair<Fac, Fac> F = m.fac[h][i], Fs{F.second, F.first};
+                if (is_cell(F.first) && is_cell(F.second) &&
+                    misaligned(ref, Rf.first, h, Fs.first) + misaligned(ref, Rf.second, h, Fs.second) <
+                        misaligned(ref, Rf.first, h, F.first) + misaligned(ref, Rf.second, h, F.second))
+                    m.fac[h][i] = Fs;
+            }
+            for (int t = 0; t < 2; ++t) {
+                const Fac &r = t ? Rf.second : Rf.first;
+                if (!is_cell(r)) continue;
+                std::vector<std::pair<int, int>> mem{{ref, r.cell}};
+                for (int h = ref + 1; h < G; ++h) {
+                    if (f.leaf_slot[h * B + i] < 0) continue;
+                    const Fac &a = t ? m.fac[h][i].second : m.fac[h][i].first;
+                    if (a.kind == r.kind) mem.push_back({h, a.cell});
+                }
+                if (mem.size() >= 2) align(mem);
+            }
+        }
+        // the rest of each lane's reactants, then the cells no lane reads
+        auto first_free = [&](int h) {
+            int k = 0;
+            while (!free_at(h, k)) ++k;
+            return k;
+        };
+        for (int h = 0; h < G; ++h)
+            for (int i = 0; i < B; ++i)
+                for (const Fac &a : {m.fac[h][i].first, m.fac[h][i].second})
+                    if (is_cell(a) && m.slot_of[h][a.cell] < 0) take(h, a.cell, first_free(h));
+        auto held = [&](int h, bool changing) {
+            int n = 0;
+            for (int c = 0; c < C; ++c) n += m.slot_of[h][c] >= 0 && (!changing || changes[c]);
+            return n;
+        };
+        for (int c = 0; c < C; ++c) {
+            bool any = false;
+            for (int h = 0; h < G; ++h) any = any || m.slot_of[h][c] >= 0;
+            if (any) continue;
+            int best = 0;
+            for (int h = 1; h < G; ++h)
+                if (held(h, changes[c]) < held(best, changes[c])) best = h;
+            take(best, c, first_free(best));
+        }
+        int S = 0;
+        for (int h = 0; h < G; ++h) S = std::max(S, (int)m.cell_of[h].size());
+        for (int h = 0; h < G; ++h) m.cell_of[h].resize(S, -1);
+        // per-slot change table, byte layout (as the lane layout's)
+        m.sf.assign(S, Field{});
+        m.spos.assign(S, 0);
+        int used[4] = {0, 0, 0, 0};
+        for (int k = 0; k < S && m.split; ++k) {
+            long long lo = 0, hi = 0;
+            for (int h = 0; h < G; ++h) {
+                const int c = m.cell_of[h][k];
+                if (c < 0) continue;
+                for (int j = 0; j < P; ++j) {
+                    lo = std::min(lo, dcl[c][j]);
+                    hi = std::max(hi, dcl[c][j]);
+                }
+            }
+            if (lo == 0 && hi == 0) continue;   // no field: never changes
+            m.spos[k] = hi > 0;
+            Field &fd = m.sf[k];
+            fd.sgn = lo < 0;
+            const bool b8 = fd.sgn ? (lo >= -128 && hi <= 127) : hi <= 255;
+            const bool b16 = fd.sgn ? (lo >= -32768 && hi <= 32767) : hi <= 65535;
+            if (!b16) {
+                m.split = false;
+                break;
+            }
+            fd.width = b8 ? 8 : 16;
+            for (int wd = 0; wd < 4 && fd.word < 0; ++wd) {
+                const int off = (used[wd] + fd.width - 1) / fd.width * fd.width;
+                if (off + fd.width <= 32) {
+                    fd.word = wd;
+                    fd.off = off;
+                    used[wd] = off + fd.width;
+                    m.pw = std::max(m.pw, wd + 1);
+                }
+            }
+            if (fd.word < 0) m.split = false;
+        }
+        if (m.pw == 3) m.pw = 4;
+        if ((size_t)G * (size_t)P * (size_t)m.pw * 4u > (G == 2 ? kPairStaticLdsBytes : kQuadStaticLdsBytes))
+            m.split = false;
+        if (!m.split) {
+            // every cell in every lane, slot k = cell k
+            m.S = C;
+            for (int h = 0; h < G; ++h) {
+                m.cell_of[h].assign(C, -1);
+                for (int c = 0; c < C; ++c) {
+                    m.cell_of[h][c] = c;
+                    m.slot_of[h][c] = c;
+                }
+            }
+        } else {
+            m.S = S;
+        }
+        return m;
+    };
+    // four-way select by the bits of h, folding equal operands
+    auto sel4 = [&](const std::string v[4]) -> std::string {
+        auto sel2 = [&](const std::string &bit, const std::string &a, const std::string &b) {
+            return a == b ? a : "((" + bit + ") ? " + b + " : " + a + ")";
+        };
+        const std::string lo = sel2("(h) & 1", v[0], v[1]);
+        const std::string hi = sel2("(h) & 1", v[2], v[3]);
+        return sel2("(h) & 2", lo, hi);
+    };
+    // The group's state macros (X = CWC_PAIR or CWC_QUAD): X_SPLIT, the
+    // slots (X_STATE), load from a count row, write the lane's cells to a
+    // count row or to a staging column (stride 64), and (for the host
+    // tests) write every cell the lane holds; the update X_APPLY_MX (the
+    // change of leaf j added to the lane's slots, the largest count that
+    // can grow left in `mx`), X_UNDO / X_REDO; the table in LDS (X_SETUP).
+    auto emit_group_state = [&](const GroupMaps &m, const std::string &X, const std::string &tab) {
+        const int G = m.G, S = m.S;
+        auto sv = [&](int k) { return (m.split ? "z" : "n") + I(k); };
+        auto owns = [&](int h, int k) {
+            const int c = m.cell_of[h][k];
+            if (c < 0) return false;
+            for (int g = 0; g < h; ++g)
+                if (m.slot_of[g][c] >= 0) return false;
+            return true;
+        };
+        o << "#define " << X << "_SPLIT " << (m.split ? 1 : 0) << "\n";
+        w.begin(X + "_STATE");
+        if (m.split)
+            for (int k = 0; k < S; ++k) w.line("int z" + I(k) + " = 0;");
+        w.end();
+        w.begin(X + "_LOAD_COUNTS(ptr, h)");
+        if (m.split) {
+            for (int k = 0; k < S; ++k) {
+                std::string l[4];
+                for (int h = 0; h < G; ++h) {
+                    const int c = m.cell_of[h][k];
+                    l[h] = c < 0 ? "0" : "(ptr)[" + I(c) + "]";
+                }
+                w.line("z" + I(k) + " = " + (G == 2 ? "(h) ? " + l[1] + " : " + l[0] : sel4(l)) + ";");
+            }
+        } else {
+            w.line("CWC_LOAD_COUNTS(ptr);");
+        }
+        w.end();
+        auto store_lines = [&](const std::string &dst, const std::string &stride, bool all) {
+            if (!m.split) {
+                w.line(all ? "{" : "if (!(h)) {");
+                for (int c = 0; c < C; ++c)
+                    w.line("(" + dst + ")[" + I(c) + stride + "] = n" + I(c) + ";");
+                w.line("}");
+                return;
+            }
+            for (int h = 0; h < G; ++h) {
+                if (G == 2) w.line(h ? "} else {" : "if (!(h)) {");
+                else w.line(h == 0 ? "if ((h) == 0) {" : h < G - 1 ? "} else if ((h) == " + I(h) + ") {" : "} else {");
+                for (int k = 0; k < S; ++k)
+                    if (all ? m.cell_of[h][k] >= 0 : owns(h, k))
+                        w.line("(" + dst + ")[" + I(m.cell_of[h][k]) + stride + "] = z" + I(k) + ";");
+            }
+            w.line("}");
+        };
+        w.begin(X + "_STORE_COUNTS(ptr, h)");
+        store_lines("ptr", "", false);
+        w.end();
+        w.begin(X + "_STAGE(col0, h)");
+        store_lines("col0", " * 64", false);
+        w.end();
+        w.begin(X + "_HELD(ptr, h)");
+        store_lines("ptr", "", true);
+        w.end();
+        if (!m.split) {
+            o << "#define " << X << "_SETUP CWC_DT_SETUP\n";
+            o << "#define " << X << "_APPLY_MX(j, mx) CWC_APPLY_MX(j, mx)\n";
+            o << "#define " << X << "_UNDO() CWC_UNDO()\n";
+            o << "#define " << X << "_REDO() CWC_REDO()\n";
+            return;
+        }
+        const int pw = m.pw;
+        const char *ty = pw == 1 ? "unsigned int" : pw == 2 ? "uint2" : "uint4";
+        if (pw > 0) {
+            o << "__constant__ unsigned int " << tab << "_g[" << G * P * pw << "] = {";
+            for (int h = 0; h < G; ++h)
+                for (int j = 0; j < P; ++j) {
+                    unsigned long long wv[4] = {0, 0, 0, 0};
+                    for (int k = 0; k < S; ++k) {
+                        const int c = m.cell_of[h][k];
+                        if (m.sf[k].word < 0 || c < 0) continue;
+                        const unsigned long long bv =
+                            (unsigned long long)dcl[c][j] & ((1ull << m.sf[k].width) - 1ull);
+                        wv[m.sf[k].word] |= bv << m.sf[k].off;
+                    }
+                    for (int q = 0; q < pw; ++q) {
+                        char b[32];
+                        std::snprintf(b, sizeof b, "%s0x%llxu", (h || j || q) ? ", " : "", wv[q]);
+                        o << b;
+                    }
+                }
+            o << "};\n";
+            // the block's copy in LDS; <tab>_h = this lane's rows
+            w.begin(X + "_SETUP");
+            w.line(std::string("__shared__ ") + ty + " " + tab + "[" + I(G * P) + "];");
+            w.line("for (int i_ = (int)threadIdx.x; i_ < " + I(G * P * pw) +
+                   "; i_ += (int)blockDim.x) ((unsigned int *)" + tab + ")[i_] = " + tab + "_g[i_];");
+            w.line("__syncthreads();");
+            if (G == 2)
+                w.line(std::string("const ") + ty + " *const " + tab + "_h = " + tab +
+                       " + ((threadIdx.x & 1u) ? " + I(P) + " : 0);");
+            else
+                w.line(std::string("const ") + ty + " *const " + tab + "_h = " + tab + " + (threadIdx.x & " +
+                       I(G - 1) + "u) * " + I(P) + "u;");
+            w.end();
+        } else {
+            o << "#define " << X << "_SETUP\n";
+        }
+        w.begin(X + "_APPLY_MX(j, mx)");
+        if (pw == 1) {
+            w.line("const unsigned dw0_ = " + tab + "_h[(unsigned)(j)];");
+        } else if (pw == 2) {
+            w.line("const uint2 dq_ = " + tab + "_h[(unsigned)(j)];");
+            w.line("const unsigned dw0_ = dq_.x, dw1_ = dq_.y;");
+        } else if (pw == 4) {
+            w.line("const uint4 dq_ = " + tab + "_h[(unsigned)(j)];");
+            w.line("const unsigned dw0_ = dq_.x, dw1_ = dq_.y, dw2_ = dq_.z, dw3_ = dq_.w;");
+        }
+        w.line("unsigned mx = 0u;");
+        for (int k = 0; k < S; ++k) {
+            const Field &fd = m.sf[k];
+            if (fd.word < 0) continue;
+            const std::string wv = "dw" + I(fd.word) + "_";
+            const std::string sh = fd.off ? "(" + wv + " >> " + I(fd.off) + ")" : wv;
+            const std::string e =
+                fd.sgn ? std::string("(unsigned)(int)(") + (fd.width == 8 ? "signed char" : "short") + ")" + sh
+                       : std::string("(unsigned)(") + (fd.width == 8 ? "unsigned char" : "unsigned short") +
+                             ")" + sh;
+            w.line("const unsigned d" + I(k) + "_ = " + e + ";");
+            w.line("z" + I(k) + " = (int)((unsigned)z" + I(k) + " + d" + I(k) + "_);");
+            w.line("CWC_KEEP(z" + I(k) + ");");
+            if (m.spos[k]) w.line("mx = mx > (unsigned)z" + I(k) + " ? mx : (unsigned)z" + I(k) + ";");
+        }
+        w.end();
+        w.begin(X + "_UNDO()");
+        for (int k = 0; k < S; ++k)
+            if (m.sf[k].word >= 0) w.line("z" + I(k) + " = (int)((unsigned)z" + I(k) + " - d" + I(k) + "_);");
+        w.end();
+        w.begin(X + "_REDO()");
+        for (int k = 0; k < S; ++k)
+            if (m.sf[k].word >= 0) w.line("z" + I(k) + " = (int)((unsigned)z" + I(k) + " + d" + I(k) + "_);");
+        w.end();
+    };
+    // A factor of lane h in slot terms: the kind and the slot of its cell in
+    // that lane.  Where the lanes' factors differ (kind or slot) h selects,
+    // integer-valued factors as integers converted once (the conversion is
+    // exact either way).  A lane whose position is empty has rate +0: any
+    // finite factor gives +0 there, so it takes another lane's factors.
+    struct SF {
+        char kind;
+        int slot;
+        bool operator==(const SF &o) const { return kind == o.kind && slot == o.slot; }
+    };
+    auto sexpr = [&](const SF &a) -> std::string {
         switch (a.kind) {
-        case 'n': return "c" + I(a.cell) + "_";
-        case 'd': return "(c" + I(a.cell) + "_ * m" + I(a.cell) + "_)";
+        case 'n': return "y" + I(a.slot) + "_";
+        case 'd': return "(y" + I(a.slot) + "_ * w" + I(a.slot) + "_)";
         case 'h': return "0.5";
         default: return "1.0";
+        }
+    };
+    // the conversions a group's tree reads: y<k>_ of every slot and
+    // w<k>_ = max(z<k> - 1, 0) of the slots some lane squares
+    auto emit_group_conv = [&](const GroupMaps &m) {
+        auto sv = [&](int k) { return (m.split ? "z" : "n") + I(k); };
+        std::vector<char> s_need_d(m.S, 0);
+        for (int h = 0; h < m.G; ++h)
+            for (int i = 0; i < m.B; ++i)
+                for (const Fac &a : {m.fac[h][i].first, m.fac[h][i].second})
+                    if (a.kind == 'd') s_need_d[m.slot_of[h][a.cell]] = 1;
+        for (int k = 0; k < m.S; ++k) {
+            w.line("const double y" + I(k) + "_ = (double)" + sv(k) + ";");
+            if (s_need_d[k])
+                w.line("const double w" + I(k) + "_ = (double)(" + sv(k) + " > 0 ? " + sv(k) + " - 1 : 0);");
+        }
+    };
+    // the factors of position i in each lane, in slot terms, an empty lane
+    // taking those of a present lane (its partner first)
+    auto group_factors = [&](const GroupMaps &m, int i, std::vector<std::pair<SF, SF>> &out) {
+        const int G = m.G, B = m.B;
+        out.assign(G, {SF{'1', -1}, SF{'1', -1}});
+        std::vector<char> present(G, 0);
+        for (int h = 0; h < G; ++h) {
+            present[h] = f.leaf_slot[h * B + i] >= 0;
+            if (!present[h]) continue;
+            const Fac &a = m.fac[h][i].first, &b = m.fac[h][i].second;
+            out[h] = {SF{a.kind, is_cell(a) ? m.slot_of[h][a.cell] : -1},
+                      SF{b.kind, is_cell(b) ? m.slot_of[h][b.cell] : -1}};
+        }
+        for (int h = 0; h < G; ++h) {
+            if (present[h]) continue;
+            for (int d = 1; d < G; ++d)
+                if (present[h ^ d]) {
+                    out[h] = out[h ^ d];
+                    break;
+                }
         }
     };
 
@@ -667,23 +1052,10 @@ std::string codegen_lane(const Flat &f)
     // root is its half plus the partner's, the root decision is taken by
     // both lanes, the rest of the descent by the lane holding the chosen
     // half.  Leaf position i of a lane is the left slot i or the right slot
-    // B + i: its factors are selected by h, and it is formed with the same
-    // operations as the lane layout's leaf (k * h with h = product of the
-    // binomial factors), so the tree has the same bits; an empty side has
-    // rate 0 and gives +0, which leaves every sum unchanged.
-    //
-    // Counts per lane: a lane keeps only the counts its half of the tree
-    // reads, and the cells no half reads are shared out between the two
-    // lanes, so an event's update and the tree's conversions touch about
-    // half of the cells in each lane.  Register z<k> (slot k) holds cell
-    // cell_of[h][k] in lane h; the left and the right reactant of the same
-    // leaf position are put in the same slot wherever the cells allow it,
-    // so their factor needs no select.  A cell read by both halves is kept
-    // by both lanes (lane 0 writes it out).  Each lane updates its slots
-    // from its own rows of a per-slot change table (lane h: rows h*P + j,
-    // byte layout).  When that table does not fit its LDS budget, both
-    // lanes keep every cell (slot k = cell k, the lane layout's counts,
-    // table and update).
+    // B + i, formed with the same operations as the lane layout's leaf
+    // (k * h with h = product of the binomial factors) from the lane's
+    // count slots, so the tree has the same bits; an empty side has rate 0
+    // and gives +0, which leaves every sum unchanged.
     if (P >= 2) {
         const int B = P / 2;
         int DB = 0;
@@ -693,146 +1065,7 @@ std::string codegen_lane(const Flat &f)
         for (int i = 0; i < B; ++i) hz[B + i] = (f.leaf_slot[i] < 0) && (f.leaf_slot[B + i] < 0);
         for (int i = B - 1; i >= 1; --i) hz[i] = hz[2 * i] && hz[2 * i + 1];
         auto hv = [&](int i) -> std::string { return hz[i] ? std::string("0.0") : "q" + I(i); };
-
-        // net change of each cell at each leaf
-        std::vector<std::vector<long long>> dcl(C, std::vector<long long>(P, 0));
-        for (int c = 0; c < C; ++c)
-            for (auto &ld : per_cell[c]) dcl[c][ld.first] += ld.second;
-        std::vector<char> changes(C, 0);
-        for (int c = 0; c < C; ++c) changes[c] = !per_cell[c].empty();
-
-        // factors at leaf position i: left from lane 0, right from lane 1
-        // (two two-cell factors of the right side may be swapped: the
-        // product is the same either way)
-        std::vector<std::pair<Fac, Fac>> facL(B), facR(B);
-        for (int i = 0; i < B; ++i) {
-            facL[i] = factors(f.leaf_slot[i]);
-            facR[i] = factors(f.leaf_slot[B + i]);
-        }
-        auto is_cell = [](const Fac &a) { return a.kind == 'n' || a.kind == 'd'; };
-
-        // --- slot maps
-        std::vector<int> slot_of[2] = {std::vector<int>(C, -1), std::vector<int>(C, -1)};
-        std::vector<int> cell_of[2];
-        auto free_at = [&](int h, int k) { return k >= (int)cell_of[h].size() || cell_of[h][k] < 0; };
-        auto take = [&](int h, int c, int k) {
-            if ((int)cell_of[h].size() <= k) cell_of[h].resize(k + 1, -1);
-            cell_of[h][k] = c;
-            slot_of[h][c] = k;
-        };
-        // would cells a (lane 0) and b (lane 1) end up in one slot
-        auto alignable = [&](int a, int b) {
-            const int ka = slot_of[0][a], kb = slot_of[1][b];
-            if (ka >= 0 && kb >= 0) return ka == kb;
-            if (ka >= 0) return free_at(1, ka);
-            if (kb >= 0) return free_at(0, kb);
-            return true;
-        };
-        auto align = [&](const Fac &l, const Fac &r) {
-            if (!(l.kind == r.kind && is_cell(l))) return;
-            const int a = l.cell, b = r.cell;
-            const int ka = slot_of[0][a], kb = slot_of[1][b];
-            if (ka >= 0 && kb >= 0) return;
-            if (ka >= 0) { if (free_at(1, ka)) take(1, b, ka); return; }
-            if (kb >= 0) { if (free_at(0, kb)) take(0, a, kb); return; }
-            int k = 0;
-            while (!free_at(0, k) || !free_at(1, k)) ++k;
-            take(0, a, k);
-            take(1, b, k);
-        };
-        auto misaligned = [&](const Fac &l, const Fac &r) {
-            if (l.kind != r.kind) return 1;
-            if (!is_cell(l)) return 0;
-            return alignable(l.cell, r.cell) ? 0 : 1;
-        };
-        for (int i = 0; i < B; ++i) {
-            if (f.leaf_slot[i] < 0 || f.leaf_slot[B + i] < 0) continue;
-            const std::pair<Fac, Fac> L = facL[i], R = facR[i], Rs{R.second, R.first};
-            if (is_cell(R.first) && is_cell(R.second) &&
-                misaligned(L.first, Rs.first) + misaligned(L.second, Rs.second) <
-                    misaligned(L.first, R.first) + misaligned(L.second, R.second))
-                facR[i] = Rs;
-            align(facL[i].first, facR[i].first);
-            align(facL[i].second, facR[i].second);
-        }
-        // the rest of each half's reactants, then the cells no half reads
-        auto first_free = [&](int h) { int k = 0; while (!free_at(h, k)) ++k; return k; };
-        for (int h = 0; h < 2; ++h)
-            for (int i = 0; i < B; ++i)
-                for (const Fac &a : {(h ? facR : facL)[i].first, (h ? facR : facL)[i].second})
-                    if (is_cell(a) && slot_of[h][a.cell] < 0) take(h, a.cell, first_free(h));
-        auto held = [&](int h, bool changing) {
-            int n = 0;
-            for (int c = 0; c < C; ++c) n += slot_of[h][c] >= 0 && (!changing || changes[c]);
-            return n;
-        };
-        for (int c = 0; c < C; ++c) {
-            if (slot_of[0][c] >= 0 || slot_of[1][c] >= 0) continue;
-            const int h = changes[c] ? (held(1, true) < held(0, true) ? 1 : 0)
-                                     : (held(1, false) < held(0, false) ? 1 : 0);
-            take(h, c, first_free(h));
-        }
-        int S = (int)std::max(cell_of[0].size(), cell_of[1].size());
-        for (int h = 0; h < 2; ++h) cell_of[h].resize(S, -1);
-
-        // --- per-slot change table, byte layout (as the lane layout's)
-        std::vector<Field> sf(S);
-        std::vector<char> spos(S, 0);
-        bool split = true;
-        int pw = 0;
-        {
-            int used[4] = {0, 0, 0, 0};
-            for (int k = 0; k < S && split; ++k) {
-                long long lo = 0, hi = 0;
-                for (int h = 0; h < 2; ++h) {
-                    const int c = cell_of[h][k];
-                    if (c < 0) continue;
-                    for (int j = 0; j < P; ++j) {
-                        lo = std::min(lo, dcl[c][j]);
-                        hi = std::max(hi, dcl[c][j]);
-                    }
-                }
-                if (lo == 0 && hi == 0) continue;   // no field: never changes
-                spos[k] = hi > 0;
-                Field &fd = sf[k];
-                fd.sgn = lo < 0;
-                const bool b8 = fd.sgn ? (lo >= -128 && hi <= 127) : hi <= 255;
-                const bool b16 = fd.sgn ? (lo >= -32768 && hi <= 32767) : hi <= 65535;
-                if (!b16) { split = false; break; }
-                fd.width = b8 ? 8 : 16;
-                for (int wd = 0; wd < 4 && fd.word < 0; ++wd) {
-                    const int off = (used[wd] + fd.width - 1) / fd.width * fd.width;
-                    if (off + fd.width <= 32) {
-                        fd.word = wd;
-                        fd.off = off;
-                        used[wd] = off + fd.width;
-                        pw = std::max(pw, wd + 1);
-                    }
-                }
-                if (fd.word < 0) split = false;
-            }
-            if (pw == 3) pw = 4;
-            if ((size_t)2 * (size_t)P * (size_t)pw * 4u > kPairStaticLdsBytes) split = false;
-        }
-        if (!split) {
-            // every cell in both lanes, slot k = cell k
-            S = C;
-            for (int h = 0; h < 2; ++h) {
-                cell_of[h].assign(C, -1);
-                for (int c = 0; c < C; ++c) { cell_of[h][c] = c; slot_of[h][c] = c; }
-            }
-        }
-        o << "#define CWC_PAIR_SPLIT " << (split ? 1 : 0) << "\n";
-        // the slot's register: z<k> of the per-lane state, or the lane
-        // layout's count n<k>
-        auto sv = [&](int k) { return (split ? "z" : "n") + I(k); };
-        // the cells lane h writes out: those it holds that lane 0 does not
-        // hold, and for lane 0 all it holds
-        auto owns = [&](int h, int k) {
-            const int c = cell_of[h][k];
-            return c >= 0 && (h == 0 || slot_of[0][c] < 0);
-        };
-
+        const GroupMaps m = group_maps(2);
         w.begin("CWC_PAIR_DECL");
         for (int i = 0; i < B; ++i)
             if (!hz[B + i]) w.line("double K" + I(i) + " = 0.0;");
@@ -849,182 +1082,26 @@ std::string codegen_lane(const Flat &f)
             w.line("K" + I(i) + " = (h) ? " + Rs + " : " + Ls + ";");
         }
         w.end();
-
-        // per-lane state: declare, load from a count row, write the lane's
-        // cells to a count row or to a staging column (stride 64), and (for
-        // the host tests) write every cell the lane holds
-        w.begin("CWC_PAIR_STATE");
-        if (split)
-            for (int k = 0; k < S; ++k) w.line("int z" + I(k) + " = 0;");
-        w.end();
-        w.begin("CWC_PAIR_LOAD_COUNTS(ptr, h)");
-        if (split) {
-            for (int k = 0; k < S; ++k) {
-                const int c0 = cell_of[0][k], c1 = cell_of[1][k];
-                const std::string l0 = c0 < 0 ? "0" : "(ptr)[" + I(c0) + "]";
-                const std::string l1 = c1 < 0 ? "0" : "(ptr)[" + I(c1) + "]";
-                w.line("z" + I(k) + " = (h) ? " + l1 + " : " + l0 + ";");
-            }
-        } else {
-            w.line("CWC_LOAD_COUNTS(ptr);");
-        }
-        w.end();
-        auto store_lines = [&](const std::string &dst, const std::string &stride, bool all) {
-            if (!split) {
-                w.line(all ? "{" : "if (!(h)) {");
-                for (int c = 0; c < C; ++c)
-                    w.line("(" + dst + ")[" + I(c) + stride + "] = n" + I(c) + ";");
-                w.line("}");
-                return;
-            }
-            for (int h = 0; h < 2; ++h) {
-                w.line(h ? "} else {" : "if (!(h)) {");
-                for (int k = 0; k < S; ++k)
-                    if (all ? cell_of[h][k] >= 0 : owns(h, k))
-                        w.line("(" + dst + ")[" + I(cell_of[h][k]) + stride + "] = z" + I(k) + ";");
-            }
-            w.line("}");
-        };
-        w.begin("CWC_PAIR_STORE_COUNTS(ptr, h)");
-        store_lines("ptr", "", false);
-        w.end();
-        w.begin("CWC_PAIR_STAGE(col0, h)");
-        store_lines("col0", " * 64", false);
-        w.end();
-        w.begin("CWC_PAIR_HELD(ptr, h)");
-        store_lines("ptr", "", true);
-        w.end();
-
-        // update: CWC_PAIR_APPLY_MX adds the change of leaf j to the lane's
-        // slots and leaves the largest count that can grow in `mx`;
-        // CWC_PAIR_UNDO / CWC_PAIR_REDO take it back and apply it again
-        if (!split) {
-            o << "#define CWC_PAIR_SETUP CWC_DT_SETUP\n";
-            o << "#define CWC_PAIR_APPLY_MX(j, mx) CWC_APPLY_MX(j, mx)\n";
-            o << "#define CWC_PAIR_UNDO() CWC_UNDO()\n";
-            o << "#define CWC_PAIR_REDO() CWC_REDO()\n";
-        } else {
-            const char *ty = pw == 1 ? "unsigned int" : pw == 2 ? "uint2" : "uint4";
-            if (pw > 0) {
-                o << "__constant__ unsigned int cwc_ptab_g[" << 2 * P * pw << "] = {";
-                for (int h = 0; h < 2; ++h)
-                    for (int j = 0; j < P; ++j) {
-                        unsigned long long wv[4] = {0, 0, 0, 0};
-                        for (int k = 0; k < S; ++k) {
-                            const int c = cell_of[h][k];
-                            if (sf[k].word < 0 || c < 0) continue;
-                            const unsigned long long bv =
-                                (unsigned long long)dcl[c][j] & ((1ull << sf[k].width) - 1ull);
-                            wv[sf[k].word] |= bv << sf[k].off;
-                        }
-                        for (int q = 0; q < pw; ++q) {
-                            char b[32];
-                            std::snprintf(b, sizeof b, "%s0x%llxu", (h || j || q) ? ", " : "", wv[q]);
-                            o << b;
-                        }
-                    }
-                o << "};\n";
-                // the block's copy in LDS; cwc_ptab_h = this lane's rows
-                w.begin("CWC_PAIR_SETUP");
-                w.line(std::string("__shared__ ") + ty + " cwc_ptab[" + I(2 * P) + "];");
-                w.line("for (int i_ = (int)threadIdx.x; i_ < " + I(2 * P * pw) +
-                       "; i_ += (int)blockDim.x) ((unsigned int *)cwc_ptab)[i_] = cwc_ptab_g[i_];");
-                w.line("__syncthreads();");
-                w.line(std::string("const ") + ty + " *const cwc_ptab_h = cwc_ptab + ((threadIdx.x & 1u) ? " +
-                       I(P) + " : 0);");
-                w.end();
-            } else {
-                o << "#define CWC_PAIR_SETUP\n";
-            }
-            w.begin("CWC_PAIR_APPLY_MX(j, mx)");
-            if (pw == 1) {
-                w.line("const unsigned dw0_ = cwc_ptab_h[(unsigned)(j)];");
-            } else if (pw == 2) {
-                w.line("const uint2 dq_ = cwc_ptab_h[(unsigned)(j)];");
-                w.line("const unsigned dw0_ = dq_.x, dw1_ = dq_.y;");
-            } else if (pw == 4) {
-                w.line("const uint4 dq_ = cwc_ptab_h[(unsigned)(j)];");
-                w.line("const unsigned dw0_ = dq_.x, dw1_ = dq_.y, dw2_ = dq_.z, dw3_ = dq_.w;");
-            }
-            w.line("unsigned mx = 0u;");
-            for (int k = 0; k < S; ++k) {
-                const Field &fd = sf[k];
-                if (fd.word < 0) continue;
-                const std::string wv = "dw" + I(fd.word) + "_";
-                const std::string sh = fd.off ? "(" + wv + " >> " + I(fd.off) + ")" : wv;
-                const std::string e =
-                    fd.sgn ? std::string("(unsigned)(int)(") + (fd.width == 8 ? "signed char" : "short") + ")" + sh
-                           : std::string("(unsigned)(") + (fd.width == 8 ? "unsigned char" : "unsigned short") +
-                                 ")" + sh;
-                w.line("const unsigned d" + I(k) + "_ = " + e + ";");
-                w.line("z" + I(k) + " = (int)((unsigned)z" + I(k) + " + d" + I(k) + "_);");
-                w.line("CWC_KEEP(z" + I(k) + ");");
-                if (spos[k]) w.line("mx = mx > (unsigned)z" + I(k) + " ? mx : (unsigned)z" + I(k) + ";");
-            }
-            w.end();
-            w.begin("CWC_PAIR_UNDO()");
-            for (int k = 0; k < S; ++k)
-                if (sf[k].word >= 0) w.line("z" + I(k) + " = (int)((unsigned)z" + I(k) + " - d" + I(k) + "_);");
-            w.end();
-            w.begin("CWC_PAIR_REDO()");
-            for (int k = 0; k < S; ++k)
-                if (sf[k].word >= 0) w.line("z" + I(k) + " = (int)((unsigned)z" + I(k) + " + d" + I(k) + "_);");
-            w.end();
-        }
-
-        // --- the lane's half tree.  A factor is taken from the slot of its
-        // cell in the lane; where the two sides' factors differ (kind or
-        // slot) h selects, two integer-valued ones as integers converted
-        // once (the conversion is exact either way).
-        struct SF {
-            char kind;
-            int slot;
-            bool operator==(const SF &o) const { return kind == o.kind && slot == o.slot; }
-        };
-        auto sfac = [&](int h, const Fac &a) -> SF {
-            return SF{a.kind, is_cell(a) ? slot_of[h][a.cell] : -1};
-        };
-        auto sexpr = [&](const SF &a) -> std::string {
-            switch (a.kind) {
-            case 'n': return "y" + I(a.slot) + "_";
-            case 'd': return "(y" + I(a.slot) + "_ * w" + I(a.slot) + "_)";
-            case 'h': return "0.5";
-            default: return "1.0";
-            }
-        };
+        emit_group_state(m, "CWC_PAIR", "cwc_ptab");
         auto ssel = [&](const SF &l, const SF &r) -> std::string {
             if (l == r) return sexpr(l);
             const bool li = l.kind == 'n' || l.kind == '1', ri = r.kind == 'n' || r.kind == '1';
+            auto sv = [&](int k) { return (m.split ? "z" : "n") + I(k); };
             if (li && ri) {
                 auto iexpr = [&](const SF &a) { return a.kind == 'n' ? sv(a.slot) : std::string("1"); };
                 return "(double)((h) ? " + iexpr(r) + " : " + iexpr(l) + ")";
             }
             return "((h) ? " + sexpr(r) + " : " + sexpr(l) + ")";
         };
-        std::vector<char> s_need_d(S, 0);
-        for (int i = 0; i < B; ++i)
-            for (int h = 0; h < 2; ++h)
-                for (const Fac &a : {(h ? facR : facL)[i].first, (h ? facR : facL)[i].second})
-                    if (a.kind == 'd') s_need_d[slot_of[h][a.cell]] = 1;
         w.begin("CWC_PAIR_TREE(h)");
         w.line("{");
-        for (int k = 0; k < S; ++k) {
-            w.line("const double y" + I(k) + "_ = (double)" + sv(k) + ";");
-            if (s_need_d[k])
-                w.line("const double w" + I(k) + "_ = (double)(" + sv(k) + " > 0 ? " + sv(k) + " - 1 : 0);");
-        }
+        emit_group_conv(m);
+        std::vector<std::pair<SF, SF>> fs;
         for (int i = 0; i < B; ++i) {
             if (hz[B + i]) continue;
-            const int sl = f.leaf_slot[i], sr = f.leaf_slot[B + i];
-            // an empty side has rate +0: any finite factor gives +0 there,
-            // so the other side's factors (at their slots) are used unselected
-            std::pair<SF, SF> L{SF{'1', -1}, SF{'1', -1}}, R = L;
-            if (sl >= 0) L = {sfac(0, facL[i].first), sfac(0, facL[i].second)};
-            if (sr >= 0) R = {sfac(1, facR[i].first), sfac(1, facR[i].second)};
-            if (sl < 0) L = R;
-            if (sr < 0) R = L;
-            const std::string F1 = ssel(L.first, R.first);
-            const std::string F2 = ssel(L.second, R.second);
+            group_factors(m, i, fs);
+            const std::string F1 = ssel(fs[0].first, fs[1].first);
+            const std::string F2 = ssel(fs[0].second, fs[1].second);
             std::string H;
             if (F2 == "1.0") H = F1;
             else H = "(" + F1 + " * " + F2 + ")";
@@ -1047,7 +1124,7 @@ std::string codegen_lane(const Flat &f)
         int htmp = 0;
         for (int d = 0; d < DB; ++d) {
             std::vector<std::string> vals;
-            for (int m = 0; m < (2 << d); ++m) vals.push_back(hv((2 << d) + m));
+            for (int q = 0; q < (2 << d); ++q) vals.push_back(hv((2 << d) + q));
             const Narrowed nw = narrow_pair(vals, hbits, "u", htmp, &w);
             const std::string Lv = nw.L, Rv = nw.R;
             if (Rv == "0.0") {
@@ -1074,9 +1151,8 @@ std::string codegen_lane(const Flat &f)
     // (B = P/4); the two top levels (halves = quarter 0 + quarter 1 and
     // quarter 2 + quarter 3, root = left half + right half) are formed from
     // the four quarter sums in every lane.  Leaf position i of a lane is
-    // slot h*B + i: factors are selected by the two bits of h (an empty
-    // slot takes the factors of a present slot of the quad, preferring its
-    // neighbour, since its rate is +0), integer-valued ones as integers.
+    // slot h*B + i, formed from the lane's count slots; factors that differ
+    // between the lanes are selected by the two bits of h.
     if (P >= 4) {
         const int B = P / 4;
         int DB = 0;
@@ -1090,21 +1166,13 @@ std::string codegen_lane(const Flat &f)
         }
         for (int i = B - 1; i >= 1; --i) qz[i] = qz[2 * i] && qz[2 * i + 1];
         auto qv = [&](int i) -> std::string { return qz[i] ? std::string("0.0") : "r" + I(i); };
+        const GroupMaps m = group_maps(4);
         w.begin("CWC_QUAD_DECL");
         for (int i = 0; i < B; ++i)
             if (!qz[B + i]) w.line("double KQ" + I(i) + " = 0.0;");
         for (int i = 1; i < 2 * B; ++i)
             if (!qz[i]) w.line("double r" + I(i) + " = 0.0;");
         w.end();
-        // four-way select by the bits of h, folding equal operands
-        auto sel4 = [&](const std::string v[4]) -> std::string {
-            auto sel2 = [&](const std::string &bit, const std::string &a, const std::string &b) {
-                return a == b ? a : "((" + bit + ") ? " + b + " : " + a + ")";
-            };
-            const std::string lo = sel2("(h) & 1", v[0], v[1]);
-            const std::string hi = sel2("(h) & 1", v[2], v[3]);
-            return sel2("(h) & 2", lo, hi);
-        };
         w.begin("CWC_QUAD_LOAD_K(ptr, h)");
         for (int i = 0; i < B; ++i) {
             if (qz[B + i]) continue;
@@ -1116,47 +1184,36 @@ std::string codegen_lane(const Flat &f)
             w.line("KQ" + I(i) + " = " + sel4(v) + ";");
         }
         w.end();
+        emit_group_state(m, "CWC_QUAD", "cwc_qtab");
+        auto fsel4 = [&](const SF g[4]) -> std::string {
+            bool all_int = true, all_eq = true;
+            for (int k = 0; k < 4; ++k) {
+                all_int = all_int && (g[k].kind == 'n' || g[k].kind == '1');
+                all_eq = all_eq && g[k] == g[0];
+            }
+            if (all_eq) return sexpr(g[0]);
+            std::string v[4];
+            if (all_int) {
+                for (int k = 0; k < 4; ++k)
+                    v[k] = g[k].kind == 'n' ? (m.split ? "z" : "n") + I(g[k].slot) : std::string("1");
+                return "(double)" + sel4(v);
+            }
+            for (int k = 0; k < 4; ++k) v[k] = sexpr(g[k]);
+            return sel4(v);
+        };
         w.begin("CWC_QUAD_TREE(h)");
         w.line("{");
-        for (int c = 0; c < C; ++c) {
-            if (need_c[c]) w.line("const double c" + I(c) + "_ = (double)n" + I(c) + ";");
-            if (need_d[c])
-                w.line("const double m" + I(c) + "_ = (double)(n" + I(c) + " > 0 ? n" + I(c) + " - 1 : 0);");
-        }
+        emit_group_conv(m);
+        std::vector<std::pair<SF, SF>> fs;
         for (int i = 0; i < B; ++i) {
             if (qz[B + i]) continue;
-            std::pair<Fac, Fac> fk[4];
-            int sl[4];
+            group_factors(m, i, fs);
+            SF g1[4], g2[4];
             for (int k = 0; k < 4; ++k) {
-                sl[k] = f.leaf_slot[k * B + i];
-                fk[k] = factors(sl[k]);
+                g1[k] = fs[k].first;
+                g2[k] = fs[k].second;
             }
-            for (int k = 0; k < 4; ++k) {
-                if (sl[k] >= 0) continue;
-                for (int alt : {k ^ 1, k ^ 2, k ^ 3})
-                    if (sl[alt] >= 0) {
-                        fk[k] = fk[alt];
-                        break;
-                    }
-            }
-            auto fsel4 = [&](bool second) -> std::string {
-                Fac g[4];
-                for (int k = 0; k < 4; ++k) g[k] = second ? fk[k].second : fk[k].first;
-                bool all_int = true, all_eq = true;
-                for (int k = 0; k < 4; ++k) {
-                    all_int = all_int && (g[k].kind == 'n' || g[k].kind == '1');
-                    all_eq = all_eq && g[k] == g[0];
-                }
-                if (all_eq) return fexpr(g[0]);
-                std::string v[4];
-                if (all_int) {
-                    for (int k = 0; k < 4; ++k) v[k] = g[k].kind == 'n' ? "n" + I(g[k].cell) : std::string("1");
-                    return "(double)" + sel4(v);
-                }
-                for (int k = 0; k < 4; ++k) v[k] = fexpr(g[k]);
-                return sel4(v);
-            };
-            const std::string F1 = fsel4(false), F2 = fsel4(true);
+            const std::string F1 = fsel4(g1), F2 = fsel4(g2);
             std::string H;
             if (F2 == "1.0") H = F1;
             else H = "(" + F1 + " * " + F2 + ")";
@@ -1179,7 +1236,7 @@ std::string codegen_lane(const Flat &f)
         int qtmp = 0;
         for (int d = 0; d < DB; ++d) {
             std::vector<std::string> vals;
-            for (int m = 0; m < (2 << d); ++m) vals.push_back(qv((2 << d) + m));
+            for (int q = 0; q < (2 << d); ++q) vals.push_back(qv((2 << d) + q));
             const Narrowed nw = narrow_pair(vals, qbits, "w", qtmp, &w);
             const std::string Lv = nw.L, Rv = nw.R;
             if (Rv == "0.0") {

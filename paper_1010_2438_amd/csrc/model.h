@@ -11,11 +11,12 @@
 #include "../../include/cwcssa.h"
 
 // LDS a lane-layout kernel may use statically for its per-leaf change
-// table in the byte layout, and a pair-layout kernel for its per-lane
-// table; the host keeps the larger, with the resident kernels' parameter
-// copies, out of the dynamic LDS it gives a block.
+// table in the byte layout, and a pair- or quad-layout kernel for its
+// per-lane table; the host keeps the largest, with the resident kernels'
+// parameter copies, out of the dynamic LDS it gives a block.
 constexpr size_t kLaneStaticLdsBytes = 64 * 8;
 constexpr size_t kPairStaticLdsBytes = 2 * 64 * 8;
+constexpr size_t kQuadStaticLdsBytes = 4 * 64 * 8;
 
 namespace cwc {
 

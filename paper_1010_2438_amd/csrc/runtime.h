@@ -3,6 +3,7 @@
 #define CWC_RUNTIME_H
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <memory>
 #include <map>
@@ -72,10 +73,10 @@ inline size_t cwc_lane_lds_bytes(int n_cells, int waves, int nslot)
 }
 constexpr int kDefaultSampleSlots = 16;
 // static LDS of a lane-group kernel: the per-leaf (lane layout) or
-// per-lane (pair layout) change table, and in the resident kernels the
-// copies of the job parameters of a block's four wavefronts
+// per-lane (pair and quad layouts) change table, and in the resident
+// kernels the copies of the job parameters of a block's four wavefronts
 constexpr size_t kLaneStaticLds =
-    (kPairStaticLdsBytes > kLaneStaticLdsBytes ? kPairStaticLdsBytes : kLaneStaticLdsBytes) +
+    std::max(std::max(kLaneStaticLdsBytes, kPairStaticLdsBytes), kQuadStaticLdsBytes) +
     4 * sizeof(cwc_kparams);
 // Compiles and loads the model's device code for `layout` if needed.
 cwc_status ensure_layout(cwc_model *m, int layout);

@@ -171,7 +171,7 @@ def test_layouts_covered():
     assert seen == {"s8", "u8", "s16", "u16", "sbfe", "ubfe", "mask32", "mask64", "w4"}
 
 
-PAIR_APPLY_HARNESS = r"""
+GROUP_APPLY_HARNESS = r"""
 #include <cstdio>
 typedef unsigned int u32;
 typedef int i32;
@@ -202,30 +202,34 @@ int main() {
         for (int j = 0; j < %(P)d; ++j) {
             int own[%(C)d];
             for (int c = 0; c < %(C)d; ++c) own[c] = -1;
-            unsigned mxs[2];
-            for (int h = 0; h < 2; ++h) {
+            unsigned mxs[%(G)d];
+            for (int h = 0; h < %(G)d; ++h) {
 %(ndecl)s
-                CWC_PAIR_STATE;
-                CWC_PAIR_LOAD_COUNTS(N, h);
+                %(X)s_STATE;
+                %(X)s_LOAD_COUNTS(N, h);
 %(tabh)s
-                CWC_PAIR_APPLY_MX(j, mx_);
+                %(X)s_APPLY_MX(j, mx_);
                 mxs[h] = mx_;
                 int held[%(C)d];
                 for (int c = 0; c < %(C)d; ++c) held[c] = -1;
-                CWC_PAIR_HELD(held, h);
+                %(X)s_HELD(held, h);
                 if (!pass) show("H", h, j, held);
-                CWC_PAIR_STORE_COUNTS(own, h);
-                CWC_PAIR_UNDO();
+                %(X)s_STORE_COUNTS(own, h);
+                %(X)s_UNDO();
                 for (int c = 0; c < %(C)d; ++c) held[c] = -1;
-                CWC_PAIR_HELD(held, h);
+                %(X)s_HELD(held, h);
                 if (!pass) show("U", h, j, held);
-                CWC_PAIR_REDO();
+                %(X)s_REDO();
                 for (int c = 0; c < %(C)d; ++c) held[c] = -1;
-                CWC_PAIR_HELD(held, h);
+                %(X)s_HELD(held, h);
                 if (!pass) show("R", h, j, held);
             }
             if (!pass) show("O", 0, j, own);
-            else std::printf("M %%d %%u\n", j, mxs[0] > mxs[1] ? mxs[0] : mxs[1]);
+            else {
+                unsigned mx = 0u;
+                for (int h = 0; h < %(G)d; ++h) mx = mxs[h] > mx ? mxs[h] : mx;
+                std::printf("M %%d %%u\n", j, mx);
+            }
         }
     }
     return 0;
@@ -233,24 +237,30 @@ int main() {
 """
 
 
+GROUPS = {"pair": ("CWC_PAIR", 2, "cwc_ptab"), "quad": ("CWC_QUAD", 4, "cwc_qtab")}
+
+
 @pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+@pytest.mark.parametrize("group", sorted(GROUPS))
 @pytest.mark.parametrize("name", sorted(MODELS))
-def test_generated_pair_change_table(name):
-    """The pair layout's per-lane counts (Sec. 2.1 update, split over two
-    lanes): for every leaf, each lane's slots take the oracle's net change
-    of the cells they hold, undo and redo restore and re-apply it exactly,
-    the two lanes' written rows together give every cell's new count, and
-    the larger of the two lanes' growth maxima exceeds the state exactly
-    when the leaf raises some count.  Covers both the per-lane table and
-    the fallback where both lanes keep every cell."""
+def test_generated_group_change_table(name, group):
+    """The pair and quad layouts' per-lane counts (Sec. 2.1 update, split
+    over the two or four lanes of a trajectory): for every leaf, each lane's
+    slots take the oracle's net change of the cells they hold, undo and redo
+    restore and re-apply it exactly, the lanes' written rows together give
+    every cell's new count, and the largest of the lanes' growth maxima
+    exceeds the state exactly when the leaf raises some count.  Covers both
+    the per-lane table and the fallback where every lane keeps every
+    cell."""
     from paper_1010_2438_amd import cwc_codegen
     model = MODELS[name]()
     src = cwc_codegen(model)
     C = int(re.search(r"#define CWC_C (\d+)", src).group(1))
     P = int(re.search(r"#define CWC_P (\d+)", src).group(1))
-    if "#define CWC_PAIR_SPLIT" not in src:
-        pytest.skip("a single leaf: no pair layout")
-    split = int(re.search(r"#define CWC_PAIR_SPLIT (\d+)", src).group(1))
+    X, G, tab = GROUPS[group]
+    if "#define %s_SPLIT" % X not in src:
+        pytest.skip("too few leaves for this layout")
+    split = int(re.search(r"#define %s_SPLIT (\d+)" % X, src).group(1))
     dtw = int(re.search(r"#define CWC_DT_W (\d+)", src).group(1))
     tables, copy, tabh = [], [], ""
     if dtw:
@@ -259,27 +269,27 @@ def test_generated_pair_change_table(name):
         tables.append("static %s cwc_dtab[%d];" % (ty, P))
         copy.append("    for (int i = 0; i < %d; ++i) ((unsigned *)cwc_dtab)[i] = cwc_dtab_g[i];"
                     % (P * dtw))
-    m = re.search(r"__constant__ unsigned int cwc_ptab_g\[(\d+)\] = \{[^}]*\};", src)
+    m = re.search(r"__constant__ unsigned int %s_g\[(\d+)\] = \{[^}]*\};" % tab, src)
     if split and m:
         tables.append(m.group(0))
-        ty = re.search(r"__shared__ (\w[\w ]*?) cwc_ptab\[", src).group(1)
-        tables.append("static %s cwc_ptab[%d];" % (ty, 2 * P))
-        copy.append("    for (int i = 0; i < %s; ++i) ((unsigned *)cwc_ptab)[i] = cwc_ptab_g[i];"
-                    % m.group(1))
-        tabh = "                const %s *cwc_ptab_h = cwc_ptab + (h ? %d : 0);" % (ty, P)
+        ty = re.search(r"__shared__ (\w[\w ]*?) %s\[" % tab, src).group(1)
+        tables.append("static %s %s[%d];" % (ty, tab, G * P))
+        copy.append("    for (int i = 0; i < %s; ++i) ((unsigned *)%s)[i] = %s_g[i];"
+                    % (m.group(1), tab, tab))
+        tabh = "                const %s *%s_h = %s + h * %d;" % (ty, tab, tab, P)
     heads = ["CWC_LOAD_COUNTS(ptr)", "CWC_STORE_COUNTS(ptr)", "CWC_APPLY_MX(j, mx)",
-             "CWC_UNDO()", "CWC_REDO()", "CWC_PAIR_STATE", "CWC_PAIR_LOAD_COUNTS(ptr, h)",
-             "CWC_PAIR_STORE_COUNTS(ptr, h)", "CWC_PAIR_HELD(ptr, h)"]
+             "CWC_UNDO()", "CWC_REDO()", X + "_STATE", X + "_LOAD_COUNTS(ptr, h)",
+             X + "_STORE_COUNTS(ptr, h)", X + "_HELD(ptr, h)"]
     macros = "".join(macro(src, hd) for hd in heads)
-    for hd in ("CWC_PAIR_APPLY_MX(", "CWC_PAIR_UNDO(", "CWC_PAIR_REDO("):
+    for hd in (X + "_APPLY_MX(", X + "_UNDO(", X + "_REDO("):
         # one-line aliases of the lane macros, or multi-line macros
         i = src.index("#define " + hd)
         eol = src.index("\n", i)
         macros += src[i:eol + 1] if not src[:eol].endswith("\\") else \
             src[i:src.index("/* end */", i)] + "/* end */\n"
-    code = PAIR_APPLY_HARNESS % {
+    code = GROUP_APPLY_HARNESS % {
         "tables": "\n".join(tables), "macros": macros, "copy": "\n".join(copy), "C": C, "P": P,
-        "base": BASE, "tabh": tabh,
+        "base": BASE, "tabh": tabh, "X": X, "G": G,
         "ndecl": "\n".join("                int n%d = 0; (void)n%d;" % (c, c) for c in range(C))}
     d = tempfile.mkdtemp(prefix="cwc_papply_")
     try:
@@ -296,7 +306,7 @@ def test_generated_pair_change_table(name):
     for line in out.splitlines():
         f = line.split()
         rows[(f[0], int(f[1]), int(f[2]))] = [int(x) for x in f[3:]]
-    n_held = [0, 0]
+    n_held = [0] * G
     for leaf in range(P):
         want = [0] * C
         for k in range(int(flat.leaf_ndelta[leaf])):
@@ -304,7 +314,7 @@ def test_generated_pair_change_table(name):
             want[cell] += v
         new = [N[c] + want[c] for c in range(C)]
         assert rows[("O", 0, leaf)] == new, "leaf %d: written rows" % leaf
-        for h in range(2):
+        for h in range(G):
             held = rows[("H", h, leaf)]
             kept = [c for c in range(C) if held[c] != -1]
             n_held[h] = len(kept)
@@ -324,10 +334,13 @@ def test_generated_pair_change_table(name):
         assert max(n_held) < C
 
 
-def test_pair_split_covered():
-    """The models above reach both pair-layout state forms."""
+@pytest.mark.parametrize("group", sorted(GROUPS))
+def test_group_split_covered(group):
+    """The models above reach both state forms of the pair and quad
+    layouts."""
     from paper_1010_2438_amd import cwc_codegen
-    seen = {int(m.group(1)) for m in (re.search(r"#define CWC_PAIR_SPLIT (\d+)", cwc_codegen(mk()))
+    X = GROUPS[group][0]
+    seen = {int(m.group(1)) for m in (re.search(r"#define %s_SPLIT (\d+)" % X, cwc_codegen(mk()))
                                       for mk in MODELS.values()) if m}
     assert seen == {0, 1}
 
@@ -517,6 +530,8 @@ int main() {
 
 QUAD_TREE_PART = r"""
         for (int h = 0; h < 4; ++h) {
+            CWC_QUAD_STATE;
+            CWC_QUAD_LOAD_COUNTS(N, h);
             CWC_QUAD_DECL;
             CWC_QUAD_LOAD_K(KR, h);
             CWC_QUAD_TREE(h);
@@ -569,7 +584,10 @@ def test_generated_trees(name):
     rnames = set()
     Q = P // 4
     if quad:
-        for head in ("CWC_QUAD_DECL", "CWC_QUAD_LOAD_K(ptr, h)", "CWC_QUAD_TREE(h)"):
+        if not pair:
+            macros += macro(src, "CWC_LOAD_COUNTS(ptr)")
+        for head in ("CWC_QUAD_STATE", "CWC_QUAD_LOAD_COUNTS(ptr, h)", "CWC_QUAD_DECL",
+                     "CWC_QUAD_LOAD_K(ptr, h)", "CWC_QUAD_TREE(h)"):
             macros += macro(src, head)
         rnames = set(re.findall(r"double (r\d+) = ", macro(src, "CWC_QUAD_DECL")))
     code = TREE_HARNESS % {
