@@ -345,6 +345,17 @@ def test_group_split_covered(group):
     assert seen == {0, 1}
 
 
+def test_benchmark_model_lanes_keep_few_counts():
+    """The benchmark's gene-regulation model (20 cells): its pair and quad
+    kernels keep per-lane counts, ten slots per lane with two lanes and six
+    with four."""
+    from paper_1010_2438_amd import cwc_codegen
+    src = cwc_codegen(W.config(1)[0])
+    for X, slots in (("CWC_PAIR", 10), ("CWC_QUAD", 6)):
+        assert re.search(r"#define %s_SPLIT 1" % X, src)
+        assert len(re.findall(r"int z\d+ = 0;", macro(src, X + "_STATE"))) == slots
+
+
 DESCENT_HARNESS = r"""
 #include <cstdio>
 %(macros)s
