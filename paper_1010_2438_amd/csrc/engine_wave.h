@@ -70,9 +70,9 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p, i64 item0, l
     CWC_DECL_STATE;
     if (SHARED_K) {
         if (FORM == CWC_FORM_PERSIST) {
-            CWC_LOAD_K_FREE(p.rates);
+            CWC_LOAD_K_FREE(p.rates, kind);
         } else {
-            CWC_LOAD_K(p.rates);
+            CWC_LOAD_K(p.rates, kind);
         }
     }
 
@@ -91,9 +91,9 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p, i64 item0, l
         if (!SHARED_K) {
             const double *kr = p.rates + (i64)p.rate_stride * inst;
             if (FORM == CWC_FORM_PERSIST) {
-                CWC_LOAD_K_FREE(kr);
+                CWC_LOAD_K_FREE(kr, kind);
             } else {
-                CWC_LOAD_K(kr);
+                CWC_LOAD_K(kr, kind);
             }
         }
         double t = 0.0, t_next = 0.0;
@@ -141,7 +141,11 @@ __device__ __forceinline__ void cwc_wave_main(const cwc_kparams &p, i64 item0, l
             if (SLICED && n == budget) break;
             ++n;
             // ---- Match: leaves, subtree, butterfly over compartment blocks
-            CWC_LEAVES(kind);
+            if (FORM == CWC_FORM_PERSIST) {
+                CWC_LEAVES_FREE(kind);
+            } else {
+                CWC_LEAVES(kind);
+            }
             const double v0 = a1;
             const double v1 = CWC_LP >= 1 ? cwc_bfly_sum(v0, 1) : v0;
             const double v2 = CWC_LP >= 2 ? cwc_bfly_sum(v1, 2) : v1;

@@ -1357,22 +1357,6 @@ std::string codegen_wave(const Flat &f)
     table("cwc_cbase", cb);
     table("cwc_wbase", wb);
 
-    w.begin("CWC_DECL_K");
-    for (int r = 0; r < NR; ++r) w.line("double k" + I(r) + " = 0.0;");
-    w.end();
-    // The rates are the same in every lane (one trajectory per wavefront),
-    // but in scalar registers they crowd out the kernel's other uniform
-    // values and spill to lanes of a VGPR (a lane read per use); kept in
-    // VGPRs instead (CWC_KEEP), they fit beside the state.
-    w.begin("CWC_LOAD_K(ptr)");
-    for (int r = 0; r < f.n_rules; ++r)
-        w.line("k" + I(r) + " = (ptr)[" + I(r) + "]; CWC_KEEP(k" + I(r) + ");");
-    w.end();
-    // the queue-draining form reloads them per trajectory and holds more
-    // state: there the compiler's own placement keeps two wavefronts per SIMD
-    w.begin("CWC_LOAD_K_FREE(ptr)");
-    for (int r = 0; r < f.n_rules; ++r) w.line("k" + I(r) + " = (ptr)[" + I(r) + "];");
-    w.end();
     w.begin("CWC_DECL_STATE");
     for (int s = 0; s < NS; ++s) w.line("int nc" + I(s) + " = 0; int np" + I(s) + " = 0;");
     if (any_wrap)
@@ -1410,27 +1394,30 @@ std::string codegen_wave(const Flat &f)
             w.line("(ptr)[" + I(NS + s) + " * (stride)] = nw" + I(s) + ";");
     w.end();
 
-    // leaves: per position, the formula of the lane's kind (0 if none)
-    // Leaves: a lane evaluates the formulas of its kind only.  The first
-    // count factor of each formula is multiplied by the lane's kind mask
-    // (1.0 for the formula's kind, else 0.0): k * (x * 1) is k * x and
-    // k * (x * 0) is +0 (every factor is finite and non-negative), so no
-    // per-leaf select by kind is needed; a leaf position that several kinds
-    // use sums their formulas, of which at most one is non-zero.
-    w.begin("CWC_LEAVES(kind)");
-    w.line("{");
+    // Leaves: a lane evaluates the formulas of its kind only.  Each
+    // formula's rate is multiplied once per trajectory by the lane's kind
+    // mask (1.0 for the formula's kind, else 0.0), into a masked rate
+    // km<position>_<kind>: (k * 1) * h is k * h and (k * 0) * h is +0 (every
+    // factor is finite and non-negative), so no per-leaf select by kind and
+    // no per-event mask is needed; a leaf position that several kinds use
+    // sums their formulas, of which at most one is non-zero.  The masked
+    // rates differ between kinds, so they take vector registers; the
+    // queue-draining form, which holds more state, keeps the rule rates
+    // uniform instead and masks the first count factor of each formula per
+    // event (k * (x * 1) is k * x, k * (x * 0) is +0): CWC_LEAVES_FREE.
     std::vector<char> used_c(NS, 0), used_d(NS, 0), used_p(NS, 0), used_pd(NS, 0), used_w(NS, 0),
         used_wd(NS, 0);
-    std::set<std::pair<int, std::string>> masked;   // (kind, factor variable)
     std::vector<char> kind_used(kinds.size(), 0);
+    std::vector<std::pair<std::string, int>> kmask;   // (masked rate, rule), kind in the name
+    std::set<std::pair<int, std::string>> masked;     // (kind, count factor) masked per event
     // representative compartment of each kind, to resolve regions
     std::vector<int> rep(kinds.size(), -1);
     for (int q = 0; q < f.n_comp; ++q)
         if (rep[kind_of[q]] < 0) rep[kind_of[q]] = q;
     std::vector<std::vector<std::string>> form(PL, std::vector<std::string>(kinds.size(), "0.0"));
+    std::vector<std::vector<std::string>> form_free = form;
     for (size_t kd = 0; kd < kinds.size(); ++kd) {
         const int q = rep[kd];
-        const std::string mk = "mk" + I((int)kd) + "_";
         for (int l = 0; l < PL; ++l) {
             int si = f.leaf_slot[q * PL + l];
             if (si < 0) continue;
@@ -1445,25 +1432,63 @@ std::string codegen_wave(const Flat &f)
                 else (dec ? used_wd : used_w)[spi] = 1;
                 return (dec ? "m" : "x") + v + "_";
             };
-            // the first factor, masked by the kind
+            // the first count factor, masked by the kind (queue-draining form)
             auto cvm = [&](int cell) {
                 const std::string v = cv(cell, false);
                 masked.insert({(int)kd, v});
                 return v + "k" + I((int)kd) + "_";
             };
             kind_used[kd] = 1;
+            std::string hm;
             if (s.n_react == 1 && s.react_mult[0] == 1) {
-                h = cvm(s.react_cell[0]);
+                h = cv(s.react_cell[0], false);
+                hm = cvm(s.react_cell[0]);
             } else if (s.n_react == 1 && s.react_mult[0] == 2) {
-                h = "((" + cvm(s.react_cell[0]) + " * " + cv(s.react_cell[0], true) + ") * 0.5)";
+                h = "((" + cv(s.react_cell[0], false) + " * " + cv(s.react_cell[0], true) + ") * 0.5)";
+                hm = "((" + cvm(s.react_cell[0]) + " * " + cv(s.react_cell[0], true) + ") * 0.5)";
             } else if (s.n_react == 2) {
-                h = "(" + cvm(s.react_cell[0]) + " * " + cv(s.react_cell[1], false) + ")";
+                h = "(" + cv(s.react_cell[0], false) + " * " + cv(s.react_cell[1], false) + ")";
+                hm = "(" + cvm(s.react_cell[0]) + " * " + cv(s.react_cell[1], false) + ")";
             } else {
-                h = mk;   // order 0: the rate itself, masked
+                hm = "mk" + I((int)kd) + "_";   // order 0: the rate itself, masked
             }
-            form[l][kd] = "k" + I(s.rule) + " * " + h;
+            const std::string km = "km" + I(l) + "_" + I((int)kd);
+            kmask.push_back({km, s.rule});
+            form[l][kd] = h.empty() ? km : km + " * " + h;   // order 0: the masked rate itself
+            form_free[l][kd] = "k" + I(s.rule) + " * " + hm;
         }
     }
+    // rates: the rule rates of the trajectory's instance, and each
+    // formula's rate masked by the lane's kind.  The masked rates are the
+    // same in every lane of a kind, but in scalar registers they crowd out
+    // the kernel's other uniform values and spill to lanes of a VGPR (a lane
+    // read per use); kept in VGPRs instead (CWC_KEEP), they fit beside the
+    // state.  The queue-draining form (CWC_LOAD_K_FREE) reloads them per
+    // trajectory and holds more state: there the compiler's own placement
+    // keeps two wavefronts per SIMD.
+    w.begin("CWC_DECL_K");
+    for (auto &km : kmask) w.line("double " + km.first + " = 0.0;");
+    for (int r = 0; r < NR; ++r) w.line("double k" + I(r) + " = 0.0;");
+    w.end();
+    w.begin("CWC_LOAD_K(ptr, kind)");
+    w.line("{");
+    for (size_t kd = 0; kd < kinds.size(); ++kd)
+        if (kind_used[kd])
+            w.line("const double mk" + I((int)kd) + "_ = (kind) == " + I((int)kd) + " ? 1.0 : 0.0;");
+    for (auto &km : kmask) {
+        const std::string kd = km.first.substr(km.first.rfind('_') + 1);
+        w.line(km.first + " = (ptr)[" + I(km.second) + "] * mk" + kd + "_; CWC_KEEP(" + km.first + ");");
+    }
+    w.line("}");
+    w.end();
+    w.begin("CWC_LOAD_K_FREE(ptr, kind)");
+    for (int r = 0; r < f.n_rules; ++r) w.line("k" + I(r) + " = (ptr)[" + I(r) + "];");
+    w.end();
+    // leaves: per position, the formula of the lane's kind (0 if none)
+    std::vector<char> zero(2 * PL, 1);
+    for (int free_form = 0; free_form < 2; ++free_form) {
+    w.begin(free_form ? "CWC_LEAVES_FREE(kind)" : "CWC_LEAVES(kind)");
+    w.line("{");
     for (int s = 0; s < NS; ++s) {
         if (used_c[s] || used_d[s]) w.line("const double xnc" + I(s) + "_ = (double)nc" + I(s) + ";");
         if (used_d[s]) w.line("const double mnc" + I(s) + "_ = (double)(nc" + I(s) + " > 0 ? nc" + I(s) + " - 1 : 0);");
@@ -1472,21 +1497,24 @@ std::string codegen_wave(const Flat &f)
         if (used_w[s] || used_wd[s]) w.line("const double xnw" + I(s) + "_ = (double)nw" + I(s) + ";");
         if (used_wd[s]) w.line("const double mnw" + I(s) + "_ = (double)(nw" + I(s) + " > 0 ? nw" + I(s) + " - 1 : 0);");
     }
-    for (size_t kd = 0; kd < kinds.size(); ++kd)
-        if (kind_used[kd])
-            w.line("const double mk" + I((int)kd) + "_ = (kind) == " + I((int)kd) + " ? 1.0 : 0.0;");
-    for (auto &mv : masked)
-        w.line("const double " + mv.second + "k" + I(mv.first) + "_ = " + mv.second + " * mk" + I(mv.first) + "_;");
-    std::vector<char> zero(2 * PL, 1);
+    if (free_form) {
+        for (size_t kd = 0; kd < kinds.size(); ++kd)
+            if (kind_used[kd])
+                w.line("const double mk" + I((int)kd) + "_ = (kind) == " + I((int)kd) + " ? 1.0 : 0.0;");
+        for (auto &mv : masked)
+            w.line("const double " + mv.second + "k" + I(mv.first) + "_ = " + mv.second + " * mk" +
+                   I(mv.first) + "_;");
+    }
+    const auto &fm = free_form ? form_free : form;
     for (int l = 0; l < PL; ++l) {
         bool any = false;
-        for (size_t kd = 0; kd < kinds.size(); ++kd) any |= form[l][kd] != "0.0";
+        for (size_t kd = 0; kd < kinds.size(); ++kd) any |= fm[l][kd] != "0.0";
         zero[PL + l] = !any;
         if (!any) continue;
         std::string e;
         for (size_t kd = 0; kd < kinds.size(); ++kd) {
-            if (form[l][kd] == "0.0") continue;
-            e = e.empty() ? form[l][kd] : "(" + e + ") + (" + form[l][kd] + ")";
+            if (fm[l][kd] == "0.0") continue;
+            e = e.empty() ? fm[l][kd] : "(" + e + ") + (" + fm[l][kd] + ")";
         }
         w.line("a" + I(PL + l) + " = " + e + ";");
     }
@@ -1500,6 +1528,7 @@ std::string codegen_wave(const Flat &f)
     if (zero[1]) w.line("a1 = 0.0;");
     w.line("}");
     w.end();
+    }
 
     // local descent inside lane b, uniform branches; node values read with
     // readlane.  The recursion emits one block per internal node.
