@@ -6,13 +6,17 @@ change the oracle's own flattening gives for that leaf (Sec. 2.1: the
 rewrite replaces the matched reactants by the products).  Covers the byte
 layout (signed and unsigned bytes and half-words, 1 to 4 words), the dense
 layout, and the per-digit leaf-mask fallback on 32- and 64-leaf trees.  The
+pair and quad layouts' per-lane counts: each lane's slots after the update,
+undo and redo, the lanes' written rows together and the growth test, per
+leaf, in both state forms (per-lane table, or every lane keeping every
+cell).  The
 selection descents (one lane; two lanes after the engine's root decision):
 compiled the same way and compared with the oracle's selection (Sec. 2.2:
 the reaction is chosen with probability proportional to its rate) on
 random trees with zero leaves and on integer trees at every tie.  The
 propensity trees: every leaf k x (double) prod C(n, m) and every node
-left + right, bit for bit, and the pair and quad layouts' partial trees
-equal to them."""
+left + right, bit for bit, and the pair and quad layouts' partial trees,
+built from each lane's own slots, equal to them."""
 import os
 import re
 import shutil
