@@ -213,13 +213,15 @@ def bursts_wide():
 
 
 @pytest.mark.parametrize("table", ["bytes", "dense", "wide"])
-@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 def test_large_changes(ctx, lanes, table):
-    """Large net changes per event, each change-table layout, both lane
-    layouts and forms; with a cap below the largest burst the trajectories
-    end in overflow with the state before the burst."""
+    """Large net changes per event, each change-table layout, one, two and
+    four lanes per trajectory (the groups' per-lane tables, or every lane
+    keeping every cell where a change does not fit a half-word) and both
+    forms; with a cap below the largest burst the trajectories end in
+    overflow with the state before the burst."""
     m = {"bytes": bursts, "dense": bursts_dense, "wide": bursts_wide}[table]()
-    tuning = PAIR if lanes == 2 else None
+    tuning = {2: PAIR, 4: QUAD}.get(lanes)
     run = W.make_run(seed=13, replicas=300, dt=0.1, n_samples=21)
     check(ctx, m, run, tuning=tuning)
     orc = check(ctx, m, dict(run, count_cap=4000), tuning=tuning)
