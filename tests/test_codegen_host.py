@@ -138,7 +138,7 @@ MODELS = {
     "bursts_wide": bursts_wide,                        # dense fields + 64-bit leaf masks
     "one_cell": lambda: W.multi_compartment(3, n_cells_=1),   # dense, 64 leaves
     "huge_burst": huge_burst,                          # dense, a 21-bit signed field
-    "lotka_volterra": W.lotka_volterra,                # 4 leaves, a lane of a quad holds one
+    "lotka_volterra": W.lotka_volterra,                # 4 leaves
     "transport": W.transport,                          # 8 leaves
 }
 
